@@ -1,0 +1,29 @@
+"""CPU oracle for the IVF-PQ search path — TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The product (the HIP library and its Python binding)
+never calls it; it shares no code with the GPU path.
+
+Parity status: every function is pinned by a CPU test against the paper's
+definitions (brute-force k-NN, the reconstructed-vector identity of Eq. 1,
+lossless constructed cases, full sorts). The u8 LUT quantisation *scheme*
+(per-subspace offset, one shared scale per (query, list), round half to
+even) is a reading of a passage that only says the LUT entries are 8-bit
+unsigned integers; it is pinned by invariants and a lossless grid case, but
+no value printed by the paper pins it: parity unpinned for the scheme itself.
+"""
+
+from .ivfpq import (  # noqa: F401
+    brute_force_knn,
+    coarse_scores,
+    lut_float,
+    list_bias,
+    quantize_lut,
+    scan_list,
+    search,
+    select_probes,
+    seq_sum,
+    tree_sum,
+    top_r,
+    rerank,
+)

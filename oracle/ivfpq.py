@@ -1,0 +1,305 @@
+"""Plain CPU oracle of the IVF-PQ search path (test infrastructure only).
+
+What it computes follows the search procedure (Alg. 2) with static
+parameters and the brute-force branch of SearchInCluster (Alg. 3):
+
+  1. coarse scores of the query against every list centroid and the
+     nprobe nearest lists (TopNClusters);
+  2. per probed list the asymmetric-distance lookup table of Eq. (1)
+     (section 2.4), over residuals of the list (section 4.1);
+  3. 8-bit quantisation of that table (sections 2.5 and 4.5.1);
+  4. the approximate distance of every point of every probed list by table
+     lookups over its 4-bit codes (CalculatePQDistances);
+  5. the `reorder` best candidates over all probed lists (UpdateNNPool);
+  6. exact re-ranking of the candidates against the query and the top k.
+
+Stages 1-5 are computed in float32 ("canonical32"): every intermediate is a
+float32 value produced by elementwise numpy float32 operations, each rounded
+on its own, in the order written below, so that an independent
+implementation can reproduce them bit for bit. No numpy reduction
+(sum/dot/matmul) is used in those stages because their summation order is
+unspecified. Stage 6 and the brute-force search are float64 ("exact64").
+
+Readings where the paper is silent (all also listed in the design notes):
+  * L2 uses one table per (query, list) built on the residual q - c_l; inner
+    product uses one table per query plus a per-list bias -<q, c_l>, with c_l
+    the arithmetic-mean centroid, while lists are *selected* with the
+    normalised centroid (section 4.6.1).
+  * Inner product is handled as the distance -<q, x>; re-ranked results are
+    returned as <q, x>, largest first.
+  * Quantisation: per-subspace offset lo_j = min_i T[j,i], one scale per
+    (query, list) from the largest per-subspace range, round half to even,
+    clamp at 255. The constant part B = (tree sum of lo_j) + bias.
+  * Ties are broken by the smaller list index / point id everywhere.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+F32 = np.float32
+ZERO = F32(0.0)
+
+
+# --------------------------------------------------------------------------
+# Summation orders used by the canonical float32 stages.
+# --------------------------------------------------------------------------
+
+def seq_sum(terms: np.ndarray) -> np.ndarray:
+    """Sequential float32 sum over the last axis: acc = 0; acc = acc + t_u."""
+    terms = np.asarray(terms, dtype=F32)
+    acc = np.zeros(terms.shape[:-1], dtype=F32)
+    for u in range(terms.shape[-1]):
+        acc = acc + terms[..., u]
+    return acc
+
+
+def tree_sum(terms: np.ndarray) -> np.ndarray:
+    """Pairwise float32 sum over the last axis.
+
+    The length is padded with +0.0 to a power of two, then adjacent pairs are
+    added level by level: (t0+t1), (t2+t3), ... until one value remains.
+    """
+    v = np.asarray(terms, dtype=F32)
+    n = v.shape[-1]
+    p = 1
+    while p < n:
+        p *= 2
+    if p != n:
+        pad = np.zeros(v.shape[:-1] + (p - n,), dtype=F32)
+        v = np.concatenate([v, pad], axis=-1)
+    while v.shape[-1] > 1:
+        v = v[..., 0::2] + v[..., 1::2]
+    return v[..., 0]
+
+
+def _plus_zero(x):
+    """Map -0.0 to +0.0 (x + 0.0 is exact otherwise)."""
+    return x + ZERO
+
+
+# --------------------------------------------------------------------------
+# Stage 1: coarse scoring and top-nprobe (Alg. 2, TopNClusters).
+# --------------------------------------------------------------------------
+
+def coarse_scores(q: np.ndarray, cp: np.ndarray, metric: str) -> np.ndarray:
+    """Score of the query against every probe centroid, smaller is nearer.
+
+    L2: s_l = sum_t (q_t - c_{l,t})^2, squared Euclidean (sections 2.4, 4.5.3).
+    IP: s_l = -sum_t q_t * c_{l,t} with normalised centroids (section 4.6.1).
+    Sums are sequential over t in float32.
+    """
+    q = np.asarray(q, dtype=F32)
+    cp = np.asarray(cp, dtype=F32)
+    if metric == "l2":
+        diff = q[None, :] - cp
+        return seq_sum(diff * diff)
+    return _plus_zero(-seq_sum(q[None, :] * cp))
+
+
+def select_probes(scores: np.ndarray, nprobe: int) -> np.ndarray:
+    """The nprobe lists with the smallest (score, list index), in that order."""
+    L = len(scores)
+    order = np.lexsort((np.arange(L), scores))
+    return order[:nprobe].astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# Stage 2: the lookup table of Eq. (1) for one (query, list).
+# --------------------------------------------------------------------------
+
+def lut_float(q: np.ndarray, cm_l: np.ndarray, codebooks: np.ndarray,
+              metric: str) -> np.ndarray:
+    """Float32 table T[j, i] = d(q^j, c_i^j) over residual PQ (Eq. 1, section 4.1).
+
+    L2: r = q - cm_l; T[j,i] = sum_u (r_{j d'+u} - B[j,i,u])^2, sequential in u.
+    IP: T[j,i] = -sum_u q_{j d'+u} * B[j,i,u] (independent of the list).
+    """
+    q = np.asarray(q, dtype=F32)
+    m, K, dsub = codebooks.shape
+    if metric == "l2":
+        r = q - np.asarray(cm_l, dtype=F32)
+        diff = r.reshape(m, 1, dsub) - codebooks
+        return seq_sum(diff * diff)
+    prod = q.reshape(m, 1, dsub) * codebooks
+    return _plus_zero(-seq_sum(prod))
+
+
+def list_bias(q: np.ndarray, cm_l: np.ndarray, metric: str) -> F32:
+    """Per-list constant of the ADC value: 0 for L2, -<q, cm_l> for IP.
+
+    For inner product the residual decomposition x = cm_l + r gives
+    -<q, x> = -<q, cm_l> - <q, r>; the first term is this bias.
+    """
+    if metric == "l2":
+        return ZERO
+    prod = np.asarray(q, dtype=F32) * np.asarray(cm_l, dtype=F32)
+    return _plus_zero(-seq_sum(prod[None, :])[0])
+
+
+# --------------------------------------------------------------------------
+# Stage 3: 8-bit quantisation of the table (sections 2.5, 4.5.1).
+# --------------------------------------------------------------------------
+
+def quantize_lut(T: np.ndarray, bias):
+    """Quantise a float32 table to u8 entries with one affine map per table.
+
+    lo_j  = min_i T[j,i]
+    rng   = max_j max_i (T[j,i] - lo_j)
+    delta = rng / 255, s = 255 / rng (both correctly rounded float32)
+    q8    = min(255, rint((T[j,i] - lo_j) * s))   (round half to even)
+    B     = tree_sum_j(lo_j) + bias
+    If rng == 0 the table is constant: delta = 0 and q8 = 0.
+    The approximate value of code vector c is then B + delta * sum_j q8[j, c_j].
+    Returns (q8 [m,16] uint8, lo [m] f32, delta f32, B f32).
+    """
+    T = np.asarray(T, dtype=F32)
+    lo = T.min(axis=1)
+    D = T - lo[:, None]
+    rng = D.max()
+    if rng > ZERO:
+        s = F32(255.0) / rng
+        delta = rng / F32(255.0)
+        q8 = np.minimum(F32(255.0), np.rint(D * s)).astype(np.uint8)
+    else:
+        delta = ZERO
+        q8 = np.zeros(T.shape, dtype=np.uint8)
+    B = tree_sum(lo[None, :])[0] + F32(bias)
+    return q8, lo, F32(delta), F32(B)
+
+
+# --------------------------------------------------------------------------
+# Stage 4: ADC scan of one list (Alg. 3, CalculatePQDistances).
+# --------------------------------------------------------------------------
+
+def scan_list(q8: np.ndarray, delta, B, codes_rows: np.ndarray):
+    """Approximate values of the points whose codes are ``codes_rows`` [n_l, m].
+
+    S(x) = sum_j q8[j, code_j(x)] is an exact integer (at most 255 m < 2^16);
+    a(x) = B + delta * float(S), product and sum each rounded in float32.
+    Returns (S int64 [n_l], a float32 [n_l]).
+    """
+    m = q8.shape[0]
+    codes_rows = np.asarray(codes_rows)
+    S = np.zeros(len(codes_rows), dtype=np.int64)
+    for j in range(m):
+        S += q8[j, codes_rows[:, j]].astype(np.int64)
+    a = _plus_zero(F32(B) + F32(delta) * S.astype(F32))
+    return S, a
+
+
+# --------------------------------------------------------------------------
+# Stage 5: candidate pool of size `reorder` (Alg. 3, UpdateNNPool).
+# --------------------------------------------------------------------------
+
+def top_r(a: np.ndarray, ids: np.ndarray, R: int):
+    """The min(R, len) smallest (a, id) pairs in lexicographic order."""
+    order = np.lexsort((ids, a))[:R]
+    return a[order], ids[order]
+
+
+# --------------------------------------------------------------------------
+# Stage 6: exact re-rank (Alg. 2, final step) -- float64.
+# --------------------------------------------------------------------------
+
+def rerank(q: np.ndarray, X: np.ndarray, cand_ids: np.ndarray, k: int,
+           metric: str):
+    """Exact distances of the candidates and the top k.
+
+    L2: e = sum_t (q_t - x_t)^2, ascending; IP: e = <q, x>, descending; ties
+    by the smaller id. Missing results are (-1, +inf) for L2 / (-1, -inf) IP.
+    """
+    q64 = np.asarray(q, dtype=np.float64)
+    ids = np.asarray(cand_ids, dtype=np.int64)
+    ids = ids[ids >= 0]
+    rows = np.asarray(X, dtype=np.float64)[ids] if len(ids) else np.zeros((0, len(q)))
+    if metric == "l2":
+        e = ((rows - q64[None, :]) ** 2).sum(axis=1)
+        order = np.lexsort((ids, e))
+        pad = np.inf
+    else:
+        e = rows @ q64
+        order = np.lexsort((ids, -e))
+        pad = -np.inf
+    order = order[:k]
+    out_ids = np.full(k, -1, dtype=np.int64)
+    out_d = np.full(k, pad, dtype=np.float64)
+    out_ids[:len(order)] = ids[order]
+    out_d[:len(order)] = e[order]
+    return out_ids, out_d
+
+
+# --------------------------------------------------------------------------
+# The whole search and the exhaustive reference.
+# --------------------------------------------------------------------------
+
+def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
+           want_stages: bool = False):
+    """Run stages 1-6 for every query.
+
+    index: dict with cm, cp [L,d] f32, codebooks [m,16,d'] f32, codes [n,m]
+    u8, list_offsets [L+1], list_ids [n], metric. nprobe: int or per-query
+    array. Returns dict with ids [nq,k] int64, dist [nq,k] f64, cand_a
+    [nq,R] f32 (+inf padded), cand_id [nq,R] int64 (-1 padded) and, when
+    want_stages, probes (list of arrays) and luts {(qi, list): (q8, lo, delta, B)}.
+    """
+    metric = index["metric"]
+    cm, cp = index["cm"], index["cp"]
+    codebooks = np.asarray(index["codebooks"], dtype=F32)
+    codes = index["codes"]
+    off, lid = index["list_offsets"], index["list_ids"]
+    nq = len(Q)
+    nprobe = np.broadcast_to(np.asarray(nprobe), (nq,))
+    out_ids = np.full((nq, k), -1, dtype=np.int64)
+    out_d = np.zeros((nq, k), dtype=np.float64)
+    cand_a = np.full((nq, R), np.inf, dtype=F32)
+    cand_id = np.full((nq, R), -1, dtype=np.int64)
+    probes, luts = [], {}
+    for qi in range(nq):
+        q = np.asarray(Q[qi], dtype=F32)
+        s = coarse_scores(q, cp, metric)
+        P = select_probes(s, int(nprobe[qi]))
+        if want_stages:
+            probes.append(P)
+        T_ip = lut_float(q, None, codebooks, metric) if metric == "ip" else None
+        all_a, all_id = [], []
+        for l in P:
+            T = T_ip if T_ip is not None else lut_float(q, cm[l], codebooks, metric)
+            q8, lo, delta, B = quantize_lut(T, list_bias(q, cm[l], metric))
+            if want_stages:
+                luts[(qi, int(l))] = (q8, lo, delta, B)
+            ids = np.asarray(lid[off[l]:off[l + 1]], dtype=np.int64)
+            _, a = scan_list(q8, delta, B, codes[ids])
+            all_a.append(a)
+            all_id.append(ids)
+        a = np.concatenate(all_a) if all_a else np.zeros(0, F32)
+        ids = np.concatenate(all_id) if all_id else np.zeros(0, np.int64)
+        ca, cid = top_r(a, ids, R)
+        cand_a[qi, :len(ca)] = ca
+        cand_id[qi, :len(cid)] = cid
+        out_ids[qi], out_d[qi] = rerank(q, X, cid, k, metric)
+    res = dict(ids=out_ids, dist=out_d, cand_a=cand_a, cand_id=cand_id)
+    if want_stages:
+        res["probes"] = probes
+        res["luts"] = luts
+    return res
+
+
+def brute_force_knn(X: np.ndarray, Q: np.ndarray, k: int, metric: str):
+    """Exact k-NN (section 1 problem statement) by exhaustive float64 search.
+
+    Ordered by (squared L2 ascending | inner product descending, id ascending).
+    """
+    X64 = np.asarray(X, dtype=np.float64)
+    ids = np.arange(len(X64), dtype=np.int64)
+    out_ids = np.zeros((len(Q), k), dtype=np.int64)
+    out_d = np.zeros((len(Q), k), dtype=np.float64)
+    for qi, q in enumerate(np.asarray(Q, dtype=np.float64)):
+        if metric == "l2":
+            e = ((X64 - q[None, :]) ** 2).sum(axis=1)
+            order = np.lexsort((ids, e))[:k]
+        else:
+            e = X64 @ q
+            order = np.lexsort((ids, -e))[:k]
+        out_ids[qi], out_d[qi] = ids[order], e[order]
+    return out_ids, out_d

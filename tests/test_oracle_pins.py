@@ -1,0 +1,298 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: brute-force
+k-NN (section 1 problem statement), the reconstructed-vector identity of
+Eq. (1) with residual PQ (sections 2.4, 4.1), constructed lossless cases in
+which the 8-bit table is exact, error bounds, plain-Python sorts, and a
+hand-worked example.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import cached_workload, make_rng
+
+EPS32 = 2.0 ** -24
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- summation
+
+def test_seq_and_tree_sum_orders():
+    # 1e8 has float32 spacing 8, so the result depends on the order.
+    v = np.array([1e8, 1.0, -1e8, 1.0], dtype=np.float32)
+    # ((1e8 + 1) - 1e8) + 1: 1e8 + 1 rounds to 1e8 -> 0 + 1 = 1.
+    assert oracle.seq_sum(v[None, :])[0] == np.float32(1.0)
+    # (1e8 + 1) + (-1e8 + 1) = 1e8 + (-1e8) = 0.
+    assert oracle.tree_sum(v[None, :])[0] == np.float32(0.0)
+    # Exactly representable integers: both equal the exact sum.
+    r = make_rng(1).integers(-1000, 1000, size=(7, 37)).astype(np.float32)
+    exact = np.array([math.fsum(row) for row in r.astype(np.float64)])
+    assert np.array_equal(oracle.seq_sum(r).astype(np.float64), exact)
+    assert np.array_equal(oracle.tree_sum(r).astype(np.float64), exact)
+
+
+# ---------------------------------------------------------- golden example
+
+def test_hand_worked_lut_example():
+    g = json.load(open(os.path.join(GOLDEN, "lut_worked_example.json")))
+    # The expected table follows closed forms derived by hand (see the
+    # fixture's derivation): rint(i^2/2) with ties to even, and i^2 + 2i.
+    half_even = [(i * i) // 2 + (1 if (i * i) % 2 and ((i * i) // 2) % 2 else 0)
+                 for i in range(16)]
+    assert g["expected_q8"][0] == half_even
+    assert g["expected_q8"][1] == [i * i + 2 * i for i in range(16)]
+    q = np.array(g["q"], dtype=np.float32)
+    cm = np.array(g["cm"], dtype=np.float32)
+    cb = np.array(g["codebooks"], dtype=np.float32)
+    T = oracle.lut_float(q, cm, cb, g["metric"])
+    q8, lo, delta, B = oracle.quantize_lut(T, oracle.list_bias(q, cm, g["metric"]))
+    assert q8.tolist() == g["expected_q8"]
+    assert lo.tolist() == g["expected_lo"]
+    assert float(delta) == g["expected_delta"]
+    assert float(B) == g["expected_B"]
+    S, a = oracle.scan_list(q8, delta, B, np.array(g["points_codes"]))
+    assert S.tolist() == g["expected_S"]
+    assert a.tolist() == g["expected_a"]
+    # Quantisation error stays within m * delta / 2 of the exact value.
+    exact = np.array(g["exact_reconstruction_dist"])
+    assert np.all(np.abs(a - exact) <= 2 * float(delta) / 2)
+
+
+# ------------------------------------------------ brute force (section 1)
+
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_all_lists_full_rerank_equals_brute_force(name):
+    cfg, X, Q, _, index = cached_workload(name, 3000, 12, L=16, ncomp=12)
+    res = oracle.search(index, X, Q, cfg.L, cfg.k, len(X))
+    ids, dist = oracle.brute_force_knn(X, Q, cfg.k, cfg.metric)
+    assert np.array_equal(res["ids"], ids)
+    np.testing.assert_allclose(res["dist"], dist, rtol=1e-12, atol=1e-12)
+
+
+def test_duplicates_tie_by_id():
+    cfg, X, Q, _, index = cached_workload("c1", 2000, 5, L=8, ncomp=8)
+    # Duplicate some rows; ties in both the approximate and exact distances
+    # must resolve to the smaller id.
+    X2 = X.copy()
+    X2[1::2] = X2[0::2][: len(X2[1::2])]
+    index2 = dict(index)
+    index2["codes"] = index["codes"].copy()
+    index2["codes"][1::2] = index["codes"][0::2][: len(X2[1::2])]
+    # Put every point in the list of its duplicate source so ties are scanned.
+    res = oracle.search(index2, X2, Q, cfg.L, 20, len(X2))
+    ids, _ = oracle.brute_force_knn(X2, Q, 20, cfg.metric)
+    assert np.array_equal(res["ids"], ids)
+    # Candidate pool: equal (a, .) pairs appear with ascending ids.
+    for qi in range(len(Q)):
+        a, cid = res["cand_a"][qi], res["cand_id"][qi]
+        same = a[1:] == a[:-1]
+        assert np.all(cid[1:][same] > cid[:-1][same])
+
+
+# ------------------------------------------ Eq. (1) reconstruction identity
+
+@pytest.mark.parametrize("name", ["c1", "c3", "c2"])
+def test_adc_equals_distance_to_reconstruction(name):
+    cfg, X, Q, _, index = cached_workload(name, 4000, 6, L=12, ncomp=10)
+    cb = index["codebooks"].astype(np.float64)
+    m, K, dsub = cb.shape
+    rng = make_rng(2, cfg.index)
+    for qi in range(len(Q)):
+        q = Q[qi]
+        for l in rng.choice(cfg.L, size=3, replace=False):
+            ids = index["list_ids"][index["list_offsets"][l]:index["list_offsets"][l + 1]]
+            if len(ids) == 0:
+                continue
+            T = oracle.lut_float(q, index["cm"][l], index["codebooks"], cfg.metric).astype(np.float64)
+            b = float(oracle.list_bias(q, index["cm"][l], cfg.metric))
+            codes = index["codes"][ids].astype(np.int64)
+            # Reconstruction x_hat = cm_l + concat_j B[j, code_j] in float64.
+            xh = index["cm"][l].astype(np.float64)[None, :] + \
+                cb[np.arange(m)[None, :], codes].reshape(len(ids), -1)
+            q64 = q.astype(np.float64)
+            adc = T[np.arange(m)[None, :], codes].sum(axis=1) + b
+            if cfg.metric == "l2":
+                ref = ((xh - q64) ** 2).sum(axis=1)
+                scale = ((np.abs(q64) + np.abs(index["cm"][l]))[None, :] +
+                         np.abs(cb[np.arange(m)[None, :], codes].reshape(len(ids), -1))) ** 2
+            else:
+                ref = -(xh @ q64)
+                scale = np.abs(q64)[None, :] * (np.abs(index["cm"][l])[None, :] +
+                                                 np.abs(cb[np.arange(m)[None, :], codes].reshape(len(ids), -1)))
+            bound = 16 * (dsub + 2 + (cfg.d if cfg.metric == "ip" else 0)) * EPS32 * scale.sum(axis=1)
+            assert np.all(np.abs(adc - ref) <= bound), (name, qi, l)
+
+
+# --------------------------------------------------- quantisation (step 3)
+
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_quantisation_error_bound(name):
+    cfg, X, Q, _, index = cached_workload(name, 4000, 6, L=12, ncomp=10)
+    m = cfg.m
+    for qi in range(len(Q)):
+        q = Q[qi]
+        for l in range(cfg.L):
+            ids = index["list_ids"][index["list_offsets"][l]:index["list_offsets"][l + 1]]
+            T = oracle.lut_float(q, index["cm"][l], index["codebooks"], cfg.metric)
+            bias = oracle.list_bias(q, index["cm"][l], cfg.metric)
+            q8, lo, delta, B = oracle.quantize_lut(T, bias)
+            # Table shape facts: every subspace has a 0 entry; the widest has 255.
+            assert np.all(q8.min(axis=1) == 0)
+            assert q8.max() == 255
+            codes = index["codes"][ids].astype(np.int64)
+            S, a = oracle.scan_list(q8, delta, B, codes)
+            exact = T.astype(np.float64)[np.arange(m)[None, :], codes].sum(axis=1) + float(bias)
+            slack = 8 * EPS32 * (np.abs(lo).astype(np.float64).sum() * 2 + abs(float(bias))
+                                 + float(delta) * 255 * m)
+            assert np.all(np.abs(a - exact) <= m * float(delta) / 2 * (1 + 1e-5) + slack)
+
+
+def _grid_index(metric, L=4, per_list=60, d=12, seed=3):
+    """Lossless grid case: d' = 1, codewords B[j,i] = i, integer data.
+
+    Every residual component is an integer in 0..15 and equals a codeword,
+    so the reconstruction is exact; the query is chosen so that each table's
+    widest subspace range is exactly 255 (scale 1), so the 8-bit table is
+    exact too and a(x) equals the exact distance.
+    """
+    rng = make_rng(seed)
+    cm = rng.integers(20, 30, size=(L, d)).astype(np.float32)
+    codes = rng.integers(0, 16, size=(L * per_list, d)).astype(np.uint8)
+    assign = np.repeat(np.arange(L), per_list)
+    X = cm[assign] + codes.astype(np.float32)
+    cb = np.tile(np.arange(16, dtype=np.float32)[None, :, None], (d, 1, 1))
+    nq = 6
+    if metric == "l2":
+        # Residual q - cm_l = -1 in dimension 0 for every list (range 255);
+        # other residual components stay within [-1, 15] (ranges <= 255).
+        cm[:, 0] = 30.0
+        X = cm[assign] + codes.astype(np.float32)
+        Q = np.zeros((nq, d), dtype=np.float32)
+        Q[:, 0] = 29.0
+        for t in range(1, d):
+            lo_t = cm[:, t].max() - 1
+            hi_t = cm[:, t].min() + 15
+            Q[:, t] = rng.integers(int(lo_t), int(hi_t) + 1, size=nq) if hi_t >= lo_t else lo_t
+        cp = cm.copy()
+    else:
+        # -q_j * i has range 15 |q_j|; max |q_j| = 17 gives range 255.
+        Q = rng.integers(-17, 18, size=(nq, d)).astype(np.float32)
+        Q[:, 0] = 17.0
+        nrm = np.sqrt((cm.astype(np.float64) ** 2).sum(axis=1, keepdims=True))
+        cp = (cm / nrm).astype(np.float32)
+    order = np.argsort(assign, kind="stable")
+    off = np.zeros(L + 1, dtype=np.int64)
+    off[1:] = np.cumsum(np.bincount(assign, minlength=L))
+    index = dict(cm=cm, cp=cp, codebooks=cb, codes=codes, list_offsets=off,
+                 list_ids=order.astype(np.int32), metric=metric)
+    return index, X, Q
+
+
+@pytest.mark.parametrize("metric", ["l2", "ip"])
+def test_lossless_grid_is_exact(metric):
+    index, X, Q = _grid_index(metric)
+    L = len(index["cm"])
+    k = 15
+    for qi, q in enumerate(Q):
+        for l in range(L):
+            ids = index["list_ids"][index["list_offsets"][l]:index["list_offsets"][l + 1]]
+            T = oracle.lut_float(q, index["cm"][l], index["codebooks"], metric)
+            q8, lo, delta, B = oracle.quantize_lut(T, oracle.list_bias(q, index["cm"][l], metric))
+            assert delta == np.float32(1.0)
+            _, a = oracle.scan_list(q8, delta, B, index["codes"][ids])
+            rows = X[ids].astype(np.float64)
+            exact = ((rows - q) ** 2).sum(1) if metric == "l2" else -(rows @ q.astype(np.float64))
+            assert np.array_equal(a.astype(np.float64), exact)
+    # With every list probed and a pool of exactly k, the candidate pool is
+    # already the exact answer (before any re-ranking).
+    res = oracle.search(index, X, Q, L, k, k)
+    ids, dist = oracle.brute_force_knn(X, Q, k, metric)
+    assert np.array_equal(res["cand_id"], ids)
+    assert np.array_equal(res["ids"], ids)
+
+
+# ------------------------------------------------- coarse selection (step 1)
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_coarse_ranking_matches_float64(name):
+    cfg, X, Q, _, index = cached_workload(name, 6000, 20, L=64, ncomp=40)
+    cp = index["cp"].astype(np.float64)
+    n = 7
+    for q in Q:
+        s32 = oracle.coarse_scores(q, index["cp"], cfg.metric).astype(np.float64)
+        q64 = q.astype(np.float64)
+        if cfg.metric == "l2":
+            s64 = ((cp - q64) ** 2).sum(1)
+            mag = ((np.abs(cp) + np.abs(q64)) ** 2).sum(1)
+        else:
+            s64 = -(cp @ q64)
+            mag = (np.abs(cp) * np.abs(q64)).sum(1)
+        bound = (cfg.d + 2) * EPS32 * mag
+        assert np.all(np.abs(s32 - s64) <= bound)
+        P = oracle.select_probes(s32, n)
+        P64 = np.lexsort((np.arange(len(s64)), s64))[:n]
+        kth = s64[P64[-1]]
+        for l in set(P.tolist()) ^ set(P64.tolist()):
+            assert abs(s64[l] - kth) <= 2 * bound.max()
+        assert np.all(np.diff(s32[P]) >= 0)
+
+
+# ----------------------------------------------- scan and pool (steps 4-5)
+
+def test_scan_and_pool_against_plain_python():
+    rng = make_rng(4)
+    m, n = 9, 300
+    q8 = rng.integers(0, 256, size=(m, 16)).astype(np.uint8)
+    codes = rng.integers(0, 16, size=(n, m)).astype(np.uint8)
+    delta, B = np.float32(0.37), np.float32(-12.5)
+    S, a = oracle.scan_list(q8, delta, B, codes)
+    for x in range(n):
+        s = sum(int(q8[j][codes[x][j]]) for j in range(m))
+        assert S[x] == s
+        assert a[x] == np.float32(B + np.float32(delta * np.float32(s)))
+    # Pool: many exact ties on a; plain sorted() over (a, id) tuples.
+    a_t = rng.integers(0, 20, size=500).astype(np.float32)
+    ids = rng.permutation(10_000)[:500].astype(np.int64)
+    for R in (1, 7, 100, 500, 800):
+        ra, rid = oracle.top_r(a_t, ids, R)
+        ref = sorted(zip(a_t.tolist(), ids.tolist()))[:R]
+        assert list(zip(ra.tolist(), rid.tolist())) == ref
+
+
+# ------------------------------------------------------------- edge cases
+
+def test_edge_cases_small_pools_and_empty_lists():
+    cfg, X, Q, _, index = cached_workload("c1", 1500, 4, L=10, ncomp=4)
+    # Empty lists: drop all points of two lists.
+    idx = dict(index)
+    off = index["list_offsets"].copy()
+    lid = index["list_ids"]
+    keep = np.ones(len(lid), bool)
+    for l in (0, 3):
+        keep[off[l]:off[l + 1]] = False
+    counts = np.diff(off).copy()
+    counts[[0, 3]] = 0
+    idx["list_offsets"] = np.concatenate(([0], np.cumsum(counts)))
+    idx["list_ids"] = lid[keep]
+    present = idx["list_ids"]
+    # R larger than the probed points: pool holds every scanned point.
+    res = oracle.search(idx, X, Q, 1, 5, 10_000)
+    for qi in range(len(Q)):
+        got = res["cand_id"][qi]
+        n_valid = int((got >= 0).sum())
+        assert np.all(got[n_valid:] == -1)
+        assert np.all(np.isinf(res["cand_a"][qi][n_valid:]))
+        assert set(got[:n_valid].tolist()) <= set(present.tolist())
+    # k == R and nprobe == L with empty lists: equals brute force over the kept points.
+    res = oracle.search(idx, X, Q, cfg.L, 5, len(X))
+    ids_bf, _ = oracle.brute_force_knn(X[present], Q, 5, cfg.metric)
+    assert np.array_equal(res["ids"], present[ids_bf])
+    # Fewer candidates than k: padded with (-1, +inf).
+    res = oracle.search(idx, X, Q, 1, 5, 3)
+    assert np.all(res["ids"][:, 3:] == -1) and np.all(np.isinf(res["dist"][:, 3:]))

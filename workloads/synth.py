@@ -1,0 +1,179 @@
+"""Seeded synthetic data shaped like the workloads the paper evaluates.
+
+The paper's datasets (SIFT/BIGANN-like integer descriptors, GloVe-like
+angular embeddings, DEEP-like 96-d angular vectors, high-dimensional
+embeddings; Table 5 of the experiments section) are not available, so every
+workload here is a seeded Gaussian mixture with the same shape: size,
+dimension, metric, value range and cluster-size skew.
+
+Every random draw comes from numpy's PCG64 seeded with
+``SeedSequence([2511, 3298, config_index, stream])``; the streams are
+
+    0 mixture means, 1 base vectors, 2 queries, 3 per-query nprobe,
+    4 IVF k-means, 5 PQ k-means, 6 rotation (anisotropic mixture).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional, Tuple
+
+import numpy as np
+
+STREAM_MEANS, STREAM_BASE, STREAM_QUERY, STREAM_NPROBE = 0, 1, 2, 3
+STREAM_KMEANS, STREAM_PQ, STREAM_ROT = 4, 5, 6
+
+
+@dataclasses.dataclass(frozen=True)
+class WorkloadConfig:
+    """One workload: data distribution, index shape and search parameters."""
+
+    name: str
+    index: int            # seed component
+    n: int                # base vectors
+    d: int                # dimension
+    metric: str           # "l2" or "ip"
+    dist: str             # generator family
+    ncomp: int            # mixture components
+    nq: int               # queries
+    L: int                # IVF lists
+    m: int                # PQ subspaces (K = 16 centroids each, 4-bit codes)
+    nprobe: Tuple[int, int]  # per-query nprobe drawn uniformly from [lo, hi]
+    k: int
+    R: int                # re-rank candidates ("reorder")
+    base_dtype: str = "f32"   # "f32" or "bf16" (rows stored as bfloat16)
+    sigma: float = 0.1
+    zipf: float = 0.0     # >0: component weights proportional to rank^-zipf
+
+    @property
+    def dsub(self) -> int:
+        return self.d // self.m
+
+
+CONFIGS = {
+    # Tiny L2: 64-component Gaussian mixture, means U[-1,1], sigma 0.1.
+    "c1": WorkloadConfig("c1", 1, 10_000, 32, "l2", "gauss", 64, 100, 64, 16,
+                         (8, 8), 10, 100, sigma=0.1),
+    # SIFT/BIGANN-like: integer components in [0,255], 1000 components.
+    "c2": WorkloadConfig("c2", 2, 1_000_000, 128, "l2", "int255", 1000, 10_000,
+                         1024, 64, (32, 32), 10, 200, sigma=16.0),
+    # GloVe-like angular data with Zipf(1.1) cluster sizes; per-query nprobe.
+    "c3": WorkloadConfig("c3", 3, 1_200_000, 100, "ip", "sphere", 2000, 10_000,
+                         2000, 50, (8, 128), 10, 200, sigma=0.6, zipf=1.1),
+    # DEEP10M-like angular data.
+    "c4": WorkloadConfig("c4", 4, 10_000_000, 96, "ip", "sphere", 4096, 10_000,
+                         4096, 48, (64, 64), 100, 1000, sigma=0.6),
+    # High-dimensional embedding-like data stored as BF16.
+    "c5": WorkloadConfig("c5", 5, 10_000_000, 768, "ip", "aniso", 8192, 4096,
+                         8192, 192, (4, 256), 10, 256, base_dtype="bf16",
+                         sigma=0.5),
+}
+
+
+def scaled(name: str, n: int, nq: int, L: Optional[int] = None,
+           ncomp: Optional[int] = None, **kw) -> WorkloadConfig:
+    """A smaller instance of a named workload: same d, m, metric, distribution."""
+    base = CONFIGS[name]
+    L = L if L is not None else max(4, round(base.L * n / base.n))
+    ncomp = ncomp if ncomp is not None else max(2, round(base.ncomp * n / base.n))
+    lo, hi = base.nprobe
+    np_lo, np_hi = min(lo, L), min(hi, L)
+    fields = dict(n=n, nq=nq, L=L, ncomp=ncomp, nprobe=(np_lo, np_hi),
+                  name=f"{name}s")
+    fields.update(kw)
+    return dataclasses.replace(base, **fields)
+
+
+def rng_for(cfg: WorkloadConfig, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(
+        np.random.SeedSequence([2511, 3298, cfg.index, stream])))
+
+
+def _normalize(x: np.ndarray) -> np.ndarray:
+    nrm = np.sqrt((x.astype(np.float64) ** 2).sum(axis=1, keepdims=True))
+    nrm[nrm == 0] = 1.0
+    return (x / nrm).astype(np.float32)
+
+
+def _weights(cfg: WorkloadConfig, rng: np.random.Generator) -> np.ndarray:
+    if cfg.zipf > 0:
+        w = np.arange(1, cfg.ncomp + 1, dtype=np.float64) ** (-cfg.zipf)
+        rng.shuffle(w)
+        return w / w.sum()
+    return np.full(cfg.ncomp, 1.0 / cfg.ncomp)
+
+
+def _means(cfg: WorkloadConfig):
+    rng = rng_for(cfg, STREAM_MEANS)
+    if cfg.dist == "gauss":
+        mu = rng.uniform(-1.0, 1.0, size=(cfg.ncomp, cfg.d))
+    elif cfg.dist == "int255":
+        mu = rng.uniform(0.0, 128.0, size=(cfg.ncomp, cfg.d))
+    elif cfg.dist == "sphere":
+        mu = _normalize(rng.standard_normal((cfg.ncomp, cfg.d))).astype(np.float64)
+    elif cfg.dist == "aniso":
+        lam = (1.0 + np.arange(cfg.d)) ** -0.5
+        mu = lam[None, :] * rng.standard_normal((cfg.ncomp, cfg.d))
+    else:
+        raise ValueError(cfg.dist)
+    w = _weights(cfg, rng)
+    return mu, w
+
+
+def _rotation(cfg: WorkloadConfig) -> np.ndarray:
+    rng = rng_for(cfg, STREAM_ROT)
+    g = rng.standard_normal((cfg.d, cfg.d))
+    qm, r = np.linalg.qr(g)
+    return qm * np.sign(np.diag(r))[None, :]
+
+
+def _draw(cfg: WorkloadConfig, mu, w, rot, count: int,
+          rng: np.random.Generator) -> np.ndarray:
+    comp = rng.choice(cfg.ncomp, size=count, p=w)
+    noise = rng.standard_normal((count, cfg.d))
+    if cfg.dist == "gauss":
+        x = mu[comp] + cfg.sigma * noise
+    elif cfg.dist == "int255":
+        x = np.clip(np.rint(mu[comp] + cfg.sigma * noise), 0.0, 255.0)
+    elif cfg.dist == "sphere":
+        x = mu[comp] + cfg.sigma * noise / np.sqrt(cfg.d)
+        x = _normalize(x)
+    elif cfg.dist == "aniso":
+        lam = (1.0 + np.arange(cfg.d)) ** -0.5
+        x = (mu[comp] + cfg.sigma * lam[None, :] * noise) @ rot.T
+        x = _normalize(x)
+    else:
+        raise ValueError(cfg.dist)
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+def to_bf16_bits(x: np.ndarray) -> np.ndarray:
+    """Round float32 to bfloat16 (round-half-to-even) and return the raw bits."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    rounding = ((u >> 16) & 1) + np.uint32(0x7FFF)
+    return ((u + rounding) >> 16).astype(np.uint16)
+
+
+def bf16_bits_to_f32(b: np.ndarray) -> np.ndarray:
+    return (b.astype(np.uint32) << 16).view(np.float32)
+
+
+def make_workload(cfg: WorkloadConfig, chunk: int = 200_000):
+    """Return (X, Q, nprobe) for ``cfg``.
+
+    X is float32 [n, d] (for BF16 workloads: the float32 values of the BF16
+    rows, which are the dataset itself), Q float32 [nq, d], nprobe int32 [nq].
+    """
+    mu, w = _means(cfg)
+    rot = _rotation(cfg) if cfg.dist == "aniso" else None
+    rng_b = rng_for(cfg, STREAM_BASE)
+    X = np.empty((cfg.n, cfg.d), dtype=np.float32)
+    for s in range(0, cfg.n, chunk):
+        e = min(cfg.n, s + chunk)
+        X[s:e] = _draw(cfg, mu, w, rot, e - s, rng_b)
+    Q = _draw(cfg, mu, w, rot, cfg.nq, rng_for(cfg, STREAM_QUERY))
+    if cfg.base_dtype == "bf16":
+        X = bf16_bits_to_f32(to_bf16_bits(X))
+    lo, hi = cfg.nprobe
+    nprobe = rng_for(cfg, STREAM_NPROBE).integers(lo, hi + 1, size=cfg.nq)
+    return X, Q, nprobe.astype(np.int32)
