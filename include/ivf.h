@@ -1,0 +1,215 @@
+/*
+ * ivf.h -- C ABI of the MI355X (gfx950) IVF-PQ search path.
+ *
+ * The library answers the k-nearest-neighbour problem of the paper's
+ * introduction (the k points of X closest to a query under a metric)
+ * approximately, with the partition-based pipeline of section 4.1 and the
+ * search procedure of Alg. 2 (static nprobe / reorder, brute-force branch of
+ * Alg. 3):
+ *   1. coarse scores of every query against the list centroids and the
+ *      nprobe nearest lists (TopNClusters);
+ *   2. per probed list a lookup table of Eq. (1) on the residual query,
+ *      quantised to 8-bit entries (sections 2.4, 2.5, 4.5);
+ *   3. the ADC scan of the probed lists' 4-bit codes;
+ *   4. the `reorder` (= rerank) best candidates per query (UpdateNNPool);
+ *   5. exact FP32 re-ranking of those candidates and the top k.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers unless marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     every call only enqueues work on it and returns, unless noted.
+ *   - The library never allocates device memory. Table memory and search
+ *     workspace are sized by the *_bytes queries and owned by the caller.
+ *   - Host-side validation happens before anything is enqueued: on a non-OK
+ *     status nothing was written and ivf_last_error() describes the problem.
+ *     No exception crosses this boundary and the library never aborts.
+ *   - Distances: IVF_METRIC_L2 returns squared Euclidean distances, ascending;
+ *     IVF_METRIC_IP returns inner products, descending. Ties are broken by
+ *     the smaller id at every selection step.
+ */
+#ifndef IVFPQ_IVF_H
+#define IVFPQ_IVF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ivf_index ivf_index; /* opaque host handle */
+
+typedef enum {
+  IVF_OK = 0,
+  IVF_ERR_INVALID_ARG = 1, /* bad size, pointer, enum or combination       */
+  IVF_ERR_DEVICE = 2,      /* no usable gfx950 device, or a HIP call failed */
+  IVF_ERR_WORKSPACE = 3,   /* table memory or workspace too small          */
+  IVF_ERR_UNSUPPORTED = 4, /* valid request this build does not implement  */
+  IVF_ERR_INTERNAL = 5
+} ivf_status;
+
+typedef enum { IVF_METRIC_L2 = 0, IVF_METRIC_IP = 1 } ivf_metric;
+typedef enum { IVF_DTYPE_F32 = 0, IVF_DTYPE_BF16 = 1 } ivf_dtype;
+
+/* A trained IVF + residual-PQ index (Alg. 1 outputs), K = 16 codewords per
+ * subspace (4-bit codes). Sizes: 1 <= d, 1 <= m <= 256, d % m == 0,
+ * 1 <= L, 1 <= n < 2^31. */
+typedef struct {
+  int64_t n;                      /* number of base vectors                        */
+  int32_t d;                      /* dimension                                     */
+  int32_t L;                      /* number of inverted lists                      */
+  int32_t m;                      /* PQ subspaces, d' = d / m                      */
+  int32_t metric;                 /* ivf_metric                                    */
+  int32_t base_dtype;             /* ivf_dtype of `base`                           */
+  const void* base;               /* [n,d] row-major raw rows for the re-rank.
+                                     Referenced, not copied: must outlive searches */
+  const float* centroids;         /* [L,d] arithmetic-mean centroids: the residual
+                                     origin (section 4.6.1). Copied.              */
+  const float* probe_centroids;   /* [L,d] centroids used to select lists, or NULL
+                                     (= centroids). For IP pass the normalised
+                                     centroids (section 4.6.1). Copied.           */
+  const float* codebooks;         /* [m,16,d'] PQ codewords of the residuals.
+                                     Copied.                                      */
+  const uint8_t* codes;           /* [n,m] one 4-bit code (0..15) per byte, row =
+                                     point id. Consumed: packed into the tables.  */
+  const int64_t* list_offsets;    /* HOST [L+1] CSR offsets into list_ids,
+                                     non-decreasing, list_offsets[L] == n.        */
+  const int32_t* list_ids;        /* [n] point ids grouped by list, ascending
+                                     within a list. Consumed.                     */
+} ivf_index_desc;
+
+/* Coarse-scoring precision (step 1). IVF_COARSE_EXACT scores every list with
+ * the canonical FP32 formula on the vector ALUs. The MFMA forms compute an
+ * approximate score matrix (FP32, BF16, or FP8 e4m3 with per-row scales, all
+ * with FP32 accumulation), keep the widen*nprobe best lists, re-score those
+ * with the canonical FP32 formula and keep the nprobe best. */
+typedef enum {
+  IVF_COARSE_EXACT = 0,
+  IVF_COARSE_F32 = 1,
+  IVF_COARSE_BF16 = 2,
+  IVF_COARSE_FP8 = 3
+} ivf_coarse;
+
+/* Scan schedule (steps 2-4). PLAIN: one workgroup per query walks its probed
+ * lists in coarse order. BATCHED: persistent workgroups pull (query, list
+ * chunk) items from a device work queue. Both give identical results. */
+typedef enum { IVF_FORM_PLAIN = 0, IVF_FORM_BATCHED = 1 } ivf_form;
+
+typedef struct {
+  int32_t coarse;    /* ivf_coarse                                              */
+  int32_t widen;     /* >= 1; MFMA coarse forms keep widen*nprobe lists before
+                        the canonical re-score (ignored by IVF_COARSE_EXACT)    */
+  int32_t form;      /* ivf_form                                                */
+  int32_t use_graph; /* BATCHED only: 1 = capture the search into a hipGraph on
+                        first use for this (nq, k, rerank, opts) and replay it   */
+  int32_t chunk;     /* BATCHED work-item size in 64-point blocks; 0 = auto      */
+  int32_t reserved;
+} ivf_search_opts;
+
+/* Defaults: EXACT coarse, widen 2, PLAIN form, no graph, auto chunk. */
+void ivf_default_opts(ivf_search_opts* opts);
+
+/* Bytes of device memory ivf_build_tables needs for this index; 0 if the
+ * descriptor is invalid (see ivf_last_error). Host only, no device work. */
+size_t ivf_tables_bytes(const ivf_index_desc* desc);
+
+/* Lay out the index in `table_mem` (>= ivf_tables_bytes, 256-byte aligned):
+ * packed 4-bit code blocks per list (step 3 operand), slot ids, centroid
+ * copies and low-precision centroid tables. Synchronises `stream` before it
+ * returns, so the descriptor's arrays may be freed afterwards (except base).
+ * On success *out receives a host handle that references table_mem. */
+ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem,
+                            size_t table_bytes, void* stream, ivf_index** out);
+
+/* Bytes of workspace one ivf_search call with these sizes needs; 0 if the
+ * arguments are invalid. max_nprobe bounds every nprobe[q]. */
+size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq,
+                                  int32_t max_nprobe, int32_t k,
+                                  int32_t rerank, const ivf_search_opts* opts);
+
+/* Search nq queries (Alg. 2 with static parameters).
+ *   queries  [nq,d] FP32 row-major.
+ *   nprobe   [nq] int32, each in 1..max_nprobe (max_nprobe <= L). A value out
+ *            of range sets the device error word (ivf_get_device_error) and
+ *            that query's row is written as ids -1, distances NaN.
+ *   k        1..rerank; rerank (reorder) 1..4096 candidates re-ranked exactly.
+ *   out_ids  [nq,k] int64 point ids, -1 when fewer than k candidates exist.
+ *   out_dist [nq,k] FP32; padding is +inf (L2) or -inf (IP).
+ * opts NULL = defaults. The workspace must hold ivf_search_workspace_bytes. */
+ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
+                      const int32_t* nprobe, int32_t max_nprobe, int32_t k,
+                      int32_t rerank, const ivf_search_opts* opts,
+                      void* workspace, size_t workspace_bytes,
+                      int64_t* out_ids, float* out_dist, void* stream);
+
+/* Steps 2-5 on caller-given probe sets: probes [nq,max_nprobe] int32 list
+ * indices in visiting order, nprobe [nq] how many of each row are used.
+ * Same outputs and workspace as ivf_search. */
+ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries,
+                                  int32_t nq, const int32_t* probes,
+                                  const int32_t* nprobe, int32_t max_nprobe,
+                                  int32_t k, int32_t rerank,
+                                  const ivf_search_opts* opts, void* workspace,
+                                  size_t workspace_bytes, int64_t* out_ids,
+                                  float* out_dist, void* stream);
+
+/* Step 1 only: out_probes [nq,max_nprobe] int32 list indices ordered by
+ * (canonical score, list index); entries past nprobe[q] are -1. */
+ivf_status ivf_debug_probes(const ivf_index* idx, const float* queries,
+                            int32_t nq, const int32_t* nprobe,
+                            int32_t max_nprobe, const ivf_search_opts* opts,
+                            void* workspace, size_t workspace_bytes,
+                            int32_t* out_probes, void* stream);
+
+/* Step 2 only, for every (q, p < nprobe[q]) of caller-given probes:
+ *   out_lut   [nq,max_nprobe,m,16] uint8 quantised table,
+ *   out_lo    [nq,max_nprobe,m] FP32 per-subspace offsets,
+ *   out_delta [nq,max_nprobe] FP32 scale, out_B [nq,max_nprobe] FP32 constant,
+ * so that the ADC value of codes c is B + delta * sum_j lut[j][c_j].
+ * Entries with p >= nprobe[q] are left untouched. */
+ivf_status ivf_debug_luts(const ivf_index* idx, const float* queries,
+                          int32_t nq, const int32_t* probes,
+                          const int32_t* nprobe, int32_t max_nprobe,
+                          uint8_t* out_lut, float* out_lo, float* out_delta,
+                          float* out_B, void* stream);
+
+/* Steps 2-4 on caller-given probes: out_keys [nq,rerank] uint64 candidate
+ * keys in ascending order, key = (ord(a) << 32) | id, where a is the FP32
+ * ADC value and ord maps float order onto unsigned order (sign bit set:
+ * all bits inverted; else sign bit set). Padding is UINT64_MAX. */
+ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries,
+                                int32_t nq, const int32_t* probes,
+                                const int32_t* nprobe, int32_t max_nprobe,
+                                int32_t rerank, const ivf_search_opts* opts,
+                                void* workspace, size_t workspace_bytes,
+                                uint64_t* out_keys, void* stream);
+
+/* Byte offsets of the table sections inside table_mem (for inspection):
+ * codes: uint32 [blocks][words][64], word w of a point holds the 4-bit codes
+ * of subspaces 8w..8w+7 in bits 4s..4s+3 (padding subspaces are 0);
+ * slot_ids: int32 [blocks][64] point id per slot, -1 for padding;
+ * block_offsets: int32 [L+1] first block of each list. */
+typedef struct {
+  size_t codes, slot_ids, block_offsets, list_len, centroids, probe_centroids,
+      codebooks, probe_norms, probe_bf16, probe_fp8, probe_fp8_scale, total;
+  int32_t words_per_point, m_padded, blocks, L_padded, d_padded, reserved;
+} ivf_table_layout;
+
+ivf_status ivf_get_table_layout(const ivf_index* idx, ivf_table_layout* out);
+
+/* Reads and clears the device error word kept in `workspace` (synchronises
+ * `stream`). Returns 0 when no device-side violation was recorded, else a
+ * bit mask: 1 = an nprobe[q] out of range. Returns -1 on a HIP failure. */
+int32_t ivf_get_device_error(const ivf_index* idx, void* workspace,
+                             void* stream);
+
+/* Frees the host handle only; table_mem stays the caller's. */
+void ivf_destroy(ivf_index* idx);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* ivf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IVFPQ_IVF_H */

@@ -1,0 +1,332 @@
+"""Python binding of the gfx950 IVF-PQ search library (libivfpq.so).
+
+Argument marshalling only: torch tensors provide device memory and the
+current HIP stream; every step of the search runs in the library's HIP
+kernels. The C ABI is declared in include/ivf.h. Loading fails loudly when
+the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "libivfpq.so")
+
+IVF_OK, IVF_ERR_INVALID_ARG, IVF_ERR_DEVICE, IVF_ERR_WORKSPACE = 0, 1, 2, 3
+IVF_ERR_UNSUPPORTED, IVF_ERR_INTERNAL = 4, 5
+METRIC = {"l2": 0, "ip": 1}
+DTYPE = {"f32": 0, "bf16": 1}
+COARSE = {"exact": 0, "f32": 1, "bf16": 2, "fp8": 3}
+FORM = {"plain": 0, "batched": 1}
+
+EXPORTED = [
+    "ivf_default_opts", "ivf_tables_bytes", "ivf_build_tables", "ivf_search_workspace_bytes",
+    "ivf_search", "ivf_search_with_probes", "ivf_debug_probes", "ivf_debug_luts",
+    "ivf_debug_candidates", "ivf_get_table_layout", "ivf_get_device_error", "ivf_destroy",
+    "ivf_last_error",
+]
+
+
+class IvfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"ivf status {status}: {message}")
+        self.status = status
+
+
+class IndexDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("base_dtype", ctypes.c_int32), ("base", ctypes.c_void_p),
+                ("centroids", ctypes.c_void_p), ("probe_centroids", ctypes.c_void_p),
+                ("codebooks", ctypes.c_void_p), ("codes", ctypes.c_void_p),
+                ("list_offsets", ctypes.c_void_p), ("list_ids", ctypes.c_void_p)]
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("coarse", ctypes.c_int32), ("widen", ctypes.c_int32),
+                ("form", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class TableLayout(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_size_t) for name in (
+        "codes", "slot_ids", "block_offsets", "list_len", "centroids", "probe_centroids",
+        "codebooks", "probe_norms", "probe_bf16", "probe_fp8", "probe_fp8_scale", "total")] + \
+        [(name, ctypes.c_int32) for name in (
+            "words_per_point", "m_padded", "blocks", "L_padded", "d_padded", "reserved")]
+
+
+_LIB = None
+
+
+def _declare(lib):
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "ivf_default_opts": (None, [P]),
+        "ivf_tables_bytes": (SZ, [P]),
+        "ivf_build_tables": (I32, [P, P, SZ, P, P]),
+        "ivf_search_workspace_bytes": (SZ, [P, I32, I32, I32, I32, P]),
+        "ivf_search": (I32, [P, P, I32, P, I32, I32, I32, P, P, SZ, P, P, P]),
+        "ivf_search_with_probes": (I32, [P, P, I32, P, P, I32, I32, I32, P, P, SZ, P, P, P]),
+        "ivf_debug_probes": (I32, [P, P, I32, P, I32, P, P, SZ, P, P]),
+        "ivf_debug_luts": (I32, [P, P, I32, P, P, I32, P, P, P, P, P]),
+        "ivf_debug_candidates": (I32, [P, P, I32, P, P, I32, I32, P, P, SZ, P, P]),
+        "ivf_get_table_layout": (I32, [P, P]),
+        "ivf_get_device_error": (I32, [P, P, P]),
+        "ivf_destroy": (None, [P]),
+        "ivf_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _ = I64
+
+
+def lib():
+    """Load libivfpq.so (built in-tree by __graft_entry__.build())."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        handle = ctypes.CDLL(LIB_PATH)
+        _declare(handle)
+        _LIB = handle
+    return _LIB
+
+
+def last_error() -> str:
+    return lib().ivf_last_error().decode()
+
+
+def check(status: int):
+    if status != IVF_OK:
+        raise IvfError(status, last_error())
+
+
+def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
+              use_graph: bool = False, chunk: int = 0) -> SearchOpts:
+    o = SearchOpts()
+    lib().ivf_default_opts(ctypes.byref(o))
+    o.coarse, o.widen, o.form = COARSE[coarse], int(widen), FORM[form]
+    o.use_graph, o.chunk = int(bool(use_graph)), int(chunk)
+    return o
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class GpuIndex:
+    """An IVF-PQ index resident on the GPU.
+
+    Inputs are the trained index arrays (numpy or torch); `base` rows are kept
+    referenced by the library for the exact re-rank.
+    """
+
+    def __init__(self, base, centroids, codebooks, codes, list_offsets, list_ids,
+                 metric: str, probe_centroids=None, base_dtype: str = "f32",
+                 device: str = "cuda"):
+        import numpy as np
+        import torch
+        L = lib()
+
+        def dev(a, dtype):
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+            return t.to(device=device, dtype=dtype).contiguous()
+
+        if base_dtype == "bf16":
+            self.base = dev(base, torch.bfloat16)
+        else:
+            self.base = dev(base, torch.float32)
+        self.centroids = dev(centroids, torch.float32)
+        self.probe_centroids = None if probe_centroids is None else dev(probe_centroids, torch.float32)
+        self.codebooks = dev(codebooks, torch.float32)
+        codes_t = dev(codes, torch.uint8)
+        ids_t = dev(list_ids, torch.int32)
+        offs = np.ascontiguousarray(np.asarray(list_offsets, dtype=np.int64))
+        n, d = self.base.shape
+        Lc = self.centroids.shape[0]
+        m = self.codebooks.shape[0]
+        self.n, self.d, self.L, self.m, self.metric = n, d, Lc, m, metric
+        desc = IndexDesc(n=n, d=d, L=Lc, m=m, metric=METRIC[metric],
+                         base_dtype=DTYPE[base_dtype], base=_ptr(self.base),
+                         centroids=_ptr(self.centroids),
+                         probe_centroids=_ptr(self.probe_centroids),
+                         codebooks=_ptr(self.codebooks), codes=_ptr(codes_t),
+                         list_offsets=offs.ctypes.data, list_ids=_ptr(ids_t))
+        nbytes = L.ivf_tables_bytes(ctypes.byref(desc))
+        if nbytes == 0:
+            raise IvfError(IVF_ERR_INVALID_ARG, last_error())
+        self.tables = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        handle = ctypes.c_void_p()
+        check(L.ivf_build_tables(ctypes.byref(desc), self.tables.data_ptr(), nbytes, _stream(),
+                                 ctypes.byref(handle)))
+        self._h = handle
+        self._ws = {}
+        self.device = device
+
+    @classmethod
+    def from_index(cls, index: dict, X, base_dtype: str = "f32", device: str = "cuda"):
+        return cls(X, index["cm"], index["codebooks"], index["codes"], index["list_offsets"],
+                   index["list_ids"], index["metric"], probe_centroids=index["cp"],
+                   base_dtype=base_dtype, device=device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.ivf_destroy(h)
+            self._h = None
+
+    # -- helpers ----------------------------------------------------------
+    def layout(self) -> TableLayout:
+        lay = TableLayout()
+        check(lib().ivf_get_table_layout(self._h, ctypes.byref(lay)))
+        return lay
+
+    def workspace(self, nq, max_nprobe, k, rerank, opts):
+        import torch
+        nbytes = lib().ivf_search_workspace_bytes(self._h, nq, max_nprobe, k, rerank,
+                                                  ctypes.byref(opts))
+        if nbytes == 0:
+            raise IvfError(IVF_ERR_INVALID_ARG, last_error())
+        key = nbytes
+        ws = self._ws.get(key)
+        if ws is None:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws = {key: ws}
+        return ws
+
+    def _queries(self, queries):
+        import numpy as np
+        import torch
+        q = queries if isinstance(queries, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(queries, dtype=np.float32))
+        return q.to(device=self.device, dtype=torch.float32).contiguous()
+
+    def _nprobe(self, nprobe, nq):
+        import numpy as np
+        import torch
+        if isinstance(nprobe, int):
+            return torch.full((nq,), nprobe, dtype=torch.int32, device=self.device)
+        t = nprobe if isinstance(nprobe, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(nprobe, dtype=np.int32))
+        return t.to(device=self.device, dtype=torch.int32).contiguous()
+
+    # -- the search -------------------------------------------------------
+    def search(self, queries, nprobe, k: int, rerank: int, max_nprobe: Optional[int] = None,
+               opts: Optional[SearchOpts] = None, out=None):
+        """Return (ids int64 [nq,k], dist float32 [nq,k]) as device tensors."""
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npb = self._nprobe(nprobe, nq)
+        if max_nprobe is None:
+            max_nprobe = int(npb.max().item()) if nq else 1
+            max_nprobe = max(1, min(max_nprobe, self.L))
+        opts = opts or make_opts()
+        ws = self.workspace(nq, max_nprobe, k, rerank, opts)
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+            dist = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        else:
+            ids, dist = out
+        check(lib().ivf_search(self._h, _ptr(q), nq, _ptr(npb), max_nprobe, k, rerank,
+                               ctypes.byref(opts), ws.data_ptr(), ws.numel(), _ptr(ids),
+                               _ptr(dist), _stream()))
+        self._keep = (q, npb)
+        return ids, dist
+
+    def search_with_probes(self, queries, probes, nprobe, k: int, rerank: int,
+                           opts: Optional[SearchOpts] = None):
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        pr = probes.to(device=self.device, dtype=torch.int32).contiguous()
+        max_nprobe = pr.shape[1]
+        npb = self._nprobe(nprobe, nq)
+        opts = opts or make_opts()
+        ws = self.workspace(nq, max_nprobe, k, rerank, opts)
+        ids = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        check(lib().ivf_search_with_probes(self._h, _ptr(q), nq, _ptr(pr), _ptr(npb), max_nprobe,
+                                           k, rerank, ctypes.byref(opts), ws.data_ptr(),
+                                           ws.numel(), _ptr(ids), _ptr(dist), _stream()))
+        return ids, dist
+
+    def debug_probes(self, queries, nprobe, max_nprobe=None, opts=None):
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npb = self._nprobe(nprobe, nq)
+        if max_nprobe is None:
+            max_nprobe = max(1, min(int(npb.max().item()), self.L))
+        opts = opts or make_opts()
+        ws = self.workspace(nq, max_nprobe, 1, 1, opts)
+        out = torch.empty((nq, max_nprobe), dtype=torch.int32, device=self.device)
+        check(lib().ivf_debug_probes(self._h, _ptr(q), nq, _ptr(npb), max_nprobe,
+                                     ctypes.byref(opts), ws.data_ptr(), ws.numel(), _ptr(out),
+                                     _stream()))
+        return out
+
+    def debug_luts(self, queries, probes, nprobe):
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        pr = probes.to(device=self.device, dtype=torch.int32).contiguous()
+        max_nprobe = pr.shape[1]
+        npb = self._nprobe(nprobe, nq)
+        lut = torch.zeros((nq, max_nprobe, self.m, 16), dtype=torch.uint8, device=self.device)
+        lo = torch.zeros((nq, max_nprobe, self.m), dtype=torch.float32, device=self.device)
+        delta = torch.zeros((nq, max_nprobe), dtype=torch.float32, device=self.device)
+        B = torch.zeros((nq, max_nprobe), dtype=torch.float32, device=self.device)
+        check(lib().ivf_debug_luts(self._h, _ptr(q), nq, _ptr(pr), _ptr(npb), max_nprobe,
+                                   _ptr(lut), _ptr(lo), _ptr(delta), _ptr(B), _stream()))
+        return lut, lo, delta, B
+
+    def debug_candidates(self, queries, probes, nprobe, rerank: int, opts=None):
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        pr = probes.to(device=self.device, dtype=torch.int32).contiguous()
+        max_nprobe = pr.shape[1]
+        npb = self._nprobe(nprobe, nq)
+        opts = opts or make_opts()
+        ws = self.workspace(nq, max_nprobe, 1, rerank, opts)
+        keys = torch.empty((nq, rerank), dtype=torch.int64, device=self.device)
+        check(lib().ivf_debug_candidates(self._h, _ptr(q), nq, _ptr(pr), _ptr(npb), max_nprobe,
+                                         rerank, ctypes.byref(opts), ws.data_ptr(), ws.numel(),
+                                         _ptr(keys), _stream()))
+        return keys
+
+    def device_error(self) -> int:
+        ws = next(iter(self._ws.values()), None)
+        if ws is None:
+            return 0
+        return int(lib().ivf_get_device_error(self._h, ws.data_ptr(), _stream()))
+
+
+def decode_keys(keys):
+    """Split candidate keys (int64 view of uint64) into (a float32, id int64) numpy arrays.
+
+    Padding keys (all ones) decode to (+inf, -1).
+    """
+    import numpy as np
+    k = np.asarray(keys).view(np.uint64)
+    none = k == np.uint64(0xFFFFFFFFFFFFFFFF)
+    o = (k >> np.uint64(32)).astype(np.uint32)
+    bits = np.where(o & np.uint32(0x80000000), o & np.uint32(0x7FFFFFFF), ~o).astype(np.uint32)
+    a = bits.view(np.float32).copy()
+    ids = (k & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    a[none] = np.inf
+    ids[none] = -1
+    return a, ids

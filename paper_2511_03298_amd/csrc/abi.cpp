@@ -1,0 +1,459 @@
+// C ABI of the IVF-PQ search path: argument validation, table and
+// workspace layout, and the order in which the kernels are enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "ivf.h"
+
+using namespace ivf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ivf_status fail(ivf_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+ivf_status hip_fail(hipError_t e, const char* what) {
+  return fail(IVF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define IVF_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+  } while (0)
+
+int32_t round_up_i(int64_t x, int64_t a) { return (int32_t)((x + a - 1) / a * a); }
+
+// Validate the descriptor and compute the table layout. Returns an empty
+// string when valid, else the reason.
+std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t* max_len) {
+  if (!d) return "desc is NULL";
+  if (d->n < 1 || d->n >= (int64_t)1 << 31) return "n must be in [1, 2^31)";
+  if (d->d < 1) return "d must be >= 1";
+  if (d->L < 1 || d->L > 16384) return "L must be in [1, 16384]";
+  if (d->m < 1 || d->m > MAX_M) return "m must be in [1, 256]";
+  if (d->d % d->m != 0) return "d must be a multiple of m";
+  if (d->metric != IVF_METRIC_L2 && d->metric != IVF_METRIC_IP) return "unknown metric";
+  if (d->base_dtype != IVF_DTYPE_F32 && d->base_dtype != IVF_DTYPE_BF16)
+    return "unknown base dtype";
+  if (!d->base || !d->centroids || !d->codebooks || !d->codes || !d->list_offsets ||
+      !d->list_ids)
+    return "a required pointer is NULL";
+  const int64_t* off = d->list_offsets;
+  if (off[0] != 0) return "list_offsets[0] must be 0";
+  int64_t blocks = 0, mx = 0;
+  for (int l = 0; l < d->L; ++l) {
+    int64_t len = off[l + 1] - off[l];
+    if (len < 0) return "list_offsets must be non-decreasing";
+    blocks += (len + BLOCK_PTS - 1) / BLOCK_PTS;
+    if (len > mx) mx = len;
+  }
+  if (off[d->L] != d->n) return "list_offsets[L] must equal n";
+  std::memset(lay, 0, sizeof(*lay));
+  const int32_t words = (d->m + 7) / 8;
+  lay->words_per_point = words;
+  lay->m_padded = words * 8;
+  lay->blocks = (int32_t)blocks;
+  lay->L_padded = round_up_i(d->L, TILE_L);
+  lay->d_padded = round_up_i(d->d, TILE_D);
+  const int32_t dsub = d->d / d->m;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  lay->codes = take((size_t)blocks * words * BLOCK_PTS * 4);
+  lay->slot_ids = take((size_t)blocks * BLOCK_PTS * 4);
+  lay->block_offsets = take((size_t)(d->L + 1) * 4);
+  lay->list_len = take((size_t)d->L * 4);
+  lay->centroids = take((size_t)d->L * d->d * 4);
+  lay->probe_centroids = take((size_t)d->L * d->d * 4);
+  lay->codebooks = take((size_t)lay->m_padded * KSUB * dsub * 4);
+  lay->probe_norms = take((size_t)lay->L_padded * 4);
+  lay->probe_bf16 = take((size_t)lay->L_padded * lay->d_padded * 2);
+  lay->probe_fp8 = take((size_t)lay->L_padded * lay->d_padded);
+  lay->probe_fp8_scale = take((size_t)lay->L_padded * 4);
+  // Build-time copy of the CSR offsets (int64), then the end.
+  take((size_t)(d->L + 1) * 8);
+  lay->total = o;
+  if (max_len) *max_len = (int32_t)mx;
+  return "";
+}
+
+size_t list_off_section(const ivf_index_desc* d, const ivf_table_layout& lay) {
+  return lay.total - align_up((size_t)(d->L + 1) * 8);
+}
+
+ivf_status check_device() {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n < 1) return fail(IVF_ERR_DEVICE, "no HIP device available");
+  int dev = 0;
+  IVF_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  IVF_HIP(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(IVF_ERR_DEVICE, std::string("device is ") + prop.gcnArchName +
+                                    ", this library is built for gfx950");
+  return IVF_OK;
+}
+
+ivf_status check_opts(const ivf_search_opts& o) {
+  if (o.coarse < IVF_COARSE_EXACT || o.coarse > IVF_COARSE_FP8)
+    return fail(IVF_ERR_INVALID_ARG, "opts.coarse out of range");
+  if (o.widen < 1) return fail(IVF_ERR_INVALID_ARG, "opts.widen must be >= 1");
+  if (o.form != IVF_FORM_PLAIN && o.form != IVF_FORM_BATCHED)
+    return fail(IVF_ERR_INVALID_ARG, "opts.form out of range");
+  if (o.use_graph != 0 && o.use_graph != 1)
+    return fail(IVF_ERR_INVALID_ARG, "opts.use_graph must be 0 or 1");
+  if (o.chunk < 0) return fail(IVF_ERR_INVALID_ARG, "opts.chunk must be >= 0");
+  if (o.coarse != IVF_COARSE_EXACT || o.form != IVF_FORM_PLAIN)
+    return fail(IVF_ERR_UNSUPPORTED, "only the exact coarse / plain form is built");
+  return IVF_OK;
+}
+
+ivf_status check_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, int32_t k,
+                        int32_t rerank) {
+  if (!idx) return fail(IVF_ERR_INVALID_ARG, "index is NULL");
+  if (nq < 0) return fail(IVF_ERR_INVALID_ARG, "nq must be >= 0");
+  if (max_nprobe < 1 || max_nprobe > idx->t.L)
+    return fail(IVF_ERR_INVALID_ARG, "max_nprobe must be in [1, L]");
+  if (rerank < 1 || rerank > MAX_RERANK)
+    return fail(IVF_ERR_INVALID_ARG, "rerank must be in [1, 2048]");
+  if (k < 1 || k > rerank) return fail(IVF_ERR_INVALID_ARG, "k must be in [1, rerank]");
+  return IVF_OK;
+}
+
+}  // namespace
+
+namespace ivf {
+
+Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_t k,
+                         int32_t rerank, const ivf_search_opts& o, char* base) {
+  (void)k;
+  Workspace w;
+  std::memset(&w, 0, sizeof(w));
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  const size_t nqs = (size_t)(nq > 0 ? nq : 1);
+  w.err = (int32_t*)take(16);
+  w.scores = (float*)take(nqs * t.L * 4);
+  w.probes = (int32_t*)take(nqs * max_nprobe * 4);
+  w.nprobe_eff = (int32_t*)take(nqs * 4);
+  w.bias = (float*)take(nqs * max_nprobe * 4);
+  w.cand = (uint64_t*)take(nqs * rerank * 8);
+  if (o.coarse != IVF_COARSE_EXACT) {
+    const size_t nq_pad = (size_t)round_up_i((int64_t)nqs, TILE_L);
+    w.q_lowp = (uint16_t*)take(nq_pad * t.d_pad * 2);
+    w.q_scale = (float*)take(nq_pad * 4);
+  }
+  if (o.form == IVF_FORM_BATCHED) {
+    w.cand_count = (int32_t*)take(nqs * 4);
+    w.queue = (uint32_t*)take(64);
+    w.thr = (uint64_t*)take(nqs * 8);
+  }
+  w.total = off;
+  return w;
+}
+
+}  // namespace ivf
+
+extern "C" {
+
+void ivf_default_opts(ivf_search_opts* o) {
+  if (!o) return;
+  o->coarse = IVF_COARSE_EXACT;
+  o->widen = 2;
+  o->form = IVF_FORM_PLAIN;
+  o->use_graph = 0;
+  o->chunk = 0;
+  o->reserved = 0;
+}
+
+const char* ivf_last_error(void) { return g_last_error.c_str(); }
+
+size_t ivf_tables_bytes(const ivf_index_desc* desc) {
+  ivf_table_layout lay;
+  std::string why = plan_tables(desc, &lay, nullptr);
+  if (!why.empty()) {
+    g_last_error = why;
+    return 0;
+  }
+  return lay.total;
+}
+
+ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t table_bytes,
+                            void* stream, ivf_index** out) {
+  if (!out) return fail(IVF_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ivf_table_layout lay;
+  int32_t max_len = 0;
+  std::string why = plan_tables(desc, &lay, &max_len);
+  if (!why.empty()) return fail(IVF_ERR_INVALID_ARG, why);
+  if (!table_mem) return fail(IVF_ERR_INVALID_ARG, "table_mem is NULL");
+  if ((uintptr_t)table_mem % ALIGN) return fail(IVF_ERR_INVALID_ARG, "table_mem not 256-byte aligned");
+  if (table_bytes < lay.total) return fail(IVF_ERR_WORKSPACE, "table_mem smaller than ivf_tables_bytes");
+  ivf_status st = check_device();
+  if (st != IVF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)table_mem;
+
+  Tables t;
+  std::memset(&t, 0, sizeof(t));
+  t.n = desc->n;
+  t.d = desc->d;
+  t.L = desc->L;
+  t.m = desc->m;
+  t.dsub = desc->d / desc->m;
+  t.metric = desc->metric;
+  t.base_dtype = desc->base_dtype;
+  t.words = lay.words_per_point;
+  t.m_pad = lay.m_padded;
+  t.blocks = lay.blocks;
+  t.L_pad = lay.L_padded;
+  t.d_pad = lay.d_padded;
+  t.max_list_len = max_len;
+  t.base = desc->base;
+  t.codes = (const uint32_t*)(base + lay.codes);
+  t.slot_ids = (const int32_t*)(base + lay.slot_ids);
+  t.block_off = (const int32_t*)(base + lay.block_offsets);
+  t.list_len = (const int32_t*)(base + lay.list_len);
+  t.cm = (const float*)(base + lay.centroids);
+  t.cp = (const float*)(base + lay.probe_centroids);
+  t.codebooks = (const float*)(base + lay.codebooks);
+  t.cp_norm2 = (const float*)(base + lay.probe_norms);
+  t.cp_bf16 = (const uint16_t*)(base + lay.probe_bf16);
+  t.cp_fp8 = (const uint8_t*)(base + lay.probe_fp8);
+  t.cp_fp8_scale = (const float*)(base + lay.probe_fp8_scale);
+
+  std::vector<int32_t> boff(desc->L + 1), llen(desc->L);
+  boff[0] = 0;
+  for (int l = 0; l < desc->L; ++l) {
+    int64_t len = desc->list_offsets[l + 1] - desc->list_offsets[l];
+    llen[l] = (int32_t)len;
+    boff[l + 1] = boff[l] + (int32_t)((len + BLOCK_PTS - 1) / BLOCK_PTS);
+  }
+  int64_t* list_off_dev = (int64_t*)(base + list_off_section(desc, lay));
+  const size_t cb_bytes = (size_t)desc->m * KSUB * t.dsub * 4;
+  const size_t cb_pad_bytes = (size_t)t.m_pad * KSUB * t.dsub * 4;
+  IVF_HIP(hipMemcpyAsync((void*)t.block_off, boff.data(), boff.size() * 4, hipMemcpyHostToDevice, s));
+  IVF_HIP(hipMemcpyAsync((void*)t.list_len, llen.data(), llen.size() * 4, hipMemcpyHostToDevice, s));
+  IVF_HIP(hipMemcpyAsync(list_off_dev, desc->list_offsets, (size_t)(desc->L + 1) * 8,
+                         hipMemcpyHostToDevice, s));
+  const size_t cbytes = (size_t)desc->L * desc->d * 4;
+  IVF_HIP(hipMemcpyAsync((void*)t.cm, desc->centroids, cbytes, hipMemcpyDeviceToDevice, s));
+  IVF_HIP(hipMemcpyAsync((void*)t.cp, desc->probe_centroids ? desc->probe_centroids : desc->centroids,
+                         cbytes, hipMemcpyDeviceToDevice, s));
+  IVF_HIP(hipMemsetAsync((void*)t.codebooks, 0, cb_pad_bytes, s));
+  IVF_HIP(hipMemcpyAsync((void*)t.codebooks, desc->codebooks, cb_bytes, hipMemcpyDeviceToDevice, s));
+  IVF_HIP(launch_pack(t, desc->codes, list_off_dev, desc->list_ids, s));
+  IVF_HIP(launch_aux_tables(t, s));
+  IVF_HIP(hipStreamSynchronize(s));
+
+  ivf_index* idx = new (std::nothrow) ivf_index;
+  if (!idx) return fail(IVF_ERR_INTERNAL, "out of host memory");
+  idx->t = t;
+  idx->layout = lay;
+  idx->table_mem = table_mem;
+  *out = idx;
+  return IVF_OK;
+}
+
+ivf_status ivf_get_table_layout(const ivf_index* idx, ivf_table_layout* out) {
+  if (!idx || !out) return fail(IVF_ERR_INVALID_ARG, "NULL argument");
+  *out = idx->layout;
+  return IVF_OK;
+}
+
+void ivf_destroy(ivf_index* idx) { delete idx; }
+
+size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq, int32_t max_nprobe,
+                                  int32_t k, int32_t rerank, const ivf_search_opts* opts) {
+  if (check_search(idx, nq, max_nprobe, k, rerank) != IVF_OK) return 0;
+  ivf_search_opts o;
+  ivf_default_opts(&o);
+  if (opts) o = *opts;
+  if (check_opts(o) != IVF_OK) return 0;
+  return plan_workspace(idx->t, nq, max_nprobe, k, rerank, o, nullptr).total;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Shared front part of every search entry: validation and workspace carving.
+ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, int32_t k,
+                        int32_t rerank, const ivf_search_opts* opts, void* workspace,
+                        size_t workspace_bytes, ivf_search_opts* o, Workspace* w) {
+  ivf_status st = check_search(idx, nq, max_nprobe, k, rerank);
+  if (st != IVF_OK) return st;
+  ivf_default_opts(o);
+  if (opts) *o = *opts;
+  st = check_opts(*o);
+  if (st != IVF_OK) return st;
+  Workspace need = plan_workspace(idx->t, nq, max_nprobe, k, rerank, *o, nullptr);
+  if (nq > 0 && !workspace) return fail(IVF_ERR_INVALID_ARG, "workspace is NULL");
+  if ((uintptr_t)workspace % ALIGN) return fail(IVF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (workspace_bytes < need.total) return fail(IVF_ERR_WORKSPACE, "workspace too small");
+  *w = plan_workspace(idx->t, nq, max_nprobe, k, rerank, *o, (char*)workspace);
+  return IVF_OK;
+}
+
+ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, int32_t nq,
+                               int32_t max_nprobe, int32_t k, int32_t rerank,
+                               const ivf_search_opts& o, const Workspace& w, int64_t* out_ids,
+                               float* out_dist, hipStream_t s) {
+  const Tables& t = idx->t;
+  IVF_HIP(launch_bias(t, Q, nq, max_nprobe, w, s));
+  if (o.form == IVF_FORM_BATCHED) {
+    IVF_HIP(launch_scan_batched(t, Q, nq, max_nprobe, rerank, o.chunk, w, s));
+  } else {
+    IVF_HIP(launch_scan_plain(t, Q, nq, max_nprobe, rerank, w, s));
+  }
+  if (out_ids) IVF_HIP(launch_rerank(t, Q, nq, k, rerank, w, out_ids, out_dist, s));
+  return IVF_OK;
+}
+
+ivf_status run_coarse(const ivf_index* idx, const float* Q, int32_t nq, const int32_t* nprobe,
+                      int32_t max_nprobe, const ivf_search_opts& o, const Workspace& w,
+                      hipStream_t s) {
+  const Tables& t = idx->t;
+  if (o.coarse == IVF_COARSE_EXACT) {
+    IVF_HIP(launch_coarse_exact(t, Q, nq, w.scores, s));
+    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, 1, false, w, s));
+  } else {
+    IVF_HIP(launch_coarse_mfma(t, Q, nq, o.coarse, w, s));
+    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, o.widen, true, w, s));
+  }
+  return IVF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
+                      const int32_t* nprobe, int32_t max_nprobe, int32_t k, int32_t rerank,
+                      const ivf_search_opts* opts, void* workspace, size_t workspace_bytes,
+                      int64_t* out_ids, float* out_dist, void* stream) {
+  ivf_search_opts o;
+  Workspace w;
+  ivf_status st = begin_search(idx, nq, max_nprobe, k, rerank, opts, workspace, workspace_bytes,
+                               &o, &w);
+  if (st != IVF_OK) return st;
+  if (nq == 0) return IVF_OK;
+  if (!queries || !nprobe || !out_ids || !out_dist)
+    return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
+  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, o, w, s);
+  if (st != IVF_OK) return st;
+  return run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);
+}
+
+ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries, int32_t nq,
+                                  const int32_t* probes, const int32_t* nprobe,
+                                  int32_t max_nprobe, int32_t k, int32_t rerank,
+                                  const ivf_search_opts* opts, void* workspace,
+                                  size_t workspace_bytes, int64_t* out_ids, float* out_dist,
+                                  void* stream) {
+  ivf_search_opts o;
+  Workspace w;
+  ivf_status st = begin_search(idx, nq, max_nprobe, k, rerank, opts, workspace, workspace_bytes,
+                               &o, &w);
+  if (st != IVF_OK) return st;
+  if (nq == 0) return IVF_OK;
+  if (!queries || !probes || !nprobe || !out_ids || !out_dist)
+    return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
+  IVF_HIP(launch_copy_probes(probes, nprobe, nq, max_nprobe, idx->t.L, w, s));
+  return run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);
+}
+
+ivf_status ivf_debug_probes(const ivf_index* idx, const float* queries, int32_t nq,
+                            const int32_t* nprobe, int32_t max_nprobe,
+                            const ivf_search_opts* opts, void* workspace, size_t workspace_bytes,
+                            int32_t* out_probes, void* stream) {
+  ivf_search_opts o;
+  Workspace w;
+  ivf_status st = begin_search(idx, nq, max_nprobe, 1, 1, opts, workspace, workspace_bytes, &o, &w);
+  if (st != IVF_OK) return st;
+  if (nq == 0) return IVF_OK;
+  if (!queries || !nprobe || !out_probes) return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
+  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, o, w, s);
+  if (st != IVF_OK) return st;
+  IVF_HIP(hipMemcpyAsync(out_probes, w.probes, (size_t)nq * max_nprobe * 4,
+                         hipMemcpyDeviceToDevice, s));
+  return IVF_OK;
+}
+
+ivf_status ivf_debug_luts(const ivf_index* idx, const float* queries, int32_t nq,
+                          const int32_t* probes, const int32_t* nprobe, int32_t max_nprobe,
+                          uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
+                          void* stream) {
+  if (!idx) return fail(IVF_ERR_INVALID_ARG, "index is NULL");
+  if (nq < 0) return fail(IVF_ERR_INVALID_ARG, "nq must be >= 0");
+  if (max_nprobe < 1 || max_nprobe > idx->t.L)
+    return fail(IVF_ERR_INVALID_ARG, "max_nprobe must be in [1, L]");
+  if (nq == 0) return IVF_OK;
+  if (!queries || !probes || !nprobe || !out_lut || !out_lo || !out_delta || !out_B)
+    return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  IVF_HIP(launch_debug_luts(idx->t, queries, nq, probes, nprobe, max_nprobe, out_lut, out_lo,
+                            out_delta, out_B, (hipStream_t)stream));
+  return IVF_OK;
+}
+
+ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries, int32_t nq,
+                                const int32_t* probes, const int32_t* nprobe,
+                                int32_t max_nprobe, int32_t rerank, const ivf_search_opts* opts,
+                                void* workspace, size_t workspace_bytes, uint64_t* out_keys,
+                                void* stream) {
+  ivf_search_opts o;
+  Workspace w;
+  ivf_status st = begin_search(idx, nq, max_nprobe, 1, rerank, opts, workspace, workspace_bytes,
+                               &o, &w);
+  if (st != IVF_OK) return st;
+  if (nq == 0) return IVF_OK;
+  if (!queries || !probes || !nprobe || !out_keys)
+    return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
+  IVF_HIP(launch_copy_probes(probes, nprobe, nq, max_nprobe, idx->t.L, w, s));
+  st = run_scan_and_rerank(idx, queries, nq, max_nprobe, 1, rerank, o, w, nullptr, nullptr, s);
+  if (st != IVF_OK) return st;
+  IVF_HIP(hipMemcpyAsync(out_keys, w.cand, (size_t)nq * rerank * 8, hipMemcpyDeviceToDevice, s));
+  return IVF_OK;
+}
+
+int32_t ivf_get_device_error(const ivf_index* idx, void* workspace, void* stream) {
+  if (!idx || !workspace) {
+    g_last_error = "NULL argument";
+    return -1;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int32_t v[4] = {0, 0, 0, 0};
+  // The error word is the first 16 bytes of every workspace layout.
+  if (hipMemcpyAsync(v, workspace, 16, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  if (launch_fill_u32((uint32_t*)workspace, 0u, 4, s) != hipSuccess) return -1;
+  return v[0];
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// Step 1 of the search (Alg. 2, TopNClusters): coarse scores of every query
+// against the list centroids, and the nprobe nearest lists per query.
+//
+// The canonical score, which fixes the probe sets bit for bit, is
+//   L2: s = sum_t (q_t - c_t)^2      IP: s = -sum_t q_t c_t
+// summed sequentially over t in FP32 with every product and sum rounded on
+// its own (this file is compiled without FP contraction). Smaller is nearer;
+// ties go to the smaller list index.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ivf {
+
+constexpr int CQ = 32;   // queries per tile
+constexpr int CL = 64;   // lists per tile
+constexpr int CD = 32;   // dimensions staged per step
+
+// One workgroup per (32-query x 64-list) tile; each thread owns 2 queries x
+// 4 lists and walks t in order, so every score is the canonical seq-sum.
+__global__ void __launch_bounds__(256) coarse_exact_kernel(Tables t, const float* __restrict__ Q,
+                                                           int32_t nq, float* __restrict__ S) {
+  __shared__ float qs[CQ][CD + 1];
+  __shared__ float cs[CL][CD + 1];
+  const int tid = threadIdx.x;
+  const int l0 = blockIdx.x * CL, q0 = blockIdx.y * CQ;
+  const int tq = (tid / 16) * 2;   // 0..30
+  const int tl = (tid % 16);       // lists tl, tl+16, tl+32, tl+48
+  const bool ip = t.metric == IVF_METRIC_IP;
+  float acc[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+  for (int d0 = 0; d0 < t.d; d0 += CD) {
+    const int dn = min(CD, t.d - d0);
+    __syncthreads();
+    for (int e = tid; e < CQ * CD; e += 256) {
+      int r = e / CD, c = e % CD;
+      int q = q0 + r;
+      qs[r][c] = (q < nq && c < dn) ? Q[(size_t)q * t.d + d0 + c] : 0.0f;
+    }
+    for (int e = tid; e < CL * CD; e += 256) {
+      int r = e / CD, c = e % CD;
+      int l = l0 + r;
+      cs[r][c] = (l < t.L && c < dn) ? t.cp[(size_t)l * t.d + d0 + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int c = 0; c < dn; ++c) {
+      float qv0 = qs[tq][c], qv1 = qs[tq + 1][c];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float cv = cs[tl + 16 * j][c];
+        if (ip) {
+          acc[0][j] = acc[0][j] + qv0 * cv;
+          acc[1][j] = acc[1][j] + qv1 * cv;
+        } else {
+          float d0v = qv0 - cv, d1v = qv1 - cv;
+          acc[0][j] = acc[0][j] + d0v * d0v;
+          acc[1][j] = acc[1][j] + d1v * d1v;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    int q = q0 + tq + i;
+    if (q >= nq) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int l = l0 + tl + 16 * j;
+      if (l < t.L) S[(size_t)q * t.L + l] = ip ? plus_zero(-acc[i][j]) : acc[i][j];
+    }
+  }
+}
+
+hipError_t launch_coarse_exact(const Tables& t, const float* Q, int32_t nq, float* scores,
+                               hipStream_t s) {
+  dim3 grid((t.L + CL - 1) / CL, (nq + CQ - 1) / CQ);
+  hipLaunchKernelGGL(coarse_exact_kernel, grid, dim3(256), 0, s, t, Q, nq, scores);
+  return hipGetLastError();
+}
+
+// Canonical score of one (query, list) pair, one thread, sequential over t.
+__device__ __forceinline__ float canonical_score(const Tables& t, const float* q, int l) {
+  const float* c = t.cp + (size_t)l * t.d;
+  float acc = 0.0f;
+  if (t.metric == IVF_METRIC_IP) {
+    for (int i = 0; i < t.d; ++i) acc = acc + q[i] * c[i];
+    return plus_zero(-acc);
+  }
+  for (int i = 0; i < t.d; ++i) {
+    float df = q[i] - c[i];
+    acc = acc + df * df;
+  }
+  return acc;
+}
+
+// One workgroup per query. Keys (ord(score) << 32 | list) live in LDS; the
+// wanted count is selected by radix selection and sorted. With `rescore`,
+// the first selection keeps widen*nprobe lists by the (approximate) score
+// matrix, those are re-scored canonically, and nprobe are kept.
+__global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __restrict__ Q,
+                                                     int32_t nq, const int32_t* __restrict__ nprobe,
+                                                     int32_t max_nprobe, int32_t widen,
+                                                     int32_t rescore, const float* __restrict__ S,
+                                                     int32_t* __restrict__ probes,
+                                                     int32_t* __restrict__ nprobe_eff,
+                                                     int32_t* __restrict__ err) {
+  extern __shared__ uint64_t keys[];  // [pow2_ceil(L)]
+  __shared__ SelectScratch sc;
+  __shared__ float qv[1024];
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int L = t.L;
+  int np = nprobe[q];
+  if (np < 1 || np > max_nprobe) {
+    if (tid == 0) {
+      nprobe_eff[q] = -1;
+      atomicOr(err, 1);
+    }
+    for (int p = tid; p < max_nprobe; p += blockDim.x) probes[(size_t)q * max_nprobe + p] = -1;
+    return;
+  }
+  const float* srow = S + (size_t)q * L;
+  int want = rescore ? min(L, np * widen) : np;
+  for (int l = tid; l < L; l += blockDim.x) keys[l] = make_key(srow[l], (uint32_t)l);
+  __syncthreads();
+  uint32_t n = (uint32_t)L;
+  __shared__ uint32_t cnt;
+  if ((uint32_t)want < n) {
+    KeyUnion u{keys, n, nullptr, 0};
+    n = block_compact_le(keys, n, block_kth(u, (uint32_t)want, &sc), &cnt);
+  }
+  if (rescore) {
+    // Canonical FP32 re-score of the kept lists; the query is staged in LDS
+    // when it fits, else read from global memory.
+    const float* qg = Q + (size_t)q * t.d;
+    const bool staged = t.d <= 1024;
+    if (staged)
+      for (int i = tid; i < t.d; i += blockDim.x) qv[i] = qg[i];
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += blockDim.x) {
+      int l = (int)(uint32_t)keys[i];
+      keys[i] = make_key(canonical_score(t, staged ? qv : qg, l), (uint32_t)l);
+    }
+    __syncthreads();
+    if ((uint32_t)np < n) {
+      KeyUnion u{keys, n, nullptr, 0};
+      n = block_compact_le(keys, n, block_kth(u, (uint32_t)np, &sc), &cnt);
+    }
+  }
+  const uint32_t n2 = pow2_ceil(n);
+  for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
+  block_bitonic_sort(keys, n2);
+  for (int p = tid; p < max_nprobe; p += blockDim.x)
+    probes[(size_t)q * max_nprobe + p] = p < np ? (int32_t)(uint32_t)keys[p] : -1;
+  if (tid == 0) nprobe_eff[q] = np;
+}
+
+hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
+                                const int32_t* nprobe, int32_t max_nprobe, int32_t widen,
+                                bool rescore, const Workspace& w, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  size_t lds = (size_t)pow2_ceil((uint32_t)t.L) * sizeof(uint64_t);
+  hipLaunchKernelGGL(select_kernel, dim3(nq), dim3(256), lds, s, t, Q, nq, nprobe, max_nprobe,
+                     widen, rescore ? 1 : 0, w.scores, w.probes, w.nprobe_eff, w.err);
+  return hipGetLastError();
+}
+
+// Caller-given probe sets: validate counts and list indices, copy.
+__global__ void copy_probes_kernel(const int32_t* __restrict__ probes_in,
+                                   const int32_t* __restrict__ nprobe, int32_t nq,
+                                   int32_t max_nprobe, int32_t L, int32_t* __restrict__ probes,
+                                   int32_t* __restrict__ nprobe_eff, int32_t* __restrict__ err) {
+  const int q = blockIdx.x;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int np = nprobe[q];
+  bool okn = np >= 1 && np <= max_nprobe;
+  for (int p = threadIdx.x; p < max_nprobe; p += blockDim.x) {
+    int l = probes_in[(size_t)q * max_nprobe + p];
+    if (okn && p < np && (l < 0 || l >= L)) bad = 1;
+    probes[(size_t)q * max_nprobe + p] = l;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!okn) atomicOr(err, 1);
+    if (bad) atomicOr(err, 2);
+    nprobe_eff[q] = (okn && !bad) ? np : -1;
+  }
+}
+
+hipError_t launch_copy_probes(const int32_t* probes, const int32_t* nprobe, int32_t nq,
+                              int32_t max_nprobe, int32_t L, const Workspace& w, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_probes_kernel, dim3(nq), dim3(64), 0, s, probes, nprobe, nq, max_nprobe,
+                     L, w.probes, w.nprobe_eff, w.err);
+  return hipGetLastError();
+}
+
+// Inner-product list constant b = -<q, cm_l> (sequential over t, FP32), one
+// thread per (query, probe slot).
+__global__ void bias_kernel(Tables t, const float* __restrict__ Q, int32_t nq, int32_t max_nprobe,
+                            const int32_t* __restrict__ probes,
+                            const int32_t* __restrict__ nprobe_eff, float* __restrict__ bias) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nq * max_nprobe) return;
+  const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
+  if (p >= nprobe_eff[q]) return;
+  const int l = probes[i];
+  const float* qq = Q + (size_t)q * t.d;
+  const float* c = t.cm + (size_t)l * t.d;
+  float acc = 0.0f;
+  for (int k = 0; k < t.d; ++k) acc = acc + qq[k] * c[k];
+  bias[i] = plus_zero(-acc);
+}
+
+hipError_t launch_bias(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                       const Workspace& w, hipStream_t s) {
+  if (t.metric != IVF_METRIC_IP || nq == 0) return hipSuccess;
+  int64_t n = (int64_t)nq * max_nprobe;
+  hipLaunchKernelGGL(bias_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, Q, nq,
+                     max_nprobe, w.probes, w.nprobe_eff, w.bias);
+  return hipGetLastError();
+}
+
+}  // namespace ivf

@@ -1,0 +1,110 @@
+// Host-side structures shared by the ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ivf.h"
+
+namespace ivf {
+
+constexpr int KSUB = 16;          // codewords per subspace (4-bit codes)
+constexpr int BLOCK_PTS = 64;     // points per packed block (one wavefront)
+constexpr int MAX_M = 256;
+constexpr int MAX_RERANK = 2048;
+constexpr int MAX_L = 1 << 20;
+constexpr int TILE_L = 64;        // low-precision centroid tables: L padded to this
+constexpr int TILE_D = 64;        // ... and d padded to this
+constexpr size_t ALIGN = 256;
+
+inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
+
+// Device view of a built index (pointers into caller-owned table memory).
+struct Tables {
+  int64_t n;
+  int32_t d, L, m, dsub, metric, base_dtype;
+  int32_t words;      // 32-bit code words per point = m_pad / 8
+  int32_t m_pad;      // m rounded up to a multiple of 8
+  int32_t blocks;     // total 64-point blocks
+  int32_t L_pad, d_pad;
+  int32_t max_list_len;
+  const void* base;
+  const uint32_t* codes;        // [blocks][words][64]
+  const int32_t* slot_ids;      // [blocks][64]
+  const int32_t* block_off;     // [L+1]
+  const int32_t* list_len;      // [L]
+  const float* cm;              // [L][d]
+  const float* cp;              // [L][d]
+  const float* codebooks;       // [m_pad][16][dsub]
+  const float* cp_norm2;        // [L_pad]
+  const uint16_t* cp_bf16;      // [L_pad][d_pad]
+  const uint8_t* cp_fp8;        // [L_pad][d_pad]
+  const float* cp_fp8_scale;    // [L_pad]
+};
+
+}  // namespace ivf
+
+struct ivf_index {
+  ivf::Tables t;
+  ivf_table_layout layout;
+  void* table_mem;
+};
+
+namespace ivf {
+
+// ---- workspace for one search -------------------------------------------
+struct Workspace {
+  float* scores;        // [nq][L] coarse scores (exact or approximate)
+  int32_t* probes;      // [nq][max_nprobe]
+  int32_t* nprobe_eff;  // [nq]; -1 marks an invalid request
+  float* bias;          // [nq][max_nprobe] per-(q,list) constant (IP), else unused
+  uint64_t* cand;       // [nq][rerank]
+  int32_t* err;         // [4] device error word
+  int32_t* cand_count;  // [nq] batched: survivors per query
+  uint32_t* queue;      // [8] batched: work-queue counters
+  uint64_t* thr;        // [nq] batched: per-query threshold keys
+  int32_t* items;       // [max_items][2] batched: (query, probe slot | chunk)
+  uint64_t* spill;      // [nq][spill_cap] batched: survivors
+  uint16_t* q_lowp;     // [nq_pad][d_pad] queries converted for MFMA coarse
+  float* q_scale;       // [nq_pad]
+  size_t total;
+  int32_t spill_cap, max_items;
+};
+
+Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_t k,
+                         int32_t rerank, const ivf_search_opts& o, char* base);
+
+// ---- launchers (each enqueues on `s`, returns hipSuccess or an error) ----
+hipError_t launch_pack(const Tables& t, const uint8_t* codes, const int64_t* list_off_dev,
+                       const int32_t* list_ids, hipStream_t s);
+hipError_t launch_aux_tables(const Tables& t, hipStream_t s);
+
+hipError_t launch_coarse_exact(const Tables& t, const float* Q, int32_t nq, float* scores,
+                               hipStream_t s);
+hipError_t launch_coarse_mfma(const Tables& t, const float* Q, int32_t nq, int coarse,
+                              const Workspace& w, hipStream_t s);
+// Select per query the nprobe[q]*widen best lists of `scores` and, when
+// widen > 1 or the scores are approximate, re-score them canonically and
+// keep the nprobe[q] best. Writes probes / nprobe_eff.
+hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
+                                const int32_t* nprobe, int32_t max_nprobe, int32_t widen,
+                                bool rescore, const Workspace& w, hipStream_t s);
+hipError_t launch_copy_probes(const int32_t* probes, const int32_t* nprobe, int32_t nq,
+                              int32_t max_nprobe, int32_t L, const Workspace& w,
+                              hipStream_t s);
+hipError_t launch_bias(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                       const Workspace& w, hipStream_t s);
+hipError_t launch_scan_plain(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                             int32_t rerank, const Workspace& w, hipStream_t s);
+hipError_t launch_scan_batched(const Tables& t, const float* Q, int32_t nq,
+                               int32_t max_nprobe, int32_t rerank, int32_t chunk,
+                               const Workspace& w, hipStream_t s);
+hipError_t launch_debug_luts(const Tables& t, const float* Q, int32_t nq, const int32_t* probes,
+                             const int32_t* nprobe, int32_t max_nprobe, uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
+                             hipStream_t s);
+hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k, int32_t rerank,
+                         const Workspace& w, int64_t* out_ids, float* out_dist, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+
+}  // namespace ivf

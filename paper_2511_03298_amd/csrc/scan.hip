@@ -1,0 +1,321 @@
+// Steps 2-4 of the search: lookup table of Eq. (1) per (query, probed list),
+// its 8-bit quantisation, the ADC scan of the list's 4-bit codes and the
+// candidate pool of the `reorder` best (approximate value, id) keys
+// (Alg. 3, brute-force branch: CalculatePQDistances + UpdateNNPool).
+//
+// Canonical arithmetic (compiled without FP contraction), identical to the
+// CPU reference definition:
+//   L2   T[j,i] = sum_u (r_{j d'+u} - B[j,i,u])^2, r = q - cm_l, sequential in u
+//   IP   T[j,i] = -sum_u q_{j d'+u} B[j,i,u];   bias_l = -<q, cm_l> (sequential)
+//   lo_j = min_i T[j,i];  rng = max_j max_i (T[j,i] - lo_j)
+//   s = 255 / rng;  delta = rng / 255  (correctly rounded divisions)
+//   lut[j,i] = min(255, rint((T[j,i] - lo_j) * s))   (0 everywhere if rng == 0)
+//   B = pairwise_sum_j(lo_j) + bias_l
+//   a(x) = B + delta * float(sum_j lut[j, code_j(x)])
+// The pool keeps the R smallest keys (ord(a) << 32 | id).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ivf {
+
+struct LutState {
+  float delta;
+  float lo_sum;   // pairwise sum of lo_j
+  uint32_t rng_bits;
+  uint32_t pad;
+};
+
+// Float table of one (query, list) pair (L2) or of the query (IP).
+__device__ __forceinline__ void lut_float(const Tables& t, const float* qv, int l, float* Tf) {
+  const int ne = t.m * KSUB;
+  const int ds = t.dsub;
+  if (t.metric == IVF_METRIC_L2) {
+    const float* c = t.cm + (size_t)l * t.d;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      const int j = e >> 4;
+      const float* cb = t.codebooks + (size_t)e * ds;
+      float acc = 0.0f;
+      for (int u = 0; u < ds; ++u) {
+        float r = qv[j * ds + u] - c[j * ds + u];
+        float df = r - cb[u];
+        acc = acc + df * df;
+      }
+      Tf[e] = acc;
+    }
+  } else {
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      const int j = e >> 4;
+      const float* cb = t.codebooks + (size_t)e * ds;
+      float acc = 0.0f;
+      for (int u = 0; u < ds; ++u) acc = acc + qv[j * ds + u] * cb[u];
+      Tf[e] = plus_zero(-acc);
+    }
+  }
+}
+
+// Pairwise sum of v[0..m) padded with zeros to a power of two, by wave 0
+// (adjacent pairs first, then pairs of pairs, ...).
+__device__ __forceinline__ float wave_pairwise_sum(const float* v, int m) {
+  const int lane = lane_id();
+  const int p2 = (int)pow2_ceil((uint32_t)m);
+  float x;
+  int width;
+  if (p2 <= IVF_WAVE) {
+    x = lane < m ? v[lane] : 0.0f;
+    width = p2;
+  } else {
+    const int per = p2 / IVF_WAVE;  // 2 or 4 consecutive elements per lane
+    float e[4];
+    for (int i = 0; i < 4; ++i) {
+      int idx = lane * per + i;
+      e[i] = (i < per && idx < m) ? v[idx] : 0.0f;
+    }
+    x = per == 2 ? e[0] + e[1] : (e[0] + e[1]) + (e[2] + e[3]);
+    width = IVF_WAVE;
+  }
+  for (int s = 1; s < width; s <<= 1) x = x + __shfl_xor(x, s);
+  return __shfl(x, 0);
+}
+
+// Quantise Tf into lut8 (m_pad*16 bytes), lo[0..m), and publish delta and
+// the pairwise sum of lo in `st`. All threads; ends with a barrier.
+__device__ __forceinline__ void lut_quantize(const Tables& t, const float* Tf, float* lo,
+                                             uint8_t* lut8, LutState* st) {
+  const int m = t.m;
+  if (threadIdx.x == 0) st->rng_bits = 0u;
+  __syncthreads();
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const float* row = Tf + j * KSUB;
+    float mn = row[0];
+    for (int i = 1; i < KSUB; ++i) mn = fminf(mn, row[i]);
+    float mx = 0.0f;
+    for (int i = 0; i < KSUB; ++i) mx = fmaxf(mx, row[i] - mn);
+    lo[j] = mn;
+    atomicMax(&st->rng_bits, __float_as_uint(mx));  // mx >= 0: bit order = value order
+  }
+  __syncthreads();
+  const float rng = __uint_as_float(st->rng_bits);
+  const bool live = rng > 0.0f;
+  const float s = live ? 255.0f / rng : 0.0f;
+  const int ne = t.m_pad * KSUB;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    const int j = e >> 4;
+    uint8_t v = 0;
+    if (live && j < m) {
+      float x = rintf((Tf[e] - lo[j]) * s);
+      v = (uint8_t)fminf(x, 255.0f);
+    }
+    lut8[e] = v;
+  }
+  if (threadIdx.x < IVF_WAVE) {
+    float ls = wave_pairwise_sum(lo, m);
+    if (threadIdx.x == 0) {
+      st->lo_sum = ls;
+      st->delta = live ? rng / 255.0f : 0.0f;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Plain form: one workgroup per query, lists visited in coarse order.
+// ---------------------------------------------------------------------------
+
+template <int W>
+struct ScanShared {
+  uint8_t lut8[W * 8 * KSUB];
+  float lo[W * 8];
+  LutState st;
+  SelectScratch sc;
+  uint32_t total;
+  uint32_t cnt;
+};
+
+// Scan the 64-point blocks [b_begin, b_end) of list l with the table in LDS;
+// append keys <= thr to keys[] (counter st.total). One wave per block.
+template <int W>
+__device__ __forceinline__ void scan_block(const Tables& t, const uint8_t* lut8, int blk,
+                                           int p_in_list, int n_l, float B, float delta,
+                                           uint64_t thr, uint64_t* keys, uint32_t* total) {
+  const int lane = lane_id();
+  const uint32_t* cw = t.codes + (size_t)blk * W * BLOCK_PTS + lane;
+  uint32_t words[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) words[w] = cw[w * BLOCK_PTS];
+  uint32_t S = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t x = words[w];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) S += lut8[(w * 8 + s) * KSUB + ((x >> (4 * s)) & 15u)];
+  }
+  const bool valid = p_in_list + lane < n_l;
+  const float a = plus_zero(B + delta * (float)S);
+  const uint32_t oa = f2ord(a);
+  const bool maybe = valid && oa <= (uint32_t)(thr >> 32);
+  const uint32_t id = maybe ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + lane] : 0u;
+  const uint64_t key = ((uint64_t)oa << 32) | id;
+  wave_append(maybe && key <= thr, key, keys, total);
+}
+
+template <int W>
+__global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* __restrict__ Q,
+                                                         int32_t nq, int32_t max_nprobe,
+                                                         int32_t R, int32_t cap,
+                                                         const int32_t* __restrict__ probes,
+                                                         const int32_t* __restrict__ nprobe_eff,
+                                                         const float* __restrict__ bias,
+                                                         uint64_t* __restrict__ cand) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ ScanShared<W> sh;
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int wave = tid / IVF_WAVE;
+  uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);            // [R + cap]
+  float* Tf = reinterpret_cast<float*>(keys + R + cap);          // [m_pad*16]
+  float* qv = Tf + t.m_pad * KSUB;                               // [d]
+  const int np = nprobe_eff[q];
+
+  for (int i = tid; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
+  if (tid == 0) sh.total = 0;
+  __syncthreads();
+
+  uint64_t thr = KEY_NONE;
+  const uint32_t limit = (uint32_t)(R + cap - IVF_BLOCK);
+  const bool ip = t.metric == IVF_METRIC_IP;
+  if (ip && np > 0) {
+    lut_float(t, qv, 0, Tf);
+    __syncthreads();
+    lut_quantize(t, Tf, sh.lo, sh.lut8, &sh.st);
+  }
+  for (int p = 0; p < np; ++p) {
+    const int l = probes[(size_t)q * max_nprobe + p];
+    float b = 0.0f;
+    if (!ip) {
+      lut_float(t, qv, l, Tf);
+      __syncthreads();
+      lut_quantize(t, Tf, sh.lo, sh.lut8, &sh.st);
+    } else {
+      b = bias[(size_t)q * max_nprobe + p];
+    }
+    const float B = sh.st.lo_sum + b;
+    const float delta = sh.st.delta;
+    const int n_l = t.list_len[l];
+    const int blk0 = t.block_off[l];
+    const int nblk = (n_l + BLOCK_PTS - 1) / BLOCK_PTS;
+    for (int b0 = 0; b0 < nblk; b0 += IVF_NWAVES) {
+      const int bi = b0 + wave;
+      if (bi < nblk) scan_block<W>(t, sh.lut8, blk0 + bi, bi * BLOCK_PTS, n_l, B, delta, thr, keys,
+                                   &sh.total);
+      __syncthreads();
+      const uint32_t total = sh.total;
+      if (total > limit) {
+        KeyUnion u{keys, total, nullptr, 0};
+        thr = block_kth(u, (uint32_t)R, &sh.sc);
+        const uint32_t kept = block_compact_le(keys, total, thr, &sh.cnt);
+        if (tid == 0) sh.total = kept < (uint32_t)R ? kept : (uint32_t)R;
+        __syncthreads();
+      }
+    }
+    __syncthreads();  // the table is rebuilt for the next list
+  }
+  uint32_t total = sh.total;
+  if (total > (uint32_t)R) {
+    KeyUnion u{keys, total, nullptr, 0};
+    thr = block_kth(u, (uint32_t)R, &sh.sc);
+    total = block_compact_le(keys, total, thr, &sh.cnt);
+    if (total > (uint32_t)R) total = (uint32_t)R;
+  }
+  const uint32_t n2 = pow2_ceil(total > 0 ? total : 1);
+  for (uint32_t i = total + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
+  block_bitonic_sort(keys, n2);
+  for (int i = tid; i < R; i += blockDim.x)
+    cand[(size_t)q * R + i] = (uint32_t)i < total ? keys[i] : KEY_NONE;
+}
+
+// Candidate-buffer slack beyond R (keys), large enough that a round of one
+// block per wave never overflows and the final sort fits.
+inline int32_t scan_cap(int32_t R) {
+  int32_t p2 = (int32_t)pow2_ceil((uint32_t)R);
+  int32_t cap = 1024;
+  if (p2 - R > cap) cap = p2 - R;
+  return cap;
+}
+
+template <int W>
+static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t nq,
+                                      int32_t max_nprobe, int32_t R, const Workspace& w,
+                                      hipStream_t s) {
+  const int32_t cap = scan_cap(R);
+  size_t lds = (size_t)(R + cap) * 8 + (size_t)t.m_pad * KSUB * 4 + (size_t)t.d * 4;
+  hipLaunchKernelGGL(scan_plain_kernel<W>, dim3(nq), dim3(256), lds, s, t, Q, nq, max_nprobe, R,
+                     cap, w.probes, w.nprobe_eff, w.bias, w.cand);
+  return hipGetLastError();
+}
+
+#define IVF_W_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
+  X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+hipError_t launch_scan_plain(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                             int32_t rerank, const Workspace& w, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  switch (t.words) {
+#define X(N) \
+  case N: return launch_scan_plain_w<N>(t, Q, nq, max_nprobe, rerank, w, s);
+    IVF_W_CASES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Parity export of step 2: the quantised table of each (query, probed list).
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) debug_lut_kernel(Tables t, const float* __restrict__ Q,
+                                                        int32_t max_nprobe,
+                                                        const int32_t* __restrict__ probes,
+                                                        const int32_t* __restrict__ nprobe,
+                                                        uint8_t* out_lut, float* out_lo,
+                                                        float* out_delta, float* out_B) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ uint8_t lut8[MAX_M * KSUB];
+  __shared__ float lo[MAX_M];
+  __shared__ LutState st;
+  const int q = blockIdx.x, p = blockIdx.y;
+  const size_t qp = (size_t)q * max_nprobe + p;
+  if (p >= nprobe[q] || probes[qp] < 0 || probes[qp] >= t.L) return;
+  float* Tf = reinterpret_cast<float*>(dyn);
+  float* qv = Tf + t.m_pad * KSUB;
+  for (int i = threadIdx.x; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
+  __syncthreads();
+  const int l = probes[qp];
+  lut_float(t, qv, l, Tf);
+  __syncthreads();
+  lut_quantize(t, Tf, lo, lut8, &st);
+  float b = 0.0f;
+  if (t.metric == IVF_METRIC_IP) {  // -<q, cm_l>, sequential over t
+    const float* c = t.cm + (size_t)l * t.d;
+    for (int k = 0; k < t.d; ++k) b = b + qv[k] * c[k];
+    b = plus_zero(-b);
+  }
+  for (int e = threadIdx.x; e < t.m * KSUB; e += blockDim.x) out_lut[qp * t.m * KSUB + e] = lut8[e];
+  for (int j = threadIdx.x; j < t.m; j += blockDim.x) out_lo[qp * t.m + j] = lo[j];
+  if (threadIdx.x == 0) {
+    out_delta[qp] = st.delta;
+    out_B[qp] = st.lo_sum + b;
+  }
+}
+
+hipError_t launch_debug_luts(const Tables& t, const float* Q, int32_t nq, const int32_t* probes,
+                             const int32_t* nprobe, int32_t max_nprobe, uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
+                             hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  size_t lds = (size_t)t.m_pad * KSUB * 4 + (size_t)t.d * 4;
+  hipLaunchKernelGGL(debug_lut_kernel, dim3(nq, max_nprobe), dim3(256), lds, s, t, Q, max_nprobe,
+                     probes, nprobe, out_lut, out_lo, out_delta, out_B);
+  return hipGetLastError();
+}
+
+}  // namespace ivf

@@ -1,0 +1,144 @@
+// Device tables of a trained index (one-time, untimed): the packed 4-bit code
+// blocks the ADC scan streams (the GPU counterpart of the SIMD data blocks of
+// Alg. 1, BuildBlocks) and the centroid tables used by coarse scoring.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ivf {
+
+// One thread per 64-point slot: find the slot's list, fetch the point's m
+// codes and write its words. Layout per block: word-major, 64 lanes
+// contiguous, so that a wavefront reading word w of a block reads 256
+// consecutive bytes.
+__global__ void __launch_bounds__(256) pack_kernel(Tables t, const uint8_t* __restrict__ codes,
+                                                   const int64_t* __restrict__ list_off,
+                                                   const int32_t* __restrict__ list_ids,
+                                                   uint32_t* __restrict__ out_codes,
+                                                   int32_t* __restrict__ out_ids) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= (int64_t)t.blocks * BLOCK_PTS) return;
+  const int blk = (int)(slot / BLOCK_PTS);
+  const int lane = (int)(slot % BLOCK_PTS);
+  int lo = 0, hi = t.L;  // block_off[lo] <= blk < block_off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (t.block_off[mid] <= blk) lo = mid; else hi = mid;
+  }
+  const int l = lo;
+  const int64_t p = (int64_t)(blk - t.block_off[l]) * BLOCK_PTS + lane;
+  const bool valid = p < t.list_len[l];
+  const int32_t id = valid ? list_ids[list_off[l] + p] : -1;
+  for (int w = 0; w < t.words; ++w) {
+    uint32_t word = 0;
+    if (valid) {
+      for (int s = 0; s < 8; ++s) {
+        int j = 8 * w + s;
+        if (j < t.m) word |= (uint32_t)(codes[(int64_t)id * t.m + j] & 15) << (4 * s);
+      }
+    }
+    out_codes[((size_t)blk * t.words + w) * BLOCK_PTS + lane] = word;
+  }
+  out_ids[slot] = id;
+}
+
+hipError_t launch_pack(const Tables& t, const uint8_t* codes, const int64_t* list_off_dev,
+                       const int32_t* list_ids, hipStream_t s) {
+  const int64_t slots = (int64_t)t.blocks * BLOCK_PTS;
+  if (slots == 0) return hipSuccess;
+  const int grid = (int)((slots + 255) / 256);
+  hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, s, t, codes, list_off_dev, list_ids,
+                     const_cast<uint32_t*>(t.codes), const_cast<int32_t*>(t.slot_ids));
+  return hipGetLastError();
+}
+
+// Round to nearest even bfloat16.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// OCP FP8 E4M3 (max finite 448, no infinities) with round to nearest even,
+// written from the format definition; |x| is pre-scaled into range.
+__device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
+  uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+  float a = fminf(fabsf(x), 448.0f);
+  if (!(a > 0.0f)) return (uint8_t)sign;
+  // Subnormal spacing 2^-9 below 2^-6; normals have 3 mantissa bits.
+  int e = 0;
+  frexpf(a, &e);            // a = f * 2^e, f in [0.5, 1)
+  int exp_unb = e - 1;      // a in [2^exp_unb, 2^(exp_unb+1))
+  if (exp_unb < -6) exp_unb = -6;
+  float quantum = ldexpf(1.0f, exp_unb - 3);
+  float qv = rintf(a / quantum) * quantum;  // a / quantum is exact (power of 2)
+  if (qv > 448.0f) qv = 448.0f;
+  if (qv == 0.0f) return (uint8_t)sign;
+  int e2 = 0;
+  float f2 = frexpf(qv, &e2);
+  int eu = e2 - 1;
+  uint32_t bits;
+  if (eu < -6) {  // subnormal: value = mant * 2^-9
+    bits = (uint32_t)rintf(qv * 512.0f);
+  } else {
+    uint32_t mant = (uint32_t)rintf((f2 * 2.0f - 1.0f) * 8.0f);
+    bits = ((uint32_t)(eu + 7) << 3) | mant;
+  }
+  return (uint8_t)(sign | bits);
+}
+
+// Low-precision copies of the probe centroids for the MFMA coarse scores:
+// squared norms, BF16 rows, FP8 rows with one scale per row; zero padded to
+// [L_pad][d_pad].
+__global__ void __launch_bounds__(256) aux_kernel(Tables t) {
+  const int l = blockIdx.x;
+  const bool live = l < t.L;
+  __shared__ float red[256];
+  float amax = 0.0f, nrm = 0.0f;
+  for (int c = threadIdx.x; c < t.d; c += blockDim.x) {
+    float v = live ? t.cp[(size_t)l * t.d + c] : 0.0f;
+    amax = fmaxf(amax, fabsf(v));
+    nrm += v * v;
+  }
+  red[threadIdx.x] = amax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const float rmax = red[0];
+  __syncthreads();
+  red[threadIdx.x] = nrm;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const float scale = rmax > 0.0f ? rmax / 448.0f : 1.0f;
+  if (threadIdx.x == 0) {
+    const_cast<float*>(t.cp_norm2)[l] = red[0];
+    const_cast<float*>(t.cp_fp8_scale)[l] = scale;
+  }
+  for (int c = threadIdx.x; c < t.d_pad; c += blockDim.x) {
+    float v = (live && c < t.d) ? t.cp[(size_t)l * t.d + c] : 0.0f;
+    const_cast<uint16_t*>(t.cp_bf16)[(size_t)l * t.d_pad + c] = f32_to_bf16(v);
+    const_cast<uint8_t*>(t.cp_fp8)[(size_t)l * t.d_pad + c] = f32_to_e4m3(v / scale);
+  }
+}
+
+hipError_t launch_aux_tables(const Tables& t, hipStream_t s) {
+  hipLaunchKernelGGL(aux_kernel, dim3(t.L_pad), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace ivf

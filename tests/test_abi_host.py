@@ -1,0 +1,120 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function include/ivf.h declares, and
+reject invalid arguments before touching a device.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2511_03298_amd as ivf
+    if not os.path.exists(ivf.LIB_PATH):
+        pytest.skip("library not built")
+    return ivf, ivf.lib()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ivf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ivf_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function():
+    ivf, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(ivf.EXPORTED)
+
+
+def _desc(ivf, n=1000, d=32, L=8, m=16, offsets=None):
+    offs = offsets if offsets is not None else np.linspace(0, n, L + 1).astype(np.int64)
+    fake = 0x10000  # never dereferenced: validation and sizing are host-only
+    desc = ivf.IndexDesc(n=n, d=d, L=L, m=m, metric=0, base_dtype=0, base=fake,
+                         centroids=fake, probe_centroids=None, codebooks=fake, codes=fake,
+                         list_offsets=offs.ctypes.data, list_ids=fake)
+    return desc, offs
+
+
+def test_table_sizing_matches_layout():
+    ivf, lib = _lib()
+    desc, offs = _desc(ivf, n=1000, d=32, L=8, m=16)
+    nbytes = lib.ivf_tables_bytes(ctypes.byref(desc))
+    lens = np.diff(offs)
+    blocks = int(((lens + 63) // 64).sum())
+    words = 2
+    assert nbytes >= blocks * words * 64 * 4 + blocks * 64 * 4
+    assert nbytes % 256 == 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 0), ("d", 0), ("L", 0), ("m", 0), ("m", 300), ("d", 33), ("metric", 7),
+    ("base_dtype", 3), ("base", None), ("codes", None), ("list_ids", None),
+])
+def test_invalid_descriptors_rejected(field, value):
+    ivf, lib = _lib()
+    desc, offs = _desc(ivf)
+    setattr(desc, field, value)
+    assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
+    assert ivf.last_error()
+    h = ctypes.c_void_p()
+    st = lib.ivf_build_tables(ctypes.byref(desc), 0x100000, 1 << 30, None, ctypes.byref(h))
+    assert st == ivf.IVF_ERR_INVALID_ARG
+    assert not h.value
+
+
+def test_bad_offsets_rejected():
+    ivf, lib = _lib()
+    offs = np.array([0, 10, 5, 1000] + [1000] * 5, dtype=np.int64)
+    desc, _ = _desc(ivf, offsets=offs)
+    assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
+    offs = np.linspace(0, 999, 9).astype(np.int64)
+    desc, _ = _desc(ivf, offsets=offs)
+    assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
+
+
+def test_small_table_memory_rejected_before_device_use():
+    ivf, lib = _lib()
+    desc, offs = _desc(ivf)
+    nbytes = lib.ivf_tables_bytes(ctypes.byref(desc))
+    h = ctypes.c_void_p()
+    st = lib.ivf_build_tables(ctypes.byref(desc), 0x100000, nbytes - 256, None, ctypes.byref(h))
+    assert st == ivf.IVF_ERR_WORKSPACE
+
+
+def test_valid_build_without_device_reports_device_error():
+    ivf, lib = _lib()
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    desc, offs = _desc(ivf)
+    nbytes = lib.ivf_tables_bytes(ctypes.byref(desc))
+    h = ctypes.c_void_p()
+    st = lib.ivf_build_tables(ctypes.byref(desc), 0x100000, nbytes, None, ctypes.byref(h))
+    assert st == ivf.IVF_ERR_DEVICE
+    assert "device" in ivf.last_error()
+
+
+def test_search_argument_validation_without_index():
+    ivf, lib = _lib()
+    o = ivf.make_opts()
+    assert lib.ivf_search_workspace_bytes(None, 10, 4, 10, 100, ctypes.byref(o)) == 0
+    st = lib.ivf_search(None, None, 1, None, 1, 1, 1, None, None, 0, None, None, None)
+    assert st == ivf.IVF_ERR_INVALID_ARG
+    assert lib.ivf_get_device_error(None, None, None) == -1
+
+
+def test_default_opts():
+    ivf, lib = _lib()
+    o = ivf.SearchOpts()
+    lib.ivf_default_opts(ctypes.byref(o))
+    assert (o.coarse, o.widen, o.form, o.use_graph, o.chunk) == (0, 2, 0, 0, 0)

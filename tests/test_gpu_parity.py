@@ -1,0 +1,225 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle.
+
+Probe sets, quantised tables (bytes, offsets, scale, constant), candidate
+pools (value, id) are compared bit for bit; re-ranked distances within 1e-5
+relative of FP64, final ids equal up to the FP64 tie band. All calls go
+through the C ABI (libivfpq.so) via the Python binding.
+"""
+
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import cached_workload
+from gpu_helpers import check_final, oracle_stages, unpack_tables
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_03298_amd as ivf
+    return ivf
+
+
+# name -> (workload, n, nq, L, ncomp, overrides)
+CASES = {
+    "c1": ("c1", 10_000, 100, None, None, {}),
+    "c2s": ("c2", 40_000, 40, 64, 40, dict(nprobe=(6, 6))),
+    "c3s": ("c3", 30_000, 40, 80, 80, dict(nprobe=(8, 32))),
+    "c4s": ("c4", 40_000, 20, 64, 64, dict(nprobe=(8, 8))),
+    "c5s": ("c5", 12_000, 12, 32, 32, dict(nprobe=(4, 16))),
+}
+
+_STATE = {}
+
+
+def case(name):
+    if name not in _STATE:
+        ivf = _gpu()
+        wl, n, nq, L, ncomp, kw = CASES[name]
+        cfg, X, Q, nprobe, index = cached_workload(wl, n, nq, L=L, ncomp=ncomp, **kw)
+        print(f"[case {name}] n={cfg.n} d={cfg.d} L={cfg.L} m={cfg.m} nq={cfg.nq} "
+              f"R={cfg.R} k={cfg.k} metric={cfg.metric}", flush=True)
+        g = ivf.GpuIndex.from_index(index, X, base_dtype=cfg.base_dtype)
+        res = oracle_stages(index, X, Q, nprobe, cfg.k, cfg.R)
+        _STATE[name] = (cfg, X, Q, nprobe, index, g, res)
+    return _STATE[name]
+
+
+def probes_tensor(res, nprobe):
+    mx = int(max(nprobe))
+    P = np.full((len(nprobe), mx), -1, dtype=np.int32)
+    for qi, p in enumerate(res["probes"]):
+        P[qi, :len(p)] = p
+    return torch.from_numpy(P)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pack_roundtrip(name):
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    lay = g.layout()
+    tables = g.tables.cpu().numpy()
+    codes, slot_ids, pad = unpack_tables(tables, lay, cfg.m)
+    assert np.all(pad == 0)
+    boff = tables[lay.block_offsets:lay.block_offsets + (cfg.L + 1) * 4].view(np.int32)
+    off, lid = index["list_offsets"], index["list_ids"]
+    for l in range(cfg.L):
+        ids = lid[off[l]:off[l + 1]]
+        s0 = boff[l] * 64
+        nblk = boff[l + 1] - boff[l]
+        assert nblk == (len(ids) + 63) // 64
+        assert np.array_equal(slot_ids[s0:s0 + len(ids)], ids)
+        assert np.all(slot_ids[s0 + len(ids):s0 + nblk * 64] == -1)
+        assert np.array_equal(codes[s0:s0 + len(ids)], index["codes"][ids])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_probe_sets_bit_exact(name):
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    got = g.debug_probes(Q, nprobe).cpu().numpy()
+    for qi, p in enumerate(res["probes"]):
+        assert np.array_equal(got[qi, :len(p)], p), qi
+        assert np.all(got[qi, len(p):] == -1)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_luts_bit_exact(name):
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    P = probes_tensor(res, nprobe)
+    lut, lo, delta, B = [t.cpu().numpy() for t in g.debug_luts(Q, P, nprobe)]
+    for qi, p in enumerate(res["probes"]):
+        for pi, l in enumerate(p):
+            q8, lo_o, d_o, B_o = res["luts"][(qi, int(l))]
+            assert np.array_equal(lut[qi, pi], q8), (qi, l)
+            assert np.array_equal(lo[qi, pi].view(np.uint32), lo_o.view(np.uint32)), (qi, l)
+            assert delta[qi, pi].view(np.uint32) == np.float32(d_o).view(np.uint32), (qi, l)
+            assert B[qi, pi].view(np.uint32) == np.float32(B_o).view(np.uint32), (qi, l)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_candidates_bit_exact(name):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    P = probes_tensor(res, nprobe)
+    keys = g.debug_candidates(Q, P, nprobe, cfg.R).cpu().numpy()
+    a, ids = ivf.decode_keys(keys)
+    assert np.array_equal(ids, res["cand_id"])
+    assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_search_end_to_end(name):
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    ids, dist = g.search(Q, nprobe, cfg.k, cfg.R)
+    torch.cuda.synchronize()
+    assert g.device_error() == 0
+    check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q, cfg.metric,
+                exact_ids=(cfg.dist == "int255"))
+
+
+@pytest.mark.parametrize("name", ["c1", "c3s"])
+def test_repeat_runs_bit_identical(name):
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    outs = []
+    for _ in range(4):
+        ids, dist = g.search(Q, nprobe, cfg.k, cfg.R)
+        outs.append((ids.cpu().numpy(), dist.cpu().numpy().view(np.uint32)))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_nprobe_one_and_all_lists():
+    cfg, X, Q, nprobe, index, g, _ = case("c1")
+    for npb in (1, cfg.L):
+        res = oracle.search(index, X, Q[:20], npb, cfg.k, cfg.R)
+        ids, dist = g.search(Q[:20], npb, cfg.k, cfg.R)
+        check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q[:20], cfg.metric)
+
+
+def test_pool_larger_than_probed_points_and_k_equals_R():
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, _ = case("c1")
+    R = 2048
+    res = oracle.search(index, X, Q[:10], 1, 7, R)
+    P = torch.from_numpy(np.stack([oracle.select_probes(
+        oracle.coarse_scores(q, index["cp"], cfg.metric), 1) for q in Q[:10]]).astype(np.int32))
+    keys = g.debug_candidates(Q[:10], P, 1, R).cpu().numpy()
+    a, ids = ivf.decode_keys(keys)
+    assert np.array_equal(ids, res["cand_id"])
+    assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+    # k == R: every candidate comes back, ordered by exact distance.
+    res = oracle.search(index, X, Q[:10], 2, 50, 50)
+    gi, gd = g.search(Q[:10], 2, 50, 50)
+    check_final(gi.cpu().numpy(), gd.cpu().numpy(), res, X, Q[:10], cfg.metric)
+
+
+def test_empty_lists_and_tiny_index():
+    ivf = _gpu()
+    cfg, X, Q, nprobe, index, _, _ = case("c1")
+    idx = dict(index)
+    off = index["list_offsets"]
+    counts = np.diff(off).copy()
+    keep = np.ones(len(index["list_ids"]), bool)
+    for l in (0, 5, 9):
+        keep[off[l]:off[l + 1]] = False
+        counts[l] = 0
+    idx["list_offsets"] = np.concatenate(([0], np.cumsum(counts)))
+    idx["list_ids"] = index["list_ids"][keep]
+    # The index covers fewer points than X; ids still index rows of X.
+    g = ivf.GpuIndex(X, idx["cm"], idx["codebooks"], idx["codes"], idx["list_offsets"],
+                     idx["list_ids"], cfg.metric, probe_centroids=idx["cp"])
+    for npb in (1, 3, cfg.L):
+        res = oracle.search(idx, X, Q[:16], npb, cfg.k, cfg.R)
+        ids, dist = g.search(Q[:16], npb, cfg.k, cfg.R)
+        check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q[:16], cfg.metric)
+    # A tiny index: fewer points than one 64-point block, fewer than k.
+    small = dict(index)
+    sel = index["list_ids"][:5]
+    small_off = np.zeros(cfg.L + 1, dtype=np.int64)
+    small_off[1:] = 5
+    small["list_offsets"] = small_off
+    small["list_ids"] = np.sort(sel).astype(np.int32)
+    g2 = ivf.GpuIndex(X, small["cm"], small["codebooks"], small["codes"], small_off,
+                      small["list_ids"], cfg.metric, probe_centroids=small["cp"])
+    res = oracle.search(small, X, Q[:4], cfg.L, 10, 100)
+    ids, dist = g2.search(Q[:4], cfg.L, 10, 100)
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    assert np.all(ids[:, 5:] == -1) and np.all(np.isinf(dist[:, 5:]))
+    check_final(ids, dist, res, X, Q[:4], cfg.metric)
+
+
+def test_invalid_nprobe_sets_error_word():
+    cfg, X, Q, nprobe, index, g, _ = case("c1")
+    npb = np.full(8, 4, dtype=np.int32)
+    npb[3] = 0
+    npb[5] = 99
+    ids, dist = g.search(Q[:8], npb, cfg.k, cfg.R, max_nprobe=8)
+    torch.cuda.synchronize()
+    assert g.device_error() == 1
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    for qi in (3, 5):
+        assert np.all(ids[qi] == -1) and np.all(np.isnan(dist[qi]))
+    res = oracle.search(index, X, Q[:8], 4, cfg.k, cfg.R)
+    for qi in (0, 1, 2, 4, 6, 7):
+        assert np.array_equal(ids[qi][ids[qi] >= 0].shape, res["ids"][qi][res["ids"][qi] >= 0].shape)
+    assert g.device_error() == 0  # cleared by the read
+
+
+@pytest.mark.parametrize("name", ["c2s", "c4s"])
+def test_multiple_probed_lists_ragged_batch(name):
+    # nq not a multiple of any tile, per-query nprobe spanning 1..L.
+    cfg, X, Q, nprobe, index, g, _ = case(name)
+    rng = np.random.default_rng(7)
+    nq = 13
+    npb = rng.integers(1, cfg.L + 1, size=nq).astype(np.int32)
+    res = oracle.search(index, X, Q[:nq], npb, cfg.k, cfg.R)
+    ids, dist = g.search(Q[:nq], npb, cfg.k, cfg.R, max_nprobe=cfg.L)
+    check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q[:nq], cfg.metric,
+                exact_ids=(cfg.dist == "int255"))
