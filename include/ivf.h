@@ -73,8 +73,11 @@ typedef struct {
   const uint8_t* codes;           /* [n,m] one 4-bit code (0..15) per byte, row =
                                      point id. Consumed: packed into the tables.  */
   const int64_t* list_offsets;    /* HOST [L+1] CSR offsets into list_ids,
-                                     non-decreasing, list_offsets[L] == n.        */
-  const int32_t* list_ids;        /* [n] point ids grouped by list, ascending
+                                     non-decreasing, list_offsets[0] == 0 and
+                                     list_offsets[L] <= n (rows in no list are
+                                     never returned).                             */
+  const int32_t* list_ids;        /* [list_offsets[L]] point ids (rows of base,
+                                     each at most once) grouped by list, ascending
                                      within a list. Consumed.                     */
 } ivf_index_desc;
 
@@ -132,7 +135,7 @@ size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq,
  *   nprobe   [nq] int32, each in 1..max_nprobe (max_nprobe <= L). A value out
  *            of range sets the device error word (ivf_get_device_error) and
  *            that query's row is written as ids -1, distances NaN.
- *   k        1..rerank; rerank (reorder) 1..4096 candidates re-ranked exactly.
+ *   k        1..rerank; rerank (reorder) 1..2048 candidates re-ranked exactly.
  *   out_ids  [nq,k] int64 point ids, -1 when fewer than k candidates exist.
  *   out_dist [nq,k] FP32; padding is +inf (L2) or -inf (IP).
  * opts NULL = defaults. The workspace must hold ivf_search_workspace_bytes. */
@@ -202,6 +205,18 @@ ivf_status ivf_get_table_layout(const ivf_index* idx, ivf_table_layout* out);
  * bit mask: 1 = an nprobe[q] out of range. Returns -1 on a HIP failure. */
 int32_t ivf_get_device_error(const ivf_index* idx, void* workspace,
                              void* stream);
+
+/* Per-stage timing of ivf_search / ivf_search_with_probes. While enabled,
+ * every search records HIP events on its stream around its stages
+ * (IVF_STAGE_*); ivf_profile_read waits for the last recorded event and
+ * returns, per stage, the summed milliseconds and the number of searches
+ * since the previous read (then resets). At most 256 searches are kept
+ * between reads; older ones are dropped. */
+enum { IVF_STAGE_COARSE = 0, IVF_STAGE_SELECT = 1, IVF_STAGE_SCAN = 2,
+       IVF_STAGE_RERANK = 3, IVF_NSTAGES = 4 };
+ivf_status ivf_profile_enable(ivf_index* idx, int32_t on);
+ivf_status ivf_profile_read(ivf_index* idx, float* ms /* [IVF_NSTAGES] */,
+                            int32_t* count);
 
 /* Frees the host handle only; table_mem stays the caller's. */
 void ivf_destroy(ivf_index* idx);

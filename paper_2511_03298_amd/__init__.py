@@ -26,8 +26,9 @@ EXPORTED = [
     "ivf_default_opts", "ivf_tables_bytes", "ivf_build_tables", "ivf_search_workspace_bytes",
     "ivf_search", "ivf_search_with_probes", "ivf_debug_probes", "ivf_debug_luts",
     "ivf_debug_candidates", "ivf_get_table_layout", "ivf_get_device_error", "ivf_destroy",
-    "ivf_last_error",
+    "ivf_last_error", "ivf_profile_enable", "ivf_profile_read",
 ]
+STAGES = ("coarse", "select", "scan", "rerank")
 
 
 class IvfError(RuntimeError):
@@ -77,6 +78,8 @@ def _declare(lib):
         "ivf_get_table_layout": (I32, [P, P]),
         "ivf_get_device_error": (I32, [P, P, P]),
         "ivf_destroy": (None, [P]),
+        "ivf_profile_enable": (I32, [P, I32]),
+        "ivf_profile_read": (I32, [P, P, P]),
         "ivf_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -307,6 +310,16 @@ class GpuIndex:
                                          rerank, ctypes.byref(opts), ws.data_ptr(), ws.numel(),
                                          _ptr(keys), _stream()))
         return keys
+
+    def profile(self, on: bool = True):
+        check(lib().ivf_profile_enable(self._h, int(on)))
+
+    def profile_read(self):
+        """Summed milliseconds per stage and the number of searches since the last read."""
+        ms = (ctypes.c_float * 4)()
+        cnt = ctypes.c_int32()
+        check(lib().ivf_profile_read(self._h, ms, ctypes.byref(cnt)))
+        return dict(zip(STAGES, list(ms))), cnt.value
 
     def device_error(self) -> int:
         ws = next(iter(self._ws.values()), None)

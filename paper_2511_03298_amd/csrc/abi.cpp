@@ -12,6 +12,16 @@
 
 using namespace ivf;
 
+// Event pairs (start, stop) per stage for up to RING searches.
+struct ivf_profile {
+  static constexpr int RING = 256;
+  bool on = false;
+  int head = 0, count = 0;
+  hipEvent_t ev[RING][IVF_NSTAGES + 1] = {};
+  bool used[RING][IVF_NSTAGES] = {};
+  int cur = -1;
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -57,7 +67,7 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
     blocks += (len + BLOCK_PTS - 1) / BLOCK_PTS;
     if (len > mx) mx = len;
   }
-  if (off[d->L] != d->n) return "list_offsets[L] must equal n";
+  if (off[d->L] > d->n) return "list_offsets[L] must be <= n";
   std::memset(lay, 0, sizeof(*lay));
   const int32_t words = (d->m + 7) / 8;
   lay->words_per_point = words;
@@ -269,6 +279,7 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
   idx->t = t;
   idx->layout = lay;
   idx->table_mem = table_mem;
+  idx->prof = nullptr;
   *out = idx;
   return IVF_OK;
 }
@@ -279,7 +290,51 @@ ivf_status ivf_get_table_layout(const ivf_index* idx, ivf_table_layout* out) {
   return IVF_OK;
 }
 
-void ivf_destroy(ivf_index* idx) { delete idx; }
+void ivf_destroy(ivf_index* idx) {
+  if (!idx) return;
+  if (idx->prof) {
+    for (auto& row : idx->prof->ev)
+      for (auto& e : row)
+        if (e) (void)hipEventDestroy(e);
+    delete idx->prof;
+  }
+  delete idx;
+}
+
+ivf_status ivf_profile_enable(ivf_index* idx, int32_t on) {
+  if (!idx) return fail(IVF_ERR_INVALID_ARG, "index is NULL");
+  if (!idx->prof) {
+    idx->prof = new (std::nothrow) ivf_profile;
+    if (!idx->prof) return fail(IVF_ERR_INTERNAL, "out of host memory");
+  }
+  idx->prof->on = on != 0;
+  idx->prof->cur = -1;
+  return IVF_OK;
+}
+
+ivf_status ivf_profile_read(ivf_index* idx, float* ms, int32_t* count) {
+  if (!idx || !ms || !count) return fail(IVF_ERR_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < IVF_NSTAGES; ++i) ms[i] = 0.0f;
+  *count = 0;
+  ivf_profile* p = idx->prof;
+  if (!p || p->count == 0) return IVF_OK;
+  const int first = (p->head - p->count + ivf_profile::RING) % ivf_profile::RING;
+  const int last = (p->head - 1 + ivf_profile::RING) % ivf_profile::RING;
+  IVF_HIP(hipEventSynchronize(p->ev[last][IVF_NSTAGES]));
+  for (int c = 0; c < p->count; ++c) {
+    const int slot = (first + c) % ivf_profile::RING;
+    for (int i = 0; i < IVF_NSTAGES; ++i) {
+      if (!p->used[slot][i]) continue;
+      float t = 0.0f;
+      IVF_HIP(hipEventElapsedTime(&t, p->ev[slot][i], p->ev[slot][i + 1]));
+      ms[i] += t;
+    }
+  }
+  *count = p->count;
+  p->count = 0;
+  p->cur = -1;
+  return IVF_OK;
+}
 
 size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq, int32_t max_nprobe,
                                   int32_t k, int32_t rerank, const ivf_search_opts* opts) {
@@ -294,6 +349,34 @@ size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq, int32_t max_
 }  // extern "C"
 
 namespace {
+
+// Stage marks: mark(idx, s, i) records boundary i (stage i starts; stage
+// i-1 ends) of the current search when profiling is on.
+hipError_t prof_begin(const ivf_index* idx) {
+  ivf_profile* p = idx->prof;
+  if (!p || !p->on) return hipSuccess;
+  int slot = p->head;
+  p->head = (p->head + 1) % ivf_profile::RING;
+  if (p->count < ivf_profile::RING) ++p->count;
+  for (int i = 0; i <= IVF_NSTAGES; ++i) {
+    if (!p->ev[slot][i]) {
+      hipError_t e = hipEventCreate(&p->ev[slot][i]);
+      if (e != hipSuccess) return e;
+    }
+  }
+  for (int i = 0; i < IVF_NSTAGES; ++i) p->used[slot][i] = false;
+  p->cur = slot;
+  return hipSuccess;
+}
+
+hipError_t prof_mark(const ivf_index* idx, hipStream_t s, int boundary) {
+  ivf_profile* p = idx->prof;
+  if (!p || !p->on || p->cur < 0) return hipSuccess;
+  if (boundary < IVF_NSTAGES) p->used[p->cur][boundary] = true;
+  hipError_t e = hipEventRecord(p->ev[p->cur][boundary], s);
+  if (boundary == IVF_NSTAGES) p->cur = -1;  // this search is complete
+  return e;
+}
 
 // Shared front part of every search entry: validation and workspace carving.
 ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, int32_t k,
@@ -318,13 +401,16 @@ ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, int32_t nq,
                                const ivf_search_opts& o, const Workspace& w, int64_t* out_ids,
                                float* out_dist, hipStream_t s) {
   const Tables& t = idx->t;
+  IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
   IVF_HIP(launch_bias(t, Q, nq, max_nprobe, w, s));
   if (o.form == IVF_FORM_BATCHED) {
     IVF_HIP(launch_scan_batched(t, Q, nq, max_nprobe, rerank, o.chunk, w, s));
   } else {
     IVF_HIP(launch_scan_plain(t, Q, nq, max_nprobe, rerank, w, s));
   }
+  IVF_HIP(prof_mark(idx, s, IVF_STAGE_RERANK));
   if (out_ids) IVF_HIP(launch_rerank(t, Q, nq, k, rerank, w, out_ids, out_dist, s));
+  IVF_HIP(prof_mark(idx, s, IVF_NSTAGES));
   return IVF_OK;
 }
 
@@ -332,11 +418,14 @@ ivf_status run_coarse(const ivf_index* idx, const float* Q, int32_t nq, const in
                       int32_t max_nprobe, const ivf_search_opts& o, const Workspace& w,
                       hipStream_t s) {
   const Tables& t = idx->t;
+  IVF_HIP(prof_mark(idx, s, IVF_STAGE_COARSE));
   if (o.coarse == IVF_COARSE_EXACT) {
     IVF_HIP(launch_coarse_exact(t, Q, nq, w.scores, s));
+    IVF_HIP(prof_mark(idx, s, IVF_STAGE_SELECT));
     IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, 1, false, w, s));
   } else {
     IVF_HIP(launch_coarse_mfma(t, Q, nq, o.coarse, w, s));
+    IVF_HIP(prof_mark(idx, s, IVF_STAGE_SELECT));
     IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, o.widen, true, w, s));
   }
   return IVF_OK;
@@ -359,6 +448,7 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
   if (!queries || !nprobe || !out_ids || !out_dist)
     return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(prof_begin(idx));
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
   st = run_coarse(idx, queries, nq, nprobe, max_nprobe, o, w, s);
   if (st != IVF_OK) return st;
@@ -380,6 +470,7 @@ ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries, in
   if (!queries || !probes || !nprobe || !out_ids || !out_dist)
     return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(prof_begin(idx));
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
   IVF_HIP(launch_copy_probes(probes, nprobe, nq, max_nprobe, idx->t.L, w, s));
   return run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);

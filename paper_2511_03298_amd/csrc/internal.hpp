@@ -45,10 +45,13 @@ struct Tables {
 
 }  // namespace ivf
 
+struct ivf_profile;  // per-stage event ring, see abi.cpp
+
 struct ivf_index {
   ivf::Tables t;
   ivf_table_layout layout;
   void* table_mem;
+  ivf_profile* prof;
 };
 
 namespace ivf {

@@ -77,7 +77,7 @@ def test_bad_offsets_rejected():
     offs = np.array([0, 10, 5, 1000] + [1000] * 5, dtype=np.int64)
     desc, _ = _desc(ivf, offsets=offs)
     assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
-    offs = np.linspace(0, 999, 9).astype(np.int64)
+    offs = np.linspace(0, 1001, 9).astype(np.int64)
     desc, _ = _desc(ivf, offsets=offs)
     assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
 
