@@ -103,8 +103,11 @@ typedef struct {
   int32_t widen;     /* >= 1; MFMA coarse forms keep widen*nprobe lists before
                         the canonical re-score (ignored by IVF_COARSE_EXACT)    */
   int32_t form;      /* ivf_form                                                */
-  int32_t use_graph; /* BATCHED only: 1 = capture the search into a hipGraph on
-                        first use for this (nq, k, rerank, opts) and replay it   */
+  int32_t use_graph; /* 1 = capture the whole search into a hipGraph on first
+                        use with these exact arguments (sizes, options and
+                        every pointer) and replay it afterwards; needs a
+                        non-default stream. Up to 8 graphs are cached per
+                        index; per-stage profiling does not see replays.     */
   int32_t chunk;     /* BATCHED work-item size in 64-point blocks; 0 = auto      */
   int32_t reserved;
 } ivf_search_opts;
@@ -164,6 +167,14 @@ ivf_status ivf_debug_probes(const ivf_index* idx, const float* queries,
                             void* workspace, size_t workspace_bytes,
                             int32_t* out_probes, void* stream);
 
+/* The approximate coarse score matrix of an MFMA form (opts->coarse != EXACT):
+ * out_scores [nq,L] FP32, |c_l|^2 - 2<q,c_l> (L2) or -<q,c_l> (IP) computed
+ * from the operands in that precision with FP32 accumulation. */
+ivf_status ivf_debug_coarse_scores(const ivf_index* idx, const float* queries,
+                                   int32_t nq, const ivf_search_opts* opts,
+                                   void* workspace, size_t workspace_bytes,
+                                   float* out_scores, void* stream);
+
 /* Step 2 only, for every (q, p < nprobe[q]) of caller-given probes:
  *   out_lut   [nq,max_nprobe,m,16] uint8 quantised table,
  *   out_lo    [nq,max_nprobe,m] FP32 per-subspace offsets,
@@ -194,7 +205,7 @@ ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries,
  * block_offsets: int32 [L+1] first block of each list. */
 typedef struct {
   size_t codes, slot_ids, block_offsets, list_len, centroids, probe_centroids,
-      codebooks, probe_norms, probe_bf16, probe_fp8, probe_fp8_scale, total;
+      codebooks, probe_norms, probe_f32, probe_bf16, probe_fp8, probe_fp8_scale, total;
   int32_t words_per_point, m_padded, blocks, L_padded, d_padded, reserved;
 } ivf_table_layout;
 

@@ -26,7 +26,7 @@ EXPORTED = [
     "ivf_default_opts", "ivf_tables_bytes", "ivf_build_tables", "ivf_search_workspace_bytes",
     "ivf_search", "ivf_search_with_probes", "ivf_debug_probes", "ivf_debug_luts",
     "ivf_debug_candidates", "ivf_get_table_layout", "ivf_get_device_error", "ivf_destroy",
-    "ivf_last_error", "ivf_profile_enable", "ivf_profile_read",
+    "ivf_last_error", "ivf_profile_enable", "ivf_profile_read", "ivf_debug_coarse_scores",
 ]
 STAGES = ("coarse", "select", "scan", "rerank")
 
@@ -55,7 +55,8 @@ class SearchOpts(ctypes.Structure):
 class TableLayout(ctypes.Structure):
     _fields_ = [(name, ctypes.c_size_t) for name in (
         "codes", "slot_ids", "block_offsets", "list_len", "centroids", "probe_centroids",
-        "codebooks", "probe_norms", "probe_bf16", "probe_fp8", "probe_fp8_scale", "total")] + \
+        "codebooks", "probe_norms", "probe_f32", "probe_bf16", "probe_fp8", "probe_fp8_scale",
+        "total")] + \
         [(name, ctypes.c_int32) for name in (
             "words_per_point", "m_padded", "blocks", "L_padded", "d_padded", "reserved")]
 
@@ -74,6 +75,7 @@ def _declare(lib):
         "ivf_search_with_probes": (I32, [P, P, I32, P, P, I32, I32, I32, P, P, SZ, P, P, P]),
         "ivf_debug_probes": (I32, [P, P, I32, P, I32, P, P, SZ, P, P]),
         "ivf_debug_luts": (I32, [P, P, I32, P, P, I32, P, P, P, P, P]),
+        "ivf_debug_coarse_scores": (I32, [P, P, I32, P, P, SZ, P, P]),
         "ivf_debug_candidates": (I32, [P, P, I32, P, P, I32, I32, P, P, SZ, P, P]),
         "ivf_get_table_layout": (I32, [P, P]),
         "ivf_get_device_error": (I32, [P, P, P]),
@@ -279,6 +281,17 @@ class GpuIndex:
         check(lib().ivf_debug_probes(self._h, _ptr(q), nq, _ptr(npb), max_nprobe,
                                      ctypes.byref(opts), ws.data_ptr(), ws.numel(), _ptr(out),
                                      _stream()))
+        return out
+
+    def debug_coarse_scores(self, queries, coarse: str):
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        opts = make_opts(coarse=coarse)
+        ws = self.workspace(nq, 1, 1, 1, opts)
+        out = torch.empty((nq, self.L), dtype=torch.float32, device=self.device)
+        check(lib().ivf_debug_coarse_scores(self._h, _ptr(q), nq, ctypes.byref(opts),
+                                            ws.data_ptr(), ws.numel(), _ptr(out), _stream()))
         return out
 
     def debug_luts(self, queries, probes, nprobe):

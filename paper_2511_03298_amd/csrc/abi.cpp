@@ -22,6 +22,23 @@ struct ivf_profile {
   int cur = -1;
 };
 
+// Captured searches: one executable graph per set of launch arguments (the
+// graph embeds every pointer and size), most recent first, at most 8.
+struct ivf_graph_cache {
+  struct Entry {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Entry> entries;
+  ~ivf_graph_cache() {
+    for (auto& e : entries) {
+      if (e.exec) (void)hipGraphExecDestroy(e.exec);
+      if (e.graph) (void)hipGraphDestroy(e.graph);
+    }
+  }
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -90,6 +107,7 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
   lay->probe_centroids = take((size_t)d->L * d->d * 4);
   lay->codebooks = take((size_t)lay->m_padded * KSUB * dsub * 4);
   lay->probe_norms = take((size_t)lay->L_padded * 4);
+  lay->probe_f32 = take((size_t)lay->L_padded * lay->d_padded * 4);
   lay->probe_bf16 = take((size_t)lay->L_padded * lay->d_padded * 2);
   lay->probe_fp8 = take((size_t)lay->L_padded * lay->d_padded);
   lay->probe_fp8_scale = take((size_t)lay->L_padded * 4);
@@ -127,8 +145,6 @@ ivf_status check_opts(const ivf_search_opts& o) {
   if (o.use_graph != 0 && o.use_graph != 1)
     return fail(IVF_ERR_INVALID_ARG, "opts.use_graph must be 0 or 1");
   if (o.chunk < 0) return fail(IVF_ERR_INVALID_ARG, "opts.chunk must be >= 0");
-  if (o.coarse != IVF_COARSE_EXACT || o.form != IVF_FORM_PLAIN)
-    return fail(IVF_ERR_UNSUPPORTED, "only the exact coarse / plain form is built");
   return IVF_OK;
 }
 
@@ -141,6 +157,12 @@ ivf_status check_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, in
   if (rerank < 1 || rerank > MAX_RERANK)
     return fail(IVF_ERR_INVALID_ARG, "rerank must be in [1, 2048]");
   if (k < 1 || k > rerank) return fail(IVF_ERR_INVALID_ARG, "k must be in [1, rerank]");
+  return IVF_OK;
+}
+
+ivf_status check_form(const ivf_index* idx, const ivf_search_opts& o) {
+  if (o.form == IVF_FORM_BATCHED && idx->t.m > 192)
+    return fail(IVF_ERR_UNSUPPORTED, "the batched form supports m <= 192");
   return IVF_OK;
 }
 
@@ -168,13 +190,22 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   w.cand = (uint64_t*)take(nqs * rerank * 8);
   if (o.coarse != IVF_COARSE_EXACT) {
     const size_t nq_pad = (size_t)round_up_i((int64_t)nqs, TILE_L);
-    w.q_lowp = (uint16_t*)take(nq_pad * t.d_pad * 2);
+    w.q_lowp = (void*)take(nq_pad * t.d_pad * 4);
     w.q_scale = (float*)take(nq_pad * 4);
   }
   if (o.form == IVF_FORM_BATCHED) {
-    w.cand_count = (int32_t*)take(nqs * 4);
-    w.queue = (uint32_t*)take(64);
+    w.spill_cap = batched_spill_cap(rerank);
+    w.p1 = (int32_t*)take(nqs * 4);
     w.thr = (uint64_t*)take(nqs * 8);
+    w.list_cnt = (int32_t*)take((size_t)t.L * 4);
+    w.list_cursor = (int32_t*)take((size_t)t.L * 4);
+    w.list_start = (int32_t*)take((size_t)(t.L + 1) * 4);
+    w.item_start = (int32_t*)take((size_t)(t.L + 1) * 4);
+    w.pairs = (int32_t*)take(nqs * max_nprobe * 8);
+    w.queue = (uint32_t*)take(64);
+    w.spill_cnt = (int32_t*)take(nqs * 4);
+    w.spill = (uint64_t*)take(nqs * w.spill_cap * 8);
+    w.redo = (int32_t*)take(nqs * 4);
   }
   w.total = off;
   return w;
@@ -246,6 +277,7 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
   t.cp = (const float*)(base + lay.probe_centroids);
   t.codebooks = (const float*)(base + lay.codebooks);
   t.cp_norm2 = (const float*)(base + lay.probe_norms);
+  t.cp_f32 = (const float*)(base + lay.probe_f32);
   t.cp_bf16 = (const uint16_t*)(base + lay.probe_bf16);
   t.cp_fp8 = (const uint8_t*)(base + lay.probe_fp8);
   t.cp_fp8_scale = (const float*)(base + lay.probe_fp8_scale);
@@ -280,6 +312,7 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
   idx->layout = lay;
   idx->table_mem = table_mem;
   idx->prof = nullptr;
+  idx->graphs = nullptr;
   *out = idx;
   return IVF_OK;
 }
@@ -292,6 +325,7 @@ ivf_status ivf_get_table_layout(const ivf_index* idx, ivf_table_layout* out) {
 
 void ivf_destroy(ivf_index* idx) {
   if (!idx) return;
+  delete idx->graphs;
   if (idx->prof) {
     for (auto& row : idx->prof->ev)
       for (auto& e : row)
@@ -388,6 +422,8 @@ ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, in
   if (opts) *o = *opts;
   st = check_opts(*o);
   if (st != IVF_OK) return st;
+  st = check_form(idx, *o);
+  if (st != IVF_OK) return st;
   Workspace need = plan_workspace(idx->t, nq, max_nprobe, k, rerank, *o, nullptr);
   if (nq > 0 && !workspace) return fail(IVF_ERR_INVALID_ARG, "workspace is NULL");
   if ((uintptr_t)workspace % ALIGN) return fail(IVF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -448,6 +484,55 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
   if (!queries || !nprobe || !out_ids || !out_dist)
     return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
+  if (o.use_graph) {
+    if (!s) return fail(IVF_ERR_INVALID_ARG, "graph capture needs a non-default stream");
+    std::vector<uint64_t> key = {(uint64_t)nq, (uint64_t)max_nprobe, (uint64_t)k,
+                                 (uint64_t)rerank, (uint64_t)o.coarse, (uint64_t)o.widen,
+                                 (uint64_t)o.form, (uint64_t)o.chunk, (uint64_t)(uintptr_t)queries,
+                                 (uint64_t)(uintptr_t)nprobe, (uint64_t)(uintptr_t)workspace,
+                                 (uint64_t)(uintptr_t)out_ids, (uint64_t)(uintptr_t)out_dist};
+    ivf_index* mi = const_cast<ivf_index*>(idx);
+    if (!mi->graphs) {
+      mi->graphs = new (std::nothrow) ivf_graph_cache;
+      if (!mi->graphs) return fail(IVF_ERR_INTERNAL, "out of host memory");
+    }
+    auto& ents = mi->graphs->entries;
+    for (size_t i = 0; i < ents.size(); ++i) {
+      if (ents[i].key == key) {
+        IVF_HIP(hipGraphLaunch(ents[i].exec, s));
+        return IVF_OK;
+      }
+    }
+    ivf_graph_cache::Entry e;
+    e.key = key;
+    IVF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ivf_status cst = IVF_OK;
+    if (launch_fill_u32((uint32_t*)w.err, 0u, 4, s) != hipSuccess) cst = IVF_ERR_DEVICE;
+    if (cst == IVF_OK) cst = run_coarse(idx, queries, nq, nprobe, max_nprobe, o, w, s);
+    if (cst == IVF_OK)
+      cst = run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(s, &g);
+    if (cst != IVF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return cst;
+    }
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+    e.graph = g;
+    hipError_t ie = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(ie, "hipGraphInstantiate");
+    }
+    if (ents.size() >= 8) {
+      (void)hipGraphExecDestroy(ents.back().exec);
+      (void)hipGraphDestroy(ents.back().graph);
+      ents.pop_back();
+    }
+    ents.insert(ents.begin(), e);
+    IVF_HIP(hipGraphLaunch(ents.front().exec, s));
+    return IVF_OK;
+  }
   IVF_HIP(prof_begin(idx));
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
   st = run_coarse(idx, queries, nq, nprobe, max_nprobe, o, w, s);
@@ -492,6 +577,22 @@ ivf_status ivf_debug_probes(const ivf_index* idx, const float* queries, int32_t 
   if (st != IVF_OK) return st;
   IVF_HIP(hipMemcpyAsync(out_probes, w.probes, (size_t)nq * max_nprobe * 4,
                          hipMemcpyDeviceToDevice, s));
+  return IVF_OK;
+}
+
+ivf_status ivf_debug_coarse_scores(const ivf_index* idx, const float* queries, int32_t nq,
+                                   const ivf_search_opts* opts, void* workspace,
+                                   size_t workspace_bytes, float* out_scores, void* stream) {
+  ivf_search_opts o;
+  Workspace w;
+  ivf_status st = begin_search(idx, nq, 1, 1, 1, opts, workspace, workspace_bytes, &o, &w);
+  if (st != IVF_OK) return st;
+  if (o.coarse == IVF_COARSE_EXACT) return fail(IVF_ERR_INVALID_ARG, "opts.coarse must be an MFMA form");
+  if (nq == 0) return IVF_OK;
+  if (!queries || !out_scores) return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_coarse_mfma(idx->t, queries, nq, o.coarse, w, s));
+  IVF_HIP(hipMemcpyAsync(out_scores, w.scores, (size_t)nq * idx->t.L * 4, hipMemcpyDeviceToDevice, s));
   return IVF_OK;
 }
 

@@ -1,0 +1,396 @@
+// Batched form of steps 2-4: list-major, persistent, work-queue scheduled.
+//
+// The candidate pool of a query is the exact set of its R smallest keys
+// (ord(a) << 32 | id) over every point of its probed lists, as in the plain
+// form; only the schedule differs:
+//   phase 1  per query, the plain scan of its first probed lists until at
+//            least R points are seen: pool P1 and threshold thr = R-th key
+//            (no key above thr can enter the final pool);
+//   phase 2  the remaining (query, list) pairs are grouped by list into
+//            work items of up to 16 queries; persistent workgroups pull items
+//            from an atomic counter, build the 16 queries' tables, stream the
+//            list's code blocks once, and append every key <= thr of its
+//            query to a per-query survivor buffer;
+//   merge    per query, the R smallest keys of P1 and its survivors. A query
+//            whose buffer overflowed is recomputed by the plain scan.
+//
+// Table layout for the scan: entry (query g, subspace j, code c) is a u16 at
+// ((j*2 + g/8)*16 + c)*8 + g%8. The 16 rows of one (j, half) span 256 bytes,
+// every LDS bank once, so lanes reading any codes of the same subspace never
+// conflict; one 16-byte read returns 8 queries' entries, summed with packed
+// 16-bit adds (sums are at most 255*256 < 2^16).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ivf {
+
+constexpr int BG = 16;  // queries per work item
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------------------
+// Work list: (query, probe slot) pairs of phase 2 grouped by list.
+// ---------------------------------------------------------------------------
+
+__global__ void pairs_count_kernel(int32_t nq, int32_t max_nprobe,
+                                   const int32_t* __restrict__ probes,
+                                   const int32_t* __restrict__ nprobe_eff,
+                                   const int32_t* __restrict__ p1, int32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nq * max_nprobe) return;
+  const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
+  if (p < p1[q] || p >= nprobe_eff[q]) return;
+  atomicAdd(&cnt[probes[i]], 1);
+}
+
+// Exclusive scans of per-list pair counts and item counts (one workgroup).
+__global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, const int32_t* __restrict__ cnt,
+                                                         int32_t* __restrict__ list_start,
+                                                         int32_t* __restrict__ item_start,
+                                                         int32_t* __restrict__ cursor) {
+  __shared__ int32_t sp[1024], si[1024];
+  const int tid = threadIdx.x;
+  const int per = (L + 1023) / 1024;
+  const int b = tid * per, e = min(L, b + per);
+  int32_t ps = 0, is = 0;
+  for (int l = b; l < e; ++l) {
+    ps += cnt[l];
+    is += (cnt[l] + BG - 1) / BG;
+  }
+  sp[tid] = ps;
+  si[tid] = is;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int32_t a = tid >= off ? sp[tid - off] : 0, c = tid >= off ? si[tid - off] : 0;
+    __syncthreads();
+    sp[tid] += a;
+    si[tid] += c;
+    __syncthreads();
+  }
+  int32_t pacc = sp[tid] - ps, iacc = si[tid] - is;
+  for (int l = b; l < e; ++l) {
+    list_start[l] = pacc;
+    item_start[l] = iacc;
+    cursor[l] = 0;
+    pacc += cnt[l];
+    iacc += (cnt[l] + BG - 1) / BG;
+  }
+  if (tid == 1023) {
+    list_start[L] = sp[1023];
+    item_start[L] = si[1023];
+  }
+}
+
+__global__ void pairs_fill_kernel(int32_t nq, int32_t max_nprobe,
+                                  const int32_t* __restrict__ probes,
+                                  const int32_t* __restrict__ nprobe_eff,
+                                  const int32_t* __restrict__ p1,
+                                  const int32_t* __restrict__ list_start,
+                                  int32_t* __restrict__ cursor, int32_t* __restrict__ pairs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nq * max_nprobe) return;
+  const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
+  if (p < p1[q] || p >= nprobe_eff[q]) return;
+  const int l = probes[i];
+  const int pos = list_start[l] + atomicAdd(&cursor[l], 1);
+  pairs[2 * pos] = q;
+  pairs[2 * pos + 1] = p;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level table build of one (query, list), the canonical arithmetic of the
+// plain form. Lane ln covers entries e = ln + 64 r (subspace j = 4r + ln/16,
+// code ln%16). Pass 1 finds the per-subspace minima (kept in LDS) and the
+// largest range; pass 2 recomputes the same float entries and writes the
+// quantised u16 table into the interleaved layout.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float lut_entry(const Tables& t, const float* __restrict__ q, int l,
+                                           int j, int code) {
+  const int ds = t.dsub;
+  const float* cb = t.codebooks + ((size_t)j * KSUB + code) * ds;
+  float acc = 0.0f;
+  if (t.metric == IVF_METRIC_L2) {
+    const float* c = t.cm + (size_t)l * t.d + j * ds;
+    for (int u = 0; u < ds; ++u) {
+      float rr = q[j * ds + u] - c[u];
+      float df = rr - cb[u];
+      acc = acc + df * df;
+    }
+    return acc;
+  }
+  for (int u = 0; u < ds; ++u) acc = acc + q[j * ds + u] * cb[u];
+  return plus_zero(-acc);
+}
+
+template <int W>
+__device__ __forceinline__ void wave_build_lut(const Tables& t, const float* __restrict__ q, int l,
+                                               float bias, int g, uint16_t* lut16, float* lo_s,
+                                               float* outB, float* outDelta) {
+  constexpr int MP = W * 8;  // padded subspaces
+  const int ln = lane_id();
+  const int code = ln & 15;
+  const int nr = (t.m + 3) / 4;
+  float mx = 0.0f;
+#pragma unroll 1
+  for (int r = 0; r < nr; ++r) {
+    const int j = 4 * r + (ln >> 4);
+    const float T = j < t.m ? lut_entry(t, q, l, j, code) : 0.0f;
+    float v = T;
+    for (int s = 1; s < 16; s <<= 1) v = fminf(v, __shfl_xor(v, s));
+    if (code == 0 && j < t.m) lo_s[j] = v;
+    mx = fmaxf(mx, T - v);
+  }
+  for (int s = 1; s < IVF_WAVE; s <<= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
+  const float rng = mx;
+  const bool live = rng > 0.0f;
+  const float sc = live ? 255.0f / rng : 0.0f;
+#pragma unroll 1
+  for (int r = 0; r < MP / 4; ++r) {
+    const int j = 4 * r + (ln >> 4);
+    uint16_t v = 0;
+    if (live && j < t.m)
+      v = (uint16_t)fminf(rintf((lut_entry(t, q, l, j, code) - lo_s[j]) * sc), 255.0f);
+    lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = v;
+  }
+  const float ls = wave_pairwise_sum(lo_s, t.m);
+  if (ln == 0) {
+    *outB = ls + bias;
+    *outDelta = live ? rng / 255.0f : 0.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Phase 2: persistent list-major scan.
+// ---------------------------------------------------------------------------
+
+template <int W>
+struct BatchShared {
+  uint16_t lut16[W * 8 * 2 * 16 * 8];
+  float lo[IVF_NWAVES][W * 8];
+  float B[BG], delta[BG];
+  uint64_t thr[BG];
+  int32_t qid[BG];
+  int32_t item, l, nqi;
+};
+
+template <int W>
+__global__ void __launch_bounds__(256) batched_scan_kernel(
+    Tables t, const float* __restrict__ Q, int32_t max_nprobe, const float* __restrict__ bias,
+    const uint64_t* __restrict__ thr, const int32_t* __restrict__ list_start,
+    const int32_t* __restrict__ item_start, const int32_t* __restrict__ pairs,
+    uint32_t* __restrict__ queue, int32_t* __restrict__ spill_cnt, uint64_t* __restrict__ spill,
+    int32_t cap) {
+  __shared__ BatchShared<W> sh;
+  const int tid = threadIdx.x, wave = tid / IVF_WAVE, ln = lane_id();
+  const int n_items = item_start[t.L];
+  for (;;) {
+    if (tid == 0) sh.item = (int32_t)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int item = sh.item;
+    if (item >= n_items) break;  // uniform: every wave leaves together
+    if (tid == 0) {
+      int lo = 0, hi = t.L;  // item_start[lo] <= item < item_start[hi]
+      while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (item_start[mid] <= item) lo = mid; else hi = mid;
+      }
+      const int first = (item - item_start[lo]) * BG;
+      const int npairs = list_start[lo + 1] - list_start[lo];
+      sh.l = lo;
+      sh.nqi = min(BG, npairs - first);
+      for (int i = 0; i < BG; ++i) {
+        const int pi = list_start[lo] + first + i;
+        const bool v = i < sh.nqi;
+        const int q = v ? pairs[2 * pi] : -1;
+        sh.qid[i] = q;
+        sh.thr[i] = v ? thr[q] : 0ull;
+      }
+    }
+    __syncthreads();
+    const int l = sh.l, nqi = sh.nqi;
+    // Tables: wave w builds queries w, w+4, w+8, w+12; absent queries get an
+    // all-zero table (their keys are never kept: threshold 0).
+#pragma unroll 1
+    for (int g = wave; g < BG; g += IVF_NWAVES) {
+      if (g < nqi) {
+        const int pi = list_start[l] + (item - item_start[l]) * BG + g;
+        const int q = pairs[2 * pi], p = pairs[2 * pi + 1];
+        const float b = t.metric == IVF_METRIC_IP ? bias[(size_t)q * max_nprobe + p] : 0.0f;
+        wave_build_lut<W>(t, Q + (size_t)q * t.d, l, b, g, sh.lut16, sh.lo[wave], &sh.B[g],
+                          &sh.delta[g]);
+      } else {
+        for (int e = ln; e < W * 8 * 16; e += IVF_WAVE)
+          sh.lut16[(((e >> 4) * 2 + (g >> 3)) * 16 + (e & 15)) * 8 + (g & 7)] = 0;
+        if (ln == 0) {
+          sh.B[g] = 0.0f;
+          sh.delta[g] = 0.0f;
+        }
+      }
+    }
+    __syncthreads();
+    const int n_l = t.list_len[l];
+    const int blk0 = t.block_off[l];
+    const int nblk = (n_l + BLOCK_PTS - 1) / BLOCK_PTS;
+#pragma unroll 1
+    for (int bi = wave; bi < nblk; bi += IVF_NWAVES) {
+      const int blk = blk0 + bi;
+      const uint32_t* cw = t.codes + (size_t)blk * W * BLOCK_PTS + ln;
+      u16x2 acc[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] = u16x2{0, 0};
+      const unsigned char* lutb = reinterpret_cast<const unsigned char*>(sh.lut16);
+      uint32_t x = cw[0];
+#pragma unroll 1
+      for (int w = 0; w < W; ++w) {
+        const uint32_t xn = w + 1 < W ? cw[(w + 1) * BLOCK_PTS] : 0u;
+        const unsigned char* base = lutb + w * 8 * 512;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const unsigned char* row = base + s * 512 + ((x >> (4 * s)) & 15u) * 16u;
+          const uint4 lo4 = *reinterpret_cast<const uint4*>(row);
+          const uint4 hi4 = *reinterpret_cast<const uint4*>(row + 256);
+          acc[0] += __builtin_bit_cast(u16x2, lo4.x);
+          acc[1] += __builtin_bit_cast(u16x2, lo4.y);
+          acc[2] += __builtin_bit_cast(u16x2, lo4.z);
+          acc[3] += __builtin_bit_cast(u16x2, lo4.w);
+          acc[4] += __builtin_bit_cast(u16x2, hi4.x);
+          acc[5] += __builtin_bit_cast(u16x2, hi4.y);
+          acc[6] += __builtin_bit_cast(u16x2, hi4.z);
+          acc[7] += __builtin_bit_cast(u16x2, hi4.w);
+        }
+        x = xn;
+      }
+      const bool valid = bi * BLOCK_PTS + ln < n_l;
+      const uint32_t id = valid ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
+#pragma unroll
+      for (int g = 0; g < BG; ++g) {
+        if (g >= nqi) continue;  // uniform
+        const uint32_t S = acc[g >> 1][g & 1];
+        const float a = plus_zero(sh.B[g] + sh.delta[g] * (float)S);
+        const uint64_t key = make_key(a, id);
+        const bool pass = valid && key <= sh.thr[g];
+        const uint64_t mask = __ballot(pass);
+        if (mask) {
+          const int q = sh.qid[g];
+          uint32_t base = 0;
+          if (ln == 0) base = (uint32_t)atomicAdd(&spill_cnt[q], (int)__popcll(mask));
+          base = __shfl(base, 0);
+          const uint32_t pos = base + lanes_below(mask);
+          if (pass && pos < (uint32_t)cap) spill[(size_t)q * cap + pos] = key;
+        }
+      }
+    }
+    __syncthreads();  // the tables are rebuilt for the next item
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Merge: pool of phase 1 plus survivors -> the R smallest keys.
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
+                                                    const int32_t* __restrict__ nprobe_eff,
+                                                    const int32_t* __restrict__ spill_cnt,
+                                                    const uint64_t* __restrict__ spill,
+                                                    uint64_t* __restrict__ cand,
+                                                    int32_t* __restrict__ redo) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);  // [pow2(R + cap)]
+  __shared__ SelectScratch sc;
+  __shared__ uint32_t cnt;
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int ns = spill_cnt[q];
+  if (tid == 0) redo[q] = 0;
+  if (nprobe_eff[q] < 0 || ns == 0) return;
+  if (ns > cap) {
+    if (tid == 0) redo[q] = 1;
+    return;
+  }
+  uint32_t n = 0;
+  if (tid == 0) cnt = 0;
+  __syncthreads();
+  for (int i = tid; i < R; i += blockDim.x) {
+    const uint64_t k = cand[(size_t)q * R + i];
+    wave_append(k != KEY_NONE, k, keys, &cnt);
+  }
+  __syncthreads();
+  n = cnt;
+  for (int i = tid; i < ns; i += blockDim.x) keys[n + i] = spill[(size_t)q * cap + i];
+  __syncthreads();
+  n += (uint32_t)ns;
+  if (n > (uint32_t)R) {
+    KeyUnion u{keys, n, nullptr, 0};
+    n = block_compact_le(keys, n, block_kth(u, (uint32_t)R, &sc), &cnt);
+    if (n > (uint32_t)R) n = (uint32_t)R;
+  }
+  const uint32_t n2 = pow2_ceil(n > 0 ? n : 1);
+  for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
+  block_bitonic_sort(keys, n2);
+  for (int i = tid; i < R; i += blockDim.x)
+    cand[(size_t)q * R + i] = (uint32_t)i < n ? keys[i] : KEY_NONE;
+}
+
+// ---------------------------------------------------------------------------
+
+hipError_t launch_scan_plain_ex(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                                int32_t rerank, const Workspace& w, int32_t* p1_out,
+                                uint64_t* thr_out, const int32_t* only, hipStream_t s);
+
+int32_t batched_spill_cap(int32_t R) {
+  int32_t c = 4 * R;
+  if (c < 1024) c = 1024;
+  if (c > 8192) c = 8192;
+  return c;
+}
+
+template <int W>
+static hipError_t launch_batched_w(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                                   int32_t R, const Workspace& w, hipStream_t s) {
+  const int64_t np_total = (int64_t)nq * max_nprobe;
+  const unsigned g1 = (unsigned)((np_total + 255) / 256);
+  hipError_t e;
+  // Phase 1: first lists per query -> pool, threshold, first probe of phase 2.
+  if ((e = launch_fill_u32((uint32_t*)w.list_cnt, 0u, (size_t)t.L, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32((uint32_t*)w.spill_cnt, 0u, (size_t)nq, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(w.queue, 0u, 4, s)) != hipSuccess) return e;
+  if ((e = launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, w.p1, w.thr, nullptr, s)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(pairs_count_kernel, dim3(g1), dim3(256), 0, s, nq, max_nprobe, w.probes,
+                     w.nprobe_eff, w.p1, w.list_cnt);
+  hipLaunchKernelGGL(pairs_scan_kernel, dim3(1), dim3(1024), 0, s, t.L, w.list_cnt, w.list_start,
+                     w.item_start, w.list_cursor);
+  hipLaunchKernelGGL(pairs_fill_kernel, dim3(g1), dim3(256), 0, s, nq, max_nprobe, w.probes,
+                     w.nprobe_eff, w.p1, w.list_start, w.list_cursor, w.pairs);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int per_cu = (int)(sizeof(BatchShared<W>) <= 20 * 1024 ? 6 : (sizeof(BatchShared<W>) <= 36 * 1024 ? 4 : 2));
+  hipLaunchKernelGGL(batched_scan_kernel<W>, dim3(cus * per_cu), dim3(256), 0, s, t, Q, max_nprobe,
+                     w.bias, w.thr, w.list_start, w.item_start, w.pairs, w.queue, w.spill_cnt,
+                     w.spill, w.spill_cap);
+  const size_t lds = (size_t)pow2_ceil((uint32_t)(R + w.spill_cap)) * 8;
+  hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, w.spill_cap, w.nprobe_eff,
+                     w.spill_cnt, w.spill, w.cand, w.redo);
+  // Queries whose survivors overflowed: recompute with the plain scan.
+  if ((e = launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, nullptr, nullptr, w.redo, s)) !=
+      hipSuccess)
+    return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_batched(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                               int32_t rerank, int32_t chunk, const Workspace& w, hipStream_t s) {
+  (void)chunk;
+  if (nq == 0) return hipSuccess;
+  switch (t.words) {
+#define X(N) \
+  case N: return launch_batched_w<N>(t, Q, nq, max_nprobe, rerank, w, s);
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+    X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
+#undef X
+    default: return hipErrorNotSupported;
+  }
+}
+
+}  // namespace ivf

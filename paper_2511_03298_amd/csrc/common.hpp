@@ -173,10 +173,64 @@ __device__ inline uint32_t block_compact_le(uint64_t* keys, uint32_t n, uint64_t
   return c;
 }
 
+// Round a float to bfloat16, nearest even (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Encode a float as OCP FP8 E4M3 (3 mantissa bits, exponent bias 7, largest
+// finite 448, subnormal spacing 2^-9), round to nearest even, saturating;
+// values that round to zero encode as +0 (0x00), never as 0x80.
+__device__ __forceinline__ uint8_t e4m3_rne(float x) {
+  const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fminf(fabsf(x), 448.0f);
+  if (!(a > 0.0f)) return 0;
+  int e = 0;
+  frexpf(a, &e);  // a = f * 2^e, f in [0.5, 1)
+  int eu = e - 1;
+  if (eu < -6) eu = -6;
+  const float quantum = ldexpf(1.0f, eu - 3);
+  const float qv = fminf(rintf(a / quantum) * quantum, 448.0f);
+  if (qv == 0.0f) return 0;
+  int e2 = 0;
+  const float f2 = frexpf(qv, &e2);
+  const int eu2 = e2 - 1;
+  const uint32_t bits =
+      eu2 < -6 ? (uint32_t)rintf(qv * 512.0f)
+               : (((uint32_t)(eu2 + 7) << 3) | (uint32_t)rintf((f2 * 2.0f - 1.0f) * 8.0f));
+  return (uint8_t)(sign | bits);
+}
+
 __host__ __device__ inline uint32_t pow2_ceil(uint32_t x) {
   uint32_t p = 1;
   while (p < x) p <<= 1;
   return p;
+}
+
+// Pairwise sum of v[0..m) padded with zeros to a power of two, by one wavefront
+// (adjacent pairs first, then pairs of pairs, ...).
+__device__ __forceinline__ float wave_pairwise_sum(const float* v, int m) {
+  const int lane = lane_id();
+  const int p2 = (int)pow2_ceil((uint32_t)m);
+  float x;
+  int width;
+  if (p2 <= IVF_WAVE) {
+    x = lane < m ? v[lane] : 0.0f;
+    width = p2;
+  } else {
+    const int per = p2 / IVF_WAVE;  // 2 or 4 consecutive elements per lane
+    float e[4];
+    for (int i = 0; i < 4; ++i) {
+      int idx = lane * per + i;
+      e[i] = (i < per && idx < m) ? v[idx] : 0.0f;
+    }
+    x = per == 2 ? e[0] + e[1] : (e[0] + e[1]) + (e[2] + e[3]);
+    width = IVF_WAVE;
+  }
+  for (int s = 1; s < width; s <<= 1) x = x + __shfl_xor(x, s);
+  return __shfl(x, 0);
 }
 
 }  // namespace ivf

@@ -38,6 +38,7 @@ struct Tables {
   const float* cp;              // [L][d]
   const float* codebooks;       // [m_pad][16][dsub]
   const float* cp_norm2;        // [L_pad]
+  const float* cp_f32;          // [L_pad][d_pad]
   const uint16_t* cp_bf16;      // [L_pad][d_pad]
   const uint8_t* cp_fp8;        // [L_pad][d_pad]
   const float* cp_fp8_scale;    // [L_pad]
@@ -45,13 +46,15 @@ struct Tables {
 
 }  // namespace ivf
 
-struct ivf_profile;  // per-stage event ring, see abi.cpp
+struct ivf_profile;      // per-stage event ring, see abi.cpp
+struct ivf_graph_cache;  // captured searches, see abi.cpp
 
 struct ivf_index {
   ivf::Tables t;
   ivf_table_layout layout;
   void* table_mem;
   ivf_profile* prof;
+  ivf_graph_cache* graphs;
 };
 
 namespace ivf {
@@ -64,16 +67,25 @@ struct Workspace {
   float* bias;          // [nq][max_nprobe] per-(q,list) constant (IP), else unused
   uint64_t* cand;       // [nq][rerank]
   int32_t* err;         // [4] device error word
-  int32_t* cand_count;  // [nq] batched: survivors per query
-  uint32_t* queue;      // [8] batched: work-queue counters
-  uint64_t* thr;        // [nq] batched: per-query threshold keys
-  int32_t* items;       // [max_items][2] batched: (query, probe slot | chunk)
-  uint64_t* spill;      // [nq][spill_cap] batched: survivors
-  uint16_t* q_lowp;     // [nq_pad][d_pad] queries converted for MFMA coarse
+  // batched form
+  int32_t* p1;          // [nq] first probe slot of phase 2
+  uint64_t* thr;        // [nq] phase-1 threshold keys
+  int32_t* list_cnt;    // [L] phase-2 pairs per list
+  int32_t* list_cursor; // [L]
+  int32_t* list_start;  // [L+1]
+  int32_t* item_start;  // [L+1]
+  int32_t* pairs;       // [nq*max_nprobe][2] (query, probe slot) grouped by list
+  uint32_t* queue;      // [4] work-queue counter
+  int32_t* spill_cnt;   // [nq] survivors per query
+  uint64_t* spill;      // [nq][spill_cap] survivors
+  int32_t* redo;        // [nq] 1 = survivors overflowed, recompute
+  void* q_lowp;         // [nq_pad][d_pad] queries converted for MFMA coarse
   float* q_scale;       // [nq_pad]
   size_t total;
-  int32_t spill_cap, max_items;
+  int32_t spill_cap;
 };
+
+int32_t batched_spill_cap(int32_t rerank);
 
 Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_t k,
                          int32_t rerank, const ivf_search_opts& o, char* base);

@@ -53,30 +53,6 @@ __device__ __forceinline__ void lut_float(const Tables& t, const float* qv, int 
   }
 }
 
-// Pairwise sum of v[0..m) padded with zeros to a power of two, by wave 0
-// (adjacent pairs first, then pairs of pairs, ...).
-__device__ __forceinline__ float wave_pairwise_sum(const float* v, int m) {
-  const int lane = lane_id();
-  const int p2 = (int)pow2_ceil((uint32_t)m);
-  float x;
-  int width;
-  if (p2 <= IVF_WAVE) {
-    x = lane < m ? v[lane] : 0.0f;
-    width = p2;
-  } else {
-    const int per = p2 / IVF_WAVE;  // 2 or 4 consecutive elements per lane
-    float e[4];
-    for (int i = 0; i < 4; ++i) {
-      int idx = lane * per + i;
-      e[i] = (i < per && idx < m) ? v[idx] : 0.0f;
-    }
-    x = per == 2 ? e[0] + e[1] : (e[0] + e[1]) + (e[2] + e[3]);
-    width = IVF_WAVE;
-  }
-  for (int s = 1; s < width; s <<= 1) x = x + __shfl_xor(x, s);
-  return __shfl(x, 0);
-}
-
 // Quantise Tf into lut8 (m_pad*16 bytes), lo[0..m), and publish delta and
 // the pairwise sum of lo in `st`. All threads; ends with a barrier.
 __device__ __forceinline__ void lut_quantize(const Tables& t, const float* Tf, float* lo,
@@ -165,7 +141,10 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
                                                          const int32_t* __restrict__ probes,
                                                          const int32_t* __restrict__ nprobe_eff,
                                                          const float* __restrict__ bias,
-                                                         uint64_t* __restrict__ cand) {
+                                                         uint64_t* __restrict__ cand,
+                                                         int32_t* __restrict__ p1_out,
+                                                         uint64_t* __restrict__ thr_out,
+                                                         const int32_t* __restrict__ only) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ ScanShared<W> sh;
   const int q = blockIdx.x;
@@ -174,6 +153,10 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
   uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);            // [R + cap]
   float* Tf = reinterpret_cast<float*>(keys + R + cap);          // [m_pad*16]
   float* qv = Tf + t.m_pad * KSUB;                               // [d]
+  // `only`: recompute just the flagged queries. `p1_out`: stop after the
+  // first lists holding at least R points, and publish where phase 2 starts
+  // and the R-th smallest key (the batched form's threshold).
+  if (only && only[q] == 0) return;
   const int np = nprobe_eff[q];
 
   for (int i = tid; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
@@ -188,7 +171,12 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
     __syncthreads();
     lut_quantize(t, Tf, sh.lo, sh.lut8, &sh.st);
   }
+  int seen = 0, p_end = np;
   for (int p = 0; p < np; ++p) {
+    if (p1_out && seen >= R) {
+      p_end = p;
+      break;
+    }
     const int l = probes[(size_t)q * max_nprobe + p];
     float b = 0.0f;
     if (!ip) {
@@ -201,6 +189,7 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
     const float B = sh.st.lo_sum + b;
     const float delta = sh.st.delta;
     const int n_l = t.list_len[l];
+    seen += n_l;
     const int blk0 = t.block_off[l];
     const int nblk = (n_l + BLOCK_PTS - 1) / BLOCK_PTS;
     for (int b0 = 0; b0 < nblk; b0 += IVF_NWAVES) {
@@ -231,6 +220,10 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
   block_bitonic_sort(keys, n2);
   for (int i = tid; i < R; i += blockDim.x)
     cand[(size_t)q * R + i] = (uint32_t)i < total ? keys[i] : KEY_NONE;
+  if (p1_out && tid == 0) {
+    p1_out[q] = np > 0 ? p_end : 0;
+    thr_out[q] = total >= (uint32_t)R ? keys[R - 1] : KEY_NONE;
+  }
 }
 
 // Candidate-buffer slack beyond R (keys), large enough that a round of one
@@ -245,11 +238,12 @@ inline int32_t scan_cap(int32_t R) {
 template <int W>
 static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t nq,
                                       int32_t max_nprobe, int32_t R, const Workspace& w,
+                                      int32_t* p1_out, uint64_t* thr_out, const int32_t* only,
                                       hipStream_t s) {
   const int32_t cap = scan_cap(R);
   size_t lds = (size_t)(R + cap) * 8 + (size_t)t.m_pad * KSUB * 4 + (size_t)t.d * 4;
   hipLaunchKernelGGL(scan_plain_kernel<W>, dim3(nq), dim3(256), lds, s, t, Q, nq, max_nprobe, R,
-                     cap, w.probes, w.nprobe_eff, w.bias, w.cand);
+                     cap, w.probes, w.nprobe_eff, w.bias, w.cand, p1_out, thr_out, only);
   return hipGetLastError();
 }
 
@@ -257,16 +251,23 @@ static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t n
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
   X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 
-hipError_t launch_scan_plain(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
-                             int32_t rerank, const Workspace& w, hipStream_t s) {
+hipError_t launch_scan_plain_ex(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                                int32_t rerank, const Workspace& w, int32_t* p1_out,
+                                uint64_t* thr_out, const int32_t* only, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   switch (t.words) {
 #define X(N) \
-  case N: return launch_scan_plain_w<N>(t, Q, nq, max_nprobe, rerank, w, s);
+  case N:    \
+    return launch_scan_plain_w<N>(t, Q, nq, max_nprobe, rerank, w, p1_out, thr_out, only, s);
     IVF_W_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_scan_plain(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                             int32_t rerank, const Workspace& w, hipStream_t s) {
+  return launch_scan_plain_ex(t, Q, nq, max_nprobe, rerank, w, nullptr, nullptr, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------

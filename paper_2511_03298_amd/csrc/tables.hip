@@ -51,41 +51,6 @@ hipError_t launch_pack(const Tables& t, const uint8_t* codes, const int64_t* lis
   return hipGetLastError();
 }
 
-// Round to nearest even bfloat16.
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-// OCP FP8 E4M3 (max finite 448, no infinities) with round to nearest even,
-// written from the format definition; |x| is pre-scaled into range.
-__device__ __forceinline__ uint8_t f32_to_e4m3(float x) {
-  uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
-  float a = fminf(fabsf(x), 448.0f);
-  if (!(a > 0.0f)) return (uint8_t)sign;
-  // Subnormal spacing 2^-9 below 2^-6; normals have 3 mantissa bits.
-  int e = 0;
-  frexpf(a, &e);            // a = f * 2^e, f in [0.5, 1)
-  int exp_unb = e - 1;      // a in [2^exp_unb, 2^(exp_unb+1))
-  if (exp_unb < -6) exp_unb = -6;
-  float quantum = ldexpf(1.0f, exp_unb - 3);
-  float qv = rintf(a / quantum) * quantum;  // a / quantum is exact (power of 2)
-  if (qv > 448.0f) qv = 448.0f;
-  if (qv == 0.0f) return (uint8_t)sign;
-  int e2 = 0;
-  float f2 = frexpf(qv, &e2);
-  int eu = e2 - 1;
-  uint32_t bits;
-  if (eu < -6) {  // subnormal: value = mant * 2^-9
-    bits = (uint32_t)rintf(qv * 512.0f);
-  } else {
-    uint32_t mant = (uint32_t)rintf((f2 * 2.0f - 1.0f) * 8.0f);
-    bits = ((uint32_t)(eu + 7) << 3) | mant;
-  }
-  return (uint8_t)(sign | bits);
-}
-
 // Low-precision copies of the probe centroids for the MFMA coarse scores:
 // squared norms, BF16 rows, FP8 rows with one scale per row; zero padded to
 // [L_pad][d_pad].
@@ -120,8 +85,9 @@ __global__ void __launch_bounds__(256) aux_kernel(Tables t) {
   }
   for (int c = threadIdx.x; c < t.d_pad; c += blockDim.x) {
     float v = (live && c < t.d) ? t.cp[(size_t)l * t.d + c] : 0.0f;
-    const_cast<uint16_t*>(t.cp_bf16)[(size_t)l * t.d_pad + c] = f32_to_bf16(v);
-    const_cast<uint8_t*>(t.cp_fp8)[(size_t)l * t.d_pad + c] = f32_to_e4m3(v / scale);
+    const_cast<float*>(t.cp_f32)[(size_t)l * t.d_pad + c] = v;
+    const_cast<uint16_t*>(t.cp_bf16)[(size_t)l * t.d_pad + c] = bf16_rne(v);
+    const_cast<uint8_t*>(t.cp_fp8)[(size_t)l * t.d_pad + c] = e4m3_rne(v / scale);
   }
 }
 

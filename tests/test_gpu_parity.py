@@ -223,3 +223,172 @@ def test_multiple_probed_lists_ragged_batch(name):
     ids, dist = g.search(Q[:nq], npb, cfg.k, cfg.R, max_nprobe=cfg.L)
     check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q[:nq], cfg.metric,
                 exact_ids=(cfg.dist == "int255"))
+
+
+# ---------------------------------------------------------------------------
+# MFMA coarse forms: approximate scores, widened pre-selection, canonical
+# re-score.
+# ---------------------------------------------------------------------------
+
+UNIT = {"f32": 2.0 ** -22, "bf16": 2.0 ** -7, "fp8": 2.0 ** -3}
+
+
+@pytest.mark.parametrize("coarse", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s"])
+def test_mfma_scores_within_operand_rounding(name, coarse):
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    S = g.debug_coarse_scores(Q, coarse).cpu().numpy().astype(np.float64)
+    cp = index["cp"].astype(np.float64)
+    q64 = Q.astype(np.float64)
+    dot = q64 @ cp.T
+    ref = (cp ** 2).sum(1)[None, :] - 2 * dot if cfg.metric == "l2" else -dot
+    mag = np.abs(q64) @ np.abs(cp).T
+    fac = 2.0 if cfg.metric == "l2" else 1.0
+    err = np.abs(S - ref)
+    # |c|^2 is exact FP32 (any order), so the error is the product's.
+    slack = 1e-5 * (np.abs(ref) + 1e-30) + cfg.d * 2.0 ** -23 * fac * mag
+    assert np.all(err <= fac * UNIT[coarse] * mag + slack)
+    # Low precision: typical error far below the worst case (catches a
+    # wrong operand scale or FP8 format, which shift every product).
+    if coarse != "f32":
+        assert np.median(err / (fac * mag + 1e-30)) <= UNIT[coarse] / 4
+
+
+def canonical_sorted(index, q, metric, lists):
+    s = oracle.coarse_scores(q, index["cp"], metric)
+    return s[np.asarray(lists, dtype=np.int64)]
+
+
+@pytest.mark.parametrize("coarse", ["f32", "bf16", "fp8"])
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c4s", "c5s"])
+def test_mfma_probe_sets(name, coarse):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    # Widening to every list: the canonical re-score decides alone -> exact.
+    full = g.debug_probes(Q, nprobe, opts=ivf.make_opts(coarse=coarse, widen=cfg.L)).cpu().numpy()
+    for qi, p in enumerate(res["probes"]):
+        assert np.array_equal(full[qi, :len(p)], p), qi
+    got = g.debug_probes(Q, nprobe, opts=ivf.make_opts(coarse=coarse, widen=2)).cpu().numpy()
+    differ = 0
+    for qi, p in enumerate(res["probes"]):
+        mine = got[qi, :len(p)]
+        if np.array_equal(mine, p):
+            continue
+        differ += 1
+        # Still a valid widened choice: distinct lists in canonical order,
+        # each rank no better than the true canonical top-nprobe.
+        assert len(set(mine.tolist())) == len(p)
+        sm = canonical_sorted(index, Q[qi], cfg.metric, mine)
+        so = canonical_sorted(index, Q[qi], cfg.metric, p)
+        assert np.all(np.diff(sm) >= 0) and np.all(sm >= so)
+    print(f"[{name}/{coarse}] probe sets differing from the canonical top-nprobe: "
+          f"{differ}/{len(Q)}")
+    if coarse == "f32":
+        assert differ == 0
+    else:
+        assert differ <= max(1, len(Q) // 10)
+
+
+@pytest.mark.parametrize("coarse", ["bf16", "fp8"])
+@pytest.mark.parametrize("name", ["c2s", "c3s"])
+def test_mfma_search_matches_oracle_on_equal_probe_sets(name, coarse):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    opts = ivf.make_opts(coarse=coarse, widen=4)
+    probes = g.debug_probes(Q, nprobe, opts=opts).cpu().numpy()
+    ids, dist = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    same = [qi for qi, p in enumerate(res["probes"]) if np.array_equal(probes[qi, :len(p)], p)]
+    assert len(same) >= len(Q) * 0.9
+    sub = {k_: v[same] for k_, v in res.items() if k_ in ("ids", "dist")}
+    check_final(ids[same], dist[same], sub, X, Q[same], cfg.metric,
+                exact_ids=(cfg.dist == "int255"))
+
+
+# ---------------------------------------------------------------------------
+# Batched form (list-major persistent scan) and hipGraph replay.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_batched_candidates_bit_exact(name):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    P = probes_tensor(res, nprobe)
+    keys = g.debug_candidates(Q, P, nprobe, cfg.R, opts=ivf.make_opts(form="batched")).cpu().numpy()
+    a, ids = ivf.decode_keys(keys)
+    assert np.array_equal(ids, res["cand_id"])
+    assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_batched_search_identical_to_plain(name):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    ip, dp = g.search(Q, nprobe, cfg.k, cfg.R)
+    ib, db = g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(form="batched"))
+    assert np.array_equal(ip.cpu().numpy(), ib.cpu().numpy())
+    assert np.array_equal(dp.cpu().numpy().view(np.uint32), db.cpu().numpy().view(np.uint32))
+    check_final(ib.cpu().numpy(), db.cpu().numpy(), res, X, Q, cfg.metric,
+                exact_ids=(cfg.dist == "int255"))
+
+
+def test_batched_survivor_overflow_recomputes():
+    # The first probed list is the farthest one, so the phase-1 threshold is
+    # loose and the near lists' survivors overflow their buffer (4R, at
+    # least 1024 keys): those queries go through the plain recompute.
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, _ = case("c2s")
+    nq = 6
+    rows = []
+    for q in Q[:nq]:
+        s = oracle.coarse_scores(q, index["cp"], cfg.metric)
+        order = oracle.select_probes(s, cfg.L)
+        rows.append(np.concatenate(([order[-1]], order[:20])))
+    P = torch.from_numpy(np.stack(rows).astype(np.int32))
+    npb = np.full(nq, P.shape[1], dtype=np.int32)
+    lens = np.diff(index["list_offsets"])
+    assert all(lens[r[1:]].sum() > 1024 for r in rows)
+    kp = g.debug_candidates(Q[:nq], P, npb, cfg.R).cpu().numpy()
+    kb = g.debug_candidates(Q[:nq], P, npb, cfg.R, opts=ivf.make_opts(form="batched")).cpu().numpy()
+    assert np.array_equal(kp, kb)
+    res = oracle.search(index, X, Q[:nq], 1, cfg.k, cfg.R)  # shape only
+    # Pool against the oracle on the same visiting order.
+    for qi, r in enumerate(rows):
+        all_a, all_i = [], []
+        for l in r:
+            T = oracle.lut_float(Q[qi], index["cm"][l], index["codebooks"], cfg.metric)
+            q8, lo, d, B = oracle.quantize_lut(T, oracle.list_bias(Q[qi], index["cm"][l], cfg.metric))
+            ids = index["list_ids"][index["list_offsets"][l]:index["list_offsets"][l + 1]].astype(np.int64)
+            all_a.append(oracle.scan_list(q8, d, B, index["codes"][ids])[1])
+            all_i.append(ids)
+        ca, ci = oracle.top_r(np.concatenate(all_a), np.concatenate(all_i), cfg.R)
+        a, ids = ivf.decode_keys(kb[qi])
+        assert np.array_equal(ids[:len(ci)], ci)
+        assert np.array_equal(a[:len(ca)].view(np.uint32), ca.view(np.uint32))
+    del res
+
+
+@pytest.mark.parametrize("form", ["plain", "batched"])
+def test_graph_replays_match_eager(form):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case("c3s")
+    stream = torch.cuda.Stream()
+    Qd = torch.from_numpy(Q).cuda()
+    npd = torch.from_numpy(nprobe).cuda()
+    eager = ivf.make_opts(form=form, coarse="bf16", widen=4)
+    graph = ivf.make_opts(form=form, coarse="bf16", widen=4, use_graph=True)
+    ids = torch.empty((len(Q), cfg.k), dtype=torch.int64, device="cuda")
+    dist = torch.empty((len(Q), cfg.k), dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(stream):
+        ie, de = g.search(Qd, npd, cfg.k, cfg.R, opts=eager)
+        ie, de = ie.clone(), de.clone()
+        for rep in range(4):
+            ids.fill_(-7)
+            dist.fill_(0.5)
+            g.search(Qd, npd, cfg.k, cfg.R, opts=graph, out=(ids, dist))
+            stream.synchronize()
+            assert torch.equal(ids, ie), rep
+            assert torch.equal(dist.view(torch.int32), de.view(torch.int32)), rep
+            # eager work between replays
+            g.search(Qd[:5], npd[:5], cfg.k, cfg.R, opts=eager)
+            stream.synchronize()
