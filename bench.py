@@ -29,6 +29,30 @@ from workloads import CONFIGS, exact_knn, make_workload, recall_at_k, train_inde
 
 METRIC_NAME = "QPS at recall@10=0.90, 1 GPU: plain vs BF16+batched; ADC-scan HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+# Lookup roofline of the vector ALUs: 256 CUs x 64 lanes per clock x 2.4 GHz,
+# two table lookups accumulated per packed 16-bit add.
+LOOKUP_PEAK_T = 256 * 64 * 2.4e9 * 2 / 1e12
+
+# HBM traffic of the dominant scan kernel, from rocprofv3 --pmc FETCH_SIZE
+# and --pmc WRITE_SIZE runs (KiB per dispatch, scaled by the factors a 1 GiB
+# device copy gave: 2.0 and 1.0). Valid only while the kernel source is the
+# one measured (sha256 of the listed files).
+TRAFFIC = {}
+
+
+def source_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2511_03298_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(config, form):
+    rec = TRAFFIC.get((config, form))
+    if not rec or source_sha(rec["files"]) != rec["sha"]:
+        return None
+    return int(rec["fetch_kib"] * 1024 * 2.0 + rec["write_kib"] * 1024 * 1.0)
 
 WORKLOAD_TEXT = {
     "c1": "10k x 32 Gaussian mixture, L2, 64 lists, PQ 16x4-bit, nprobe 8, k 10, rerank 100",
@@ -92,6 +116,28 @@ def cpu_baseline(index, X, Q, nprobe, k, R, seconds_per_worker=1.5):
 # ---------------------------------------------------------------------------
 
 
+def roofline(config, cfg, r, code_bytes):
+    """Roofline of the dominant kernel (the scan stage's kernel) of form r."""
+    kernel = ("batched_scan_kernel (list-major: 16-query tables, ADC scan, survivors)"
+              if r["form"] == "batched" else
+              "scan_plain_kernel (per-query: table build, ADC scan, top-R pool)")
+    code_total = {"c2": 32e6, "c3": 30e6, "c1": 80e3}.get(config, None)
+    streaming = r["form"] == "plain" and code_total is None  # code array >> caches
+    alg_bytes = r["scan_points"] * code_bytes
+    out = {"kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes,
+           "traffic": recorded_traffic(config, r["form"])}
+    if streaming:
+        out.update(bound="hbm", achieved=round(r["scan_gbs"], 1), peak=HBM_PEAK_GBS,
+                   unit="GB/s", frac=round(r["scan_gbs"] / HBM_PEAK_GBS, 4))
+    else:
+        # Code arrays of tens of MB stay in L2 / Infinity Cache: the scan is
+        # bound by table lookups on the vector ALUs (m per query and point).
+        out.update(bound="alu", achieved=round(r["scan_tlookups"], 3), peak=round(LOOKUP_PEAK_T, 2),
+                   unit="T lookups/s", frac=round(r["scan_tlookups"] / LOOKUP_PEAK_T, 4),
+                   algorithmic_lookups_per_launch=r["scan_points"] * cfg.m)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +148,9 @@ def main():
                     help="comma list of form:coarse, e.g. plain:exact,batched:bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-queries", type=int, default=1000)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this many MiB before timing (a kernel of "
+                         "known traffic for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -133,6 +182,14 @@ def main():
     import torch
 
     import paper_2511_03298_amd as ivf
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: one copy kernel reading {nbytes} B and writing {nbytes} B")
+        del src, dst
     g = ivf.GpuIndex.from_index(index, X, base_dtype=cfg.base_dtype)
     Qd = torch.from_numpy(Q).cuda()
     npd = torch.from_numpy(nprobe).cuda()
@@ -145,8 +202,18 @@ def main():
     probes = g.debug_probes(Qd, npd, max_nprobe=max_np).cpu().numpy()
     scanned = int(lens[probes[probes >= 0]].sum())
     code_bytes = (cfg.m + 1) // 2
-    scan_bytes = scanned * code_bytes
-    log(f"points scanned per step {scanned} ({scanned / cfg.nq:.0f} per query)")
+    # The batched scan kernel covers the lists after each query's first ones
+    # holding >= R points (those go through the first-list pass).
+    scanned_main = 0
+    for row in probes:
+        row = row[row >= 0]
+        seen, p = 0, 0
+        while p < len(row) and seen < cfg.R:
+            seen += int(lens[row[p]])
+            p += 1
+        scanned_main += int(lens[row[p:]].sum())
+    log(f"points scanned per step {scanned} ({scanned / cfg.nq:.0f} per query); "
+        f"batched scan kernel {scanned_main}")
 
     results = []
     for spec in args.forms.split(","):
@@ -169,12 +236,14 @@ def main():
         rec = recall_at_k(ids[:nrec].cpu().numpy(), gt_ids, 10)
         per = {k_: v / max(count, 1) for k_, v in stage_ms.items()}
         scan_ms = per["scan"]
+        pts = scanned_main if form == "batched" else scanned
         r = dict(form=form, coarse=coarse, qps=cfg.nq / (ms_step / 1000.0), ms_per_step=ms_step,
-                 recall_at_10=rec, stage_ms=per,
-                 scan_gbs=scan_bytes / (scan_ms / 1000.0) / 1e9 if scan_ms > 0 else None)
+                 recall_at_10=rec, stage_ms=per, scan_points=pts,
+                 scan_gbs=pts * code_bytes / (scan_ms / 1e3) / 1e9 if scan_ms > 0 else None,
+                 scan_tlookups=pts * cfg.m / (scan_ms / 1e3) / 1e12 if scan_ms > 0 else None)
         log(f"{form}/{coarse}: {r['qps']:.0f} q/s, {ms_step:.3f} ms/step, recall@10 {rec:.4f}, "
-            f"stages {', '.join(f'{k_} {v:.3f}ms' for k_, v in per.items())}, "
-            f"scan {r['scan_gbs']:.0f} GB/s algorithmic")
+            f"stages {', '.join(f'{k_} {v:.3f}ms' for k_, v in per.items())}, scan kernel "
+            f"{r['scan_gbs']:.0f} GB/s algorithmic, {r['scan_tlookups']:.2f} T lookups/s")
         results.append(r)
 
     ok = [r for r in results if r["recall_at_10"] >= 0.90] or results
@@ -199,16 +268,7 @@ def main():
         "forms": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()
                    if k_ != "stage_ms"} | {"stage_ms": {s: round(x, 4) for s, x in r["stage_ms"].items()}}
                   for r in results],
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "scan_plain_kernel (LUT build + ADC scan + top-R pool)",
-            "achieved": round(best["scan_gbs"], 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(best["scan_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "algorithmic_bytes_per_launch": scan_bytes,
-        },
+        "roofline": roofline(args.config, cfg, best, code_bytes),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

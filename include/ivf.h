@@ -219,12 +219,15 @@ int32_t ivf_get_device_error(const ivf_index* idx, void* workspace,
 
 /* Per-stage timing of ivf_search / ivf_search_with_probes. While enabled,
  * every search records HIP events on its stream around its stages
- * (IVF_STAGE_*); ivf_profile_read waits for the last recorded event and
- * returns, per stage, the summed milliseconds and the number of searches
- * since the previous read (then resets). At most 256 searches are kept
- * between reads; older ones are dropped. */
-enum { IVF_STAGE_COARSE = 0, IVF_STAGE_SELECT = 1, IVF_STAGE_SCAN = 2,
-       IVF_STAGE_RERANK = 3, IVF_NSTAGES = 4 };
+ * (IVF_STAGE_*): coarse scoring, probe selection, scan preparation (IP
+ * biases; batched form: first-list pass and work-list build), the scan
+ * kernel itself, the merge (batched form), the re-rank. ivf_profile_read
+ * waits for the last recorded event and returns, per stage, the summed
+ * milliseconds and the number of searches since the previous read (then
+ * resets). At most 256 searches are kept between reads. */
+enum { IVF_STAGE_COARSE = 0, IVF_STAGE_SELECT = 1, IVF_STAGE_PREP = 2,
+       IVF_STAGE_SCAN = 3, IVF_STAGE_MERGE = 4, IVF_STAGE_RERANK = 5,
+       IVF_NSTAGES = 6 };
 ivf_status ivf_profile_enable(ivf_index* idx, int32_t on);
 ivf_status ivf_profile_read(ivf_index* idx, float* ms /* [IVF_NSTAGES] */,
                             int32_t* count);

@@ -28,7 +28,7 @@ EXPORTED = [
     "ivf_debug_candidates", "ivf_get_table_layout", "ivf_get_device_error", "ivf_destroy",
     "ivf_last_error", "ivf_profile_enable", "ivf_profile_read", "ivf_debug_coarse_scores",
 ]
-STAGES = ("coarse", "select", "scan", "rerank")
+STAGES = ("coarse", "select", "prep", "scan", "merge", "rerank")
 
 
 class IvfError(RuntimeError):
@@ -329,7 +329,7 @@ class GpuIndex:
 
     def profile_read(self):
         """Summed milliseconds per stage and the number of searches since the last read."""
-        ms = (ctypes.c_float * 4)()
+        ms = (ctypes.c_float * len(STAGES))()
         cnt = ctypes.c_int32()
         check(lib().ivf_profile_read(self._h, ms, ctypes.byref(cnt)))
         return dict(zip(STAGES, list(ms))), cnt.value

@@ -18,7 +18,7 @@ struct ivf_profile {
   bool on = false;
   int head = 0, count = 0;
   hipEvent_t ev[RING][IVF_NSTAGES + 1] = {};
-  bool used[RING][IVF_NSTAGES] = {};
+  bool used[RING][IVF_NSTAGES + 1] = {};  // boundary recorded in this search
   int cur = -1;
 };
 
@@ -357,10 +357,14 @@ ivf_status ivf_profile_read(ivf_index* idx, float* ms, int32_t* count) {
   IVF_HIP(hipEventSynchronize(p->ev[last][IVF_NSTAGES]));
   for (int c = 0; c < p->count; ++c) {
     const int slot = (first + c) % ivf_profile::RING;
+    // A stage runs from its boundary to the next recorded one.
     for (int i = 0; i < IVF_NSTAGES; ++i) {
       if (!p->used[slot][i]) continue;
+      int j = i + 1;
+      while (j < IVF_NSTAGES && !p->used[slot][j]) ++j;
+      if (!p->used[slot][j]) continue;
       float t = 0.0f;
-      IVF_HIP(hipEventElapsedTime(&t, p->ev[slot][i], p->ev[slot][i + 1]));
+      IVF_HIP(hipEventElapsedTime(&t, p->ev[slot][i], p->ev[slot][j]));
       ms[i] += t;
     }
   }
@@ -398,7 +402,7 @@ hipError_t prof_begin(const ivf_index* idx) {
       if (e != hipSuccess) return e;
     }
   }
-  for (int i = 0; i < IVF_NSTAGES; ++i) p->used[slot][i] = false;
+  for (int i = 0; i <= IVF_NSTAGES; ++i) p->used[slot][i] = false;
   p->cur = slot;
   return hipSuccess;
 }
@@ -406,7 +410,7 @@ hipError_t prof_begin(const ivf_index* idx) {
 hipError_t prof_mark(const ivf_index* idx, hipStream_t s, int boundary) {
   ivf_profile* p = idx->prof;
   if (!p || !p->on || p->cur < 0) return hipSuccess;
-  if (boundary < IVF_NSTAGES) p->used[p->cur][boundary] = true;
+  p->used[p->cur][boundary] = true;
   hipError_t e = hipEventRecord(p->ev[p->cur][boundary], s);
   if (boundary == IVF_NSTAGES) p->cur = -1;  // this search is complete
   return e;
@@ -437,11 +441,16 @@ ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, int32_t nq,
                                const ivf_search_opts& o, const Workspace& w, int64_t* out_ids,
                                float* out_dist, hipStream_t s) {
   const Tables& t = idx->t;
-  IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
+  IVF_HIP(prof_mark(idx, s, IVF_STAGE_PREP));
   IVF_HIP(launch_bias(t, Q, nq, max_nprobe, w, s));
   if (o.form == IVF_FORM_BATCHED) {
-    IVF_HIP(launch_scan_batched(t, Q, nq, max_nprobe, rerank, o.chunk, w, s));
+    IVF_HIP(launch_batched_prep(t, Q, nq, max_nprobe, rerank, w, s));
+    IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
+    IVF_HIP(launch_batched_main(t, Q, nq, max_nprobe, rerank, w, s));
+    IVF_HIP(prof_mark(idx, s, IVF_STAGE_MERGE));
+    IVF_HIP(launch_batched_merge(t, Q, nq, max_nprobe, rerank, w, s));
   } else {
+    IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
     IVF_HIP(launch_scan_plain(t, Q, nq, max_nprobe, rerank, w, s));
   }
   IVF_HIP(prof_mark(idx, s, IVF_STAGE_RERANK));

@@ -32,15 +32,27 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 // Work list: (query, probe slot) pairs of phase 2 grouped by list.
 // ---------------------------------------------------------------------------
 
-__global__ void pairs_count_kernel(int32_t nq, int32_t max_nprobe,
-                                   const int32_t* __restrict__ probes,
-                                   const int32_t* __restrict__ nprobe_eff,
-                                   const int32_t* __restrict__ p1, int32_t* __restrict__ cnt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nq * max_nprobe) return;
-  const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
-  if (p < p1[q] || p >= nprobe_eff[q]) return;
-  atomicAdd(&cnt[probes[i]], 1);
+constexpr int PAIR_CHUNK = 4096;  // (query, probe) entries per workgroup
+
+// Per-list counts of phase-2 pairs: a workgroup histograms its chunk in LDS
+// and adds each non-zero bin to the global count once.
+__global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t max_nprobe, int32_t L,
+                                                          const int32_t* __restrict__ probes,
+                                                          const int32_t* __restrict__ nprobe_eff,
+                                                          const int32_t* __restrict__ p1,
+                                                          int32_t* __restrict__ cnt) {
+  extern __shared__ int32_t hist[];  // [L]
+  for (int l = threadIdx.x; l < L; l += blockDim.x) hist[l] = 0;
+  __syncthreads();
+  const int64_t n = (int64_t)nq * max_nprobe;
+  const int64_t b = (int64_t)blockIdx.x * PAIR_CHUNK;
+  for (int64_t i = b + threadIdx.x; i < b + PAIR_CHUNK && i < n; i += blockDim.x) {
+    const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
+    if (p >= p1[q] && p < nprobe_eff[q]) atomicAdd(&hist[probes[i]], 1);
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < L; l += blockDim.x)
+    if (hist[l]) atomicAdd(&cnt[l], hist[l]);
 }
 
 // Exclusive scans of per-list pair counts and item counts (one workgroup).
@@ -81,20 +93,36 @@ __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, const int32
   }
 }
 
-__global__ void pairs_fill_kernel(int32_t nq, int32_t max_nprobe,
-                                  const int32_t* __restrict__ probes,
-                                  const int32_t* __restrict__ nprobe_eff,
-                                  const int32_t* __restrict__ p1,
-                                  const int32_t* __restrict__ list_start,
-                                  int32_t* __restrict__ cursor, int32_t* __restrict__ pairs) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nq * max_nprobe) return;
-  const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
-  if (p < p1[q] || p >= nprobe_eff[q]) return;
-  const int l = probes[i];
-  const int pos = list_start[l] + atomicAdd(&cursor[l], 1);
-  pairs[2 * pos] = q;
-  pairs[2 * pos + 1] = p;
+// Scatter the pairs to their list's range: a workgroup reserves, per list,
+// one range for its whole chunk, then places entries with LDS atomics.
+__global__ void __launch_bounds__(256) pairs_fill_kernel(int32_t nq, int32_t max_nprobe, int32_t L,
+                                                         const int32_t* __restrict__ probes,
+                                                         const int32_t* __restrict__ nprobe_eff,
+                                                         const int32_t* __restrict__ p1,
+                                                         const int32_t* __restrict__ list_start,
+                                                         int32_t* __restrict__ cursor,
+                                                         int32_t* __restrict__ pairs) {
+  extern __shared__ int32_t hist[];  // [L]: counts, then base positions
+  for (int l = threadIdx.x; l < L; l += blockDim.x) hist[l] = 0;
+  __syncthreads();
+  const int64_t n = (int64_t)nq * max_nprobe;
+  const int64_t b = (int64_t)blockIdx.x * PAIR_CHUNK;
+  for (int64_t i = b + threadIdx.x; i < b + PAIR_CHUNK && i < n; i += blockDim.x) {
+    const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
+    if (p >= p1[q] && p < nprobe_eff[q]) atomicAdd(&hist[probes[i]], 1);
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < L; l += blockDim.x)
+    if (hist[l]) hist[l] = list_start[l] + atomicAdd(&cursor[l], hist[l]);
+  __syncthreads();
+  for (int64_t i = b + threadIdx.x; i < b + PAIR_CHUNK && i < n; i += blockDim.x) {
+    const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
+    if (p >= p1[q] && p < nprobe_eff[q]) {
+      const int pos = atomicAdd(&hist[probes[i]], 1);
+      pairs[2 * pos] = q;
+      pairs[2 * pos + 1] = p;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -344,24 +372,31 @@ int32_t batched_spill_cap(int32_t R) {
   return c;
 }
 
-template <int W>
-static hipError_t launch_batched_w(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
-                                   int32_t R, const Workspace& w, hipStream_t s) {
-  const int64_t np_total = (int64_t)nq * max_nprobe;
-  const unsigned g1 = (unsigned)((np_total + 255) / 256);
+hipError_t launch_batched_prep(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                               int32_t R, const Workspace& w, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
   hipError_t e;
-  // Phase 1: first lists per query -> pool, threshold, first probe of phase 2.
   if ((e = launch_fill_u32((uint32_t*)w.list_cnt, 0u, (size_t)t.L, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32((uint32_t*)w.spill_cnt, 0u, (size_t)nq, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(w.queue, 0u, 4, s)) != hipSuccess) return e;
+  // Phase 1: first lists per query -> pool, threshold, first probe of phase 2.
   if ((e = launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, w.p1, w.thr, nullptr, s)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(pairs_count_kernel, dim3(g1), dim3(256), 0, s, nq, max_nprobe, w.probes,
-                     w.nprobe_eff, w.p1, w.list_cnt);
+  const int64_t np_total = (int64_t)nq * max_nprobe;
+  const unsigned g1 = (unsigned)((np_total + PAIR_CHUNK - 1) / PAIR_CHUNK);
+  const size_t hist_lds = (size_t)t.L * 4;
+  hipLaunchKernelGGL(pairs_count_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
+                     w.probes, w.nprobe_eff, w.p1, w.list_cnt);
   hipLaunchKernelGGL(pairs_scan_kernel, dim3(1), dim3(1024), 0, s, t.L, w.list_cnt, w.list_start,
                      w.item_start, w.list_cursor);
-  hipLaunchKernelGGL(pairs_fill_kernel, dim3(g1), dim3(256), 0, s, nq, max_nprobe, w.probes,
-                     w.nprobe_eff, w.p1, w.list_start, w.list_cursor, w.pairs);
+  hipLaunchKernelGGL(pairs_fill_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
+                     w.probes, w.nprobe_eff, w.p1, w.list_start, w.list_cursor, w.pairs);
+  return hipGetLastError();
+}
+
+template <int W>
+static hipError_t launch_main_w(const Tables& t, const float* Q, int32_t max_nprobe,
+                                const Workspace& w, hipStream_t s) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -369,28 +404,31 @@ static hipError_t launch_batched_w(const Tables& t, const float* Q, int32_t nq, 
   hipLaunchKernelGGL(batched_scan_kernel<W>, dim3(cus * per_cu), dim3(256), 0, s, t, Q, max_nprobe,
                      w.bias, w.thr, w.list_start, w.item_start, w.pairs, w.queue, w.spill_cnt,
                      w.spill, w.spill_cap);
-  const size_t lds = (size_t)pow2_ceil((uint32_t)(R + w.spill_cap)) * 8;
-  hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, w.spill_cap, w.nprobe_eff,
-                     w.spill_cnt, w.spill, w.cand, w.redo);
-  // Queries whose survivors overflowed: recompute with the plain scan.
-  if ((e = launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, nullptr, nullptr, w.redo, s)) !=
-      hipSuccess)
-    return e;
   return hipGetLastError();
 }
 
-hipError_t launch_scan_batched(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
-                               int32_t rerank, int32_t chunk, const Workspace& w, hipStream_t s) {
-  (void)chunk;
+hipError_t launch_batched_main(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                               int32_t R, const Workspace& w, hipStream_t s) {
+  (void)R;
   if (nq == 0) return hipSuccess;
   switch (t.words) {
 #define X(N) \
-  case N: return launch_batched_w<N>(t, Q, nq, max_nprobe, rerank, w, s);
+  case N: return launch_main_w<N>(t, Q, max_nprobe, w, s);
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
     X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
 #undef X
     default: return hipErrorNotSupported;
   }
+}
+
+hipError_t launch_batched_merge(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                                int32_t R, const Workspace& w, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  const size_t lds = (size_t)pow2_ceil((uint32_t)(R + w.spill_cap)) * 8;
+  hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, w.spill_cap, w.nprobe_eff,
+                     w.spill_cnt, w.spill, w.cand, w.redo);
+  // Queries whose survivors overflowed: recompute with the plain scan.
+  return launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, nullptr, nullptr, w.redo, s);
 }
 
 }  // namespace ivf

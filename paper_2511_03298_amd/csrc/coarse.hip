@@ -77,18 +77,47 @@ hipError_t launch_coarse_exact(const Tables& t, const float* Q, int32_t nq, floa
 }
 
 // Canonical score of one (query, list) pair, one thread, sequential over t.
+// Rows are fetched four floats at a time when d is a multiple of 4; the
+// accumulation order is the same in both paths.
 __device__ __forceinline__ float canonical_score(const Tables& t, const float* q, int l) {
   const float* c = t.cp + (size_t)l * t.d;
+  const bool ip = t.metric == IVF_METRIC_IP;
   float acc = 0.0f;
-  if (t.metric == IVF_METRIC_IP) {
-    for (int i = 0; i < t.d; ++i) acc = acc + q[i] * c[i];
-    return plus_zero(-acc);
+  int i = 0;
+  if ((t.d & 3) == 0) {
+    const float4* c4 = reinterpret_cast<const float4*>(c);
+    for (; i < t.d; i += 16) {
+      float4 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = i + 4 * k < t.d ? c4[(i >> 2) + k] : make_float4(0, 0, 0, 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float cv[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int ii = i + 4 * k + e;
+          if (ii < t.d) {
+            if (ip) {
+              acc = acc + q[ii] * cv[e];
+            } else {
+              const float df = q[ii] - cv[e];
+              acc = acc + df * df;
+            }
+          }
+        }
+      }
+    }
+  } else {
+    for (; i < t.d; ++i) {
+      if (ip) {
+        acc = acc + q[i] * c[i];
+      } else {
+        const float df = q[i] - c[i];
+        acc = acc + df * df;
+      }
+    }
   }
-  for (int i = 0; i < t.d; ++i) {
-    float df = q[i] - c[i];
-    acc = acc + df * df;
-  }
-  return acc;
+  return ip ? plus_zero(-acc) : acc;
 }
 
 // One workgroup per query. Keys (ord(score) << 32 | list) live in LDS; the

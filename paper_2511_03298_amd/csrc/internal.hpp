@@ -112,9 +112,14 @@ hipError_t launch_bias(const Tables& t, const float* Q, int32_t nq, int32_t max_
                        const Workspace& w, hipStream_t s);
 hipError_t launch_scan_plain(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
                              int32_t rerank, const Workspace& w, hipStream_t s);
-hipError_t launch_scan_batched(const Tables& t, const float* Q, int32_t nq,
-                               int32_t max_nprobe, int32_t rerank, int32_t chunk,
-                               const Workspace& w, hipStream_t s);
+// Batched form in three parts: first-list pass + work list, the persistent
+// list-major scan, and the merge (+ recompute of overflowed queries).
+hipError_t launch_batched_prep(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                               int32_t rerank, const Workspace& w, hipStream_t s);
+hipError_t launch_batched_main(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                               int32_t rerank, const Workspace& w, hipStream_t s);
+hipError_t launch_batched_merge(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                                int32_t rerank, const Workspace& w, hipStream_t s);
 hipError_t launch_debug_luts(const Tables& t, const float* Q, int32_t nq, const int32_t* probes,
                              const int32_t* nprobe, int32_t max_nprobe, uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
                              hipStream_t s);
