@@ -201,6 +201,7 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
     w.list_cursor = (int32_t*)take((size_t)t.L * 4);
     w.list_start = (int32_t*)take((size_t)(t.L + 1) * 4);
     w.item_start = (int32_t*)take((size_t)(t.L + 1) * 4);
+    w.item_list = (int32_t*)take(nqs * max_nprobe * 4);
     w.pairs = (int32_t*)take(nqs * max_nprobe * 8);
     w.queue = (uint32_t*)take(64);
     w.spill_cnt = (int32_t*)take(nqs * 4);

@@ -59,7 +59,8 @@ __global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t ma
 __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, const int32_t* __restrict__ cnt,
                                                          int32_t* __restrict__ list_start,
                                                          int32_t* __restrict__ item_start,
-                                                         int32_t* __restrict__ cursor) {
+                                                         int32_t* __restrict__ cursor,
+                                                         int32_t* __restrict__ item_list) {
   __shared__ int32_t sp[1024], si[1024];
   const int tid = threadIdx.x;
   const int per = (L + 1023) / 1024;
@@ -84,8 +85,10 @@ __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, const int32
     list_start[l] = pacc;
     item_start[l] = iacc;
     cursor[l] = 0;
+    const int ni = (cnt[l] + BG - 1) / BG;
+    for (int i = 0; i < ni; ++i) item_list[iacc + i] = l;
     pacc += cnt[l];
-    iacc += (cnt[l] + BG - 1) / BG;
+    iacc += ni;
   }
   if (tid == 1023) {
     list_start[L] = sp[1023];
@@ -127,32 +130,33 @@ __global__ void __launch_bounds__(256) pairs_fill_kernel(int32_t nq, int32_t max
 
 // ---------------------------------------------------------------------------
 // Wave-level table build of one (query, list), the canonical arithmetic of the
-// plain form. Lane ln covers entries e = ln + 64 r (subspace j = 4r + ln/16,
-// code ln%16). Pass 1 finds the per-subspace minima (kept in LDS) and the
-// largest range; pass 2 recomputes the same float entries and writes the
-// quantised u16 table into the interleaved layout.
+// plain form. Operands come from LDS: rq = the residual q - c_l (L2, each
+// component rounded once) or q itself (IP), and the codebooks. Lane ln covers
+// entries e = ln + 64 r (subspace j = 4r + ln/16, code ln%16). Pass 1 finds
+// the per-subspace minima (kept in LDS) and the largest range; pass 2
+// recomputes the same entries and writes the quantised u16 table into the
+// interleaved layout.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float lut_entry(const Tables& t, const float* __restrict__ q, int l,
+__device__ __forceinline__ float lut_entry(const Tables& t, const float* rq, const float* cb_s,
                                            int j, int code) {
   const int ds = t.dsub;
-  const float* cb = t.codebooks + ((size_t)j * KSUB + code) * ds;
+  const float* cb = cb_s + ((size_t)j * KSUB + code) * ds;
+  const float* r = rq + j * ds;
   float acc = 0.0f;
   if (t.metric == IVF_METRIC_L2) {
-    const float* c = t.cm + (size_t)l * t.d + j * ds;
     for (int u = 0; u < ds; ++u) {
-      float rr = q[j * ds + u] - c[u];
-      float df = rr - cb[u];
+      const float df = r[u] - cb[u];
       acc = acc + df * df;
     }
     return acc;
   }
-  for (int u = 0; u < ds; ++u) acc = acc + q[j * ds + u] * cb[u];
+  for (int u = 0; u < ds; ++u) acc = acc + r[u] * cb[u];
   return plus_zero(-acc);
 }
 
 template <int W>
-__device__ __forceinline__ void wave_build_lut(const Tables& t, const float* __restrict__ q, int l,
+__device__ __forceinline__ void wave_build_lut(const Tables& t, const float* rq, const float* cb_s,
                                                float bias, int g, uint16_t* lut16, float* lo_s,
                                                float* outB, float* outDelta) {
   constexpr int MP = W * 8;  // padded subspaces
@@ -163,7 +167,7 @@ __device__ __forceinline__ void wave_build_lut(const Tables& t, const float* __r
 #pragma unroll 1
   for (int r = 0; r < nr; ++r) {
     const int j = 4 * r + (ln >> 4);
-    const float T = j < t.m ? lut_entry(t, q, l, j, code) : 0.0f;
+    const float T = j < t.m ? lut_entry(t, rq, cb_s, j, code) : 0.0f;
     float v = T;
     for (int s = 1; s < 16; s <<= 1) v = fminf(v, __shfl_xor(v, s));
     if (code == 0 && j < t.m) lo_s[j] = v;
@@ -178,7 +182,7 @@ __device__ __forceinline__ void wave_build_lut(const Tables& t, const float* __r
     const int j = 4 * r + (ln >> 4);
     uint16_t v = 0;
     if (live && j < t.m)
-      v = (uint16_t)fminf(rintf((lut_entry(t, q, l, j, code) - lo_s[j]) * sc), 255.0f);
+      v = (uint16_t)fminf(rintf((lut_entry(t, rq, cb_s, j, code) - lo_s[j]) * sc), 255.0f);
     lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = v;
   }
   const float ls = wave_pairwise_sum(lo_s, t.m);
@@ -198,63 +202,93 @@ struct BatchShared {
   float lo[IVF_NWAVES][W * 8];
   float B[BG], delta[BG];
   uint64_t thr[BG];
-  int32_t qid[BG];
-  int32_t item, l, nqi;
+  uint32_t smax[BG];  // largest S whose value can still pass (0xffffffff: none)
+  int32_t qid[BG], slot[BG];
+  int32_t item, next, l, nqi;
 };
+
+// Codebooks are staged in LDS when they fit beside the tables.
+template <int W>
+constexpr bool cb_in_lds() { return W <= 16; }
 
 template <int W>
 __global__ void __launch_bounds__(256) batched_scan_kernel(
     Tables t, const float* __restrict__ Q, int32_t max_nprobe, const float* __restrict__ bias,
     const uint64_t* __restrict__ thr, const int32_t* __restrict__ list_start,
-    const int32_t* __restrict__ item_start, const int32_t* __restrict__ pairs,
-    uint32_t* __restrict__ queue, int32_t* __restrict__ spill_cnt, uint64_t* __restrict__ spill,
-    int32_t cap) {
+    const int32_t* __restrict__ item_start, const int32_t* __restrict__ item_list,
+    const int32_t* __restrict__ pairs, uint32_t* __restrict__ queue,
+    int32_t* __restrict__ spill_cnt, uint64_t* __restrict__ spill, int32_t cap) {
   __shared__ BatchShared<W> sh;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  float* rq_all = reinterpret_cast<float*>(dyn);         // [4][d] per-wave query operand
+  float* cb_s = rq_all + IVF_NWAVES * t.d;               // [m*16*d'] (when staged)
+  const float* cb = cb_in_lds<W>() ? cb_s : t.codebooks;
+  float* rq = rq_all + wave_index() * t.d;
   const int tid = threadIdx.x, wave = tid / IVF_WAVE, ln = lane_id();
   const int n_items = item_start[t.L];
+  if (cb_in_lds<W>())
+    for (int i = tid; i < t.m * KSUB * t.dsub; i += blockDim.x) cb_s[i] = t.codebooks[i];
+  if (tid == 0) sh.next = (int32_t)atomicAdd(queue, 1u);
+  __syncthreads();
   for (;;) {
-    if (tid == 0) sh.item = (int32_t)atomicAdd(queue, 1u);
-    __syncthreads();
-    const int item = sh.item;
+    const int item = sh.next;
     if (item >= n_items) break;  // uniform: every wave leaves together
-    if (tid == 0) {
-      int lo = 0, hi = t.L;  // item_start[lo] <= item < item_start[hi]
-      while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (item_start[mid] <= item) lo = mid; else hi = mid;
-      }
-      const int first = (item - item_start[lo]) * BG;
-      const int npairs = list_start[lo + 1] - list_start[lo];
-      sh.l = lo;
-      sh.nqi = min(BG, npairs - first);
-      for (int i = 0; i < BG; ++i) {
-        const int pi = list_start[lo] + first + i;
-        const bool v = i < sh.nqi;
-        const int q = v ? pairs[2 * pi] : -1;
-        sh.qid[i] = q;
-        sh.thr[i] = v ? thr[q] : 0ull;
+    if (tid < BG) {
+      const int l = item_list[item];
+      const int first = (item - item_start[l]) * BG;
+      const int nqi = min(BG, list_start[l + 1] - list_start[l] - first);
+      const bool v = tid < nqi;
+      const int pi = list_start[l] + first + tid;
+      const int q = v ? pairs[2 * pi] : -1;
+      sh.qid[tid] = q;
+      sh.slot[tid] = v ? pairs[2 * pi + 1] : 0;
+      sh.thr[tid] = v ? thr[q] : 0ull;
+      if (tid == 0) {
+        sh.l = l;
+        sh.nqi = nqi;
       }
     }
     __syncthreads();
+    if (tid == 0) sh.next = (int32_t)atomicAdd(queue, 1u);  // overlaps this item
     const int l = sh.l, nqi = sh.nqi;
     // Tables: wave w builds queries w, w+4, w+8, w+12; absent queries get an
-    // all-zero table (their keys are never kept: threshold 0).
+    // all-zero table and no passing S.
 #pragma unroll 1
     for (int g = wave; g < BG; g += IVF_NWAVES) {
       if (g < nqi) {
-        const int pi = list_start[l] + (item - item_start[l]) * BG + g;
-        const int q = pairs[2 * pi], p = pairs[2 * pi + 1];
-        const float b = t.metric == IVF_METRIC_IP ? bias[(size_t)q * max_nprobe + p] : 0.0f;
-        wave_build_lut<W>(t, Q + (size_t)q * t.d, l, b, g, sh.lut16, sh.lo[wave], &sh.B[g],
-                          &sh.delta[g]);
+        const int q = sh.qid[g];
+        const float* qg = Q + (size_t)q * t.d;
+        if (t.metric == IVF_METRIC_L2) {
+          const float* c = t.cm + (size_t)l * t.d;
+          for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
+        } else {
+          for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i];
+        }
+        const float b = t.metric == IVF_METRIC_IP ? bias[(size_t)q * max_nprobe + sh.slot[g]] : 0.0f;
+        wave_build_lut<W>(t, rq, cb, b, g, sh.lut16, sh.lo[wave], &sh.B[g], &sh.delta[g]);
       } else {
         for (int e = ln; e < W * 8 * 16; e += IVF_WAVE)
           sh.lut16[(((e >> 4) * 2 + (g >> 3)) * 16 + (e & 15)) * 8 + (g & 7)] = 0;
-        if (ln == 0) {
-          sh.B[g] = 0.0f;
-          sh.delta[g] = 0.0f;
-        }
       }
+    }
+    __syncthreads();
+    // Per query, the largest integer sum S whose value a(S) = B + delta*S can
+    // still be <= the threshold's value part; a(S) is non-decreasing in S, so
+    // a point with a larger S cannot pass and needs no key.
+    if (tid < BG) {
+      const int g = tid;
+      uint32_t smax = 0xffffffffu;  // no S passes
+      if (g < nqi) {
+        const uint32_t othr = (uint32_t)(sh.thr[g] >> 32);
+        const float Bg = sh.B[g], dg = sh.delta[g];
+        int lo = -1, hi = 65536;  // f(lo) passes (or lo = -1), f(hi) fails
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (f2ord(plus_zero(Bg + dg * (float)mid)) <= othr) lo = mid; else hi = mid;
+        }
+        smax = lo < 0 ? 0xffffffffu : (uint32_t)lo;
+      }
+      sh.smax[g] = smax;
     }
     __syncthreads();
     const int n_l = t.list_len[l];
@@ -290,14 +324,24 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
         x = xn;
       }
       const bool valid = bi * BLOCK_PTS + ln < n_l;
-      const uint32_t id = valid ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
+      // Pre-check in the integer domain; absent queries have smax = none.
+      uint32_t cand = 0;
 #pragma unroll
       for (int g = 0; g < BG; ++g) {
-        if (g >= nqi) continue;  // uniform
+        const uint32_t S = acc[g >> 1][g & 1];
+        const uint32_t sm = sh.smax[g];
+        cand |= (sm != 0xffffffffu && S <= sm) ? (1u << g) : 0u;
+      }
+      if (!valid) cand = 0;
+      if (__ballot(cand != 0) == 0) continue;  // the common case: nothing passes
+      const uint32_t id = cand ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
+#pragma unroll
+      for (int g = 0; g < BG; ++g) {
+        if (__ballot((cand >> g) & 1u) == 0) continue;
         const uint32_t S = acc[g >> 1][g & 1];
         const float a = plus_zero(sh.B[g] + sh.delta[g] * (float)S);
         const uint64_t key = make_key(a, id);
-        const bool pass = valid && key <= sh.thr[g];
+        const bool pass = ((cand >> g) & 1u) && key <= sh.thr[g];
         const uint64_t mask = __ballot(pass);
         if (mask) {
           const int q = sh.qid[g];
@@ -330,7 +374,7 @@ __global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
   const int q = blockIdx.x, tid = threadIdx.x;
   const int ns = spill_cnt[q];
   if (tid == 0) redo[q] = 0;
-  if (nprobe_eff[q] < 0 || ns == 0) return;
+  if (nprobe_eff[q] < 0) return;
   if (ns > cap) {
     if (tid == 0) redo[q] = 1;
     return;
@@ -388,7 +432,7 @@ hipError_t launch_batched_prep(const Tables& t, const float* Q, int32_t nq, int3
   hipLaunchKernelGGL(pairs_count_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
                      w.probes, w.nprobe_eff, w.p1, w.list_cnt);
   hipLaunchKernelGGL(pairs_scan_kernel, dim3(1), dim3(1024), 0, s, t.L, w.list_cnt, w.list_start,
-                     w.item_start, w.list_cursor);
+                     w.item_start, w.list_cursor, w.item_list);
   hipLaunchKernelGGL(pairs_fill_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
                      w.probes, w.nprobe_eff, w.p1, w.list_start, w.list_cursor, w.pairs);
   return hipGetLastError();
@@ -400,10 +444,14 @@ static hipError_t launch_main_w(const Tables& t, const float* Q, int32_t max_npr
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = (int)(sizeof(BatchShared<W>) <= 20 * 1024 ? 6 : (sizeof(BatchShared<W>) <= 36 * 1024 ? 4 : 2));
-  hipLaunchKernelGGL(batched_scan_kernel<W>, dim3(cus * per_cu), dim3(256), 0, s, t, Q, max_nprobe,
-                     w.bias, w.thr, w.list_start, w.item_start, w.pairs, w.queue, w.spill_cnt,
-                     w.spill, w.spill_cap);
+  const size_t lds = (size_t)IVF_NWAVES * t.d * 4 +
+                     (cb_in_lds<W>() ? (size_t)t.m * KSUB * t.dsub * 4 : 0);
+  const size_t total = sizeof(BatchShared<W>) + lds;
+  const int per_cu = total <= 24 * 1024 ? 6 : total <= 36 * 1024 ? 4 : total <= 52 * 1024 ? 3
+                   : total <= 76 * 1024 ? 2 : 1;
+  hipLaunchKernelGGL(batched_scan_kernel<W>, dim3(cus * per_cu), dim3(256), lds, s, t, Q,
+                     max_nprobe, w.bias, w.thr, w.list_start, w.item_start, w.item_list, w.pairs,
+                     w.queue, w.spill_cnt, w.spill, w.spill_cap);
   return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ __device__ __forceinline__ uint64_t make_key(float v, uint32_t idx) {
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ int wave_index() { return threadIdx.x / IVF_WAVE; }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

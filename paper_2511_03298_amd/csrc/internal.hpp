@@ -74,6 +74,7 @@ struct Workspace {
   int32_t* list_cursor; // [L]
   int32_t* list_start;  // [L+1]
   int32_t* item_start;  // [L+1]
+  int32_t* item_list;   // [nq*max_nprobe] list of each work item
   int32_t* pairs;       // [nq*max_nprobe][2] (query, probe slot) grouped by list
   uint32_t* queue;      // [4] work-queue counter
   int32_t* spill_cnt;   // [nq] survivors per query

@@ -41,31 +41,45 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   for (int i = tid; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
   __syncthreads();
   constexpr int GROUPS = IVF_BLOCK / G;
+  constexpr int U = 4;  // candidates in flight per lane group
   const int g = tid / G, gl = tid % G;
-  for (int c0 = 0; c0 < R; c0 += GROUPS) {
-    const int c = c0 + g;
-    uint64_t key = c < R ? cand[(size_t)q * R + c] : KEY_NONE;
-    float acc = 0.0f;
-    if (key != KEY_NONE) {
-      const int64_t row = (int64_t)(uint32_t)key;
-      if (ip) {
-        for (int i = gl; i < t.d; i += G) acc = acc + qv[i] * load_base(t, row, i);
-      } else {
-        for (int i = gl; i < t.d; i += G) {
-          float df = qv[i] - load_base(t, row, i);
-          acc = acc + df * df;
+  for (int c0 = 0; c0 < R; c0 += GROUPS * U) {
+    uint64_t key[U];
+    float acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * GROUPS + g;
+      key[u] = c < R ? cand[(size_t)q * R + c] : KEY_NONE;
+      acc[u] = 0.0f;
+    }
+    for (int i = gl; i < t.d; i += G) {
+      float x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        x[u] = key[u] != KEY_NONE ? load_base(t, (int64_t)(uint32_t)key[u], i) : 0.0f;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ip) {
+          acc[u] = acc[u] + qv[i] * x[u];
+        } else {
+          const float df = qv[i] - x[u];
+          acc[u] = acc[u] + df * df;
         }
       }
     }
-    for (int s = 1; s < G; s <<= 1) acc = acc + __shfl_xor(acc, s, G);
-    if (gl == 0 && c < R) {
-      if (key == KEY_NONE) {
-        keys[c] = KEY_NONE;
-      } else {
-        // Ascending key = ascending L2 distance / descending inner
-        // product, then ascending id (the key's low 32 bits).
-        const float e = plus_zero(acc);
-        keys[c] = make_key(ip ? plus_zero(-e) : e, (uint32_t)key);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      for (int s = 1; s < G; s <<= 1) acc[u] = acc[u] + __shfl_xor(acc[u], s, G);
+      const int c = c0 + u * GROUPS + g;
+      if (gl == 0 && c < R) {
+        if (key[u] == KEY_NONE) {
+          keys[c] = KEY_NONE;
+        } else {
+          // Ascending key = ascending L2 distance / descending inner
+          // product, then ascending id (the key's low 32 bits).
+          const float e = plus_zero(acc[u]);
+          keys[c] = make_key(ip ? plus_zero(-e) : e, (uint32_t)key[u]);
+        }
       }
     }
   }

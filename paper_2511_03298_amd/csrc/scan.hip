@@ -103,6 +103,7 @@ struct ScanShared {
   float lo[W * 8];
   LutState st;
   SelectScratch sc;
+  unsigned long long maxkey;
   uint32_t total;
   uint32_t cnt;
 };
@@ -215,15 +216,28 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
     total = block_compact_le(keys, total, thr, &sh.cnt);
     if (total > (uint32_t)R) total = (uint32_t)R;
   }
+  if (p1_out) {
+    // First-list pass of the batched form: the pool unsorted (the merge
+    // sorts) and its largest key, the exact R-th smallest, as threshold.
+    if (tid == 0) sh.maxkey = 0;
+    __syncthreads();
+    uint64_t mk = 0;
+    for (uint32_t i = tid; i < total; i += blockDim.x) mk = keys[i] > mk ? keys[i] : mk;
+    if (mk) atomicMax(&sh.maxkey, (unsigned long long)mk);
+    for (int i = tid; i < R; i += blockDim.x)
+      cand[(size_t)q * R + i] = (uint32_t)i < total ? keys[i] : KEY_NONE;
+    __syncthreads();
+    if (tid == 0) {
+      p1_out[q] = np > 0 ? p_end : 0;
+      thr_out[q] = total >= (uint32_t)R ? (uint64_t)sh.maxkey : KEY_NONE;
+    }
+    return;
+  }
   const uint32_t n2 = pow2_ceil(total > 0 ? total : 1);
   for (uint32_t i = total + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
   block_bitonic_sort(keys, n2);
   for (int i = tid; i < R; i += blockDim.x)
     cand[(size_t)q * R + i] = (uint32_t)i < total ? keys[i] : KEY_NONE;
-  if (p1_out && tid == 0) {
-    p1_out[q] = np > 0 ? p_end : 0;
-    thr_out[q] = total >= (uint32_t)R ? keys[R - 1] : KEY_NONE;
-  }
 }
 
 // Candidate-buffer slack beyond R (keys), large enough that a round of one
