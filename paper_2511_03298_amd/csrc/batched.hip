@@ -205,6 +205,9 @@ struct BatchShared {
   uint32_t smax[BG];  // largest S whose value can still pass (0xffffffff: none)
   int32_t qid[BG], slot[BG];
   int32_t item, next, l, nqi;
+  // Per wave: the current block's code words, then (after the word loop)
+  // its 16 sums per point for the rare exact-key path.
+  uint32_t stage[IVF_NWAVES][(W * 2 > BG ? W * 2 : BG) * BLOCK_PTS / 2];
 };
 
 // Codebooks are staged in LDS when they fit beside the tables.
@@ -294,22 +297,37 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
     const int n_l = t.list_len[l];
     const int blk0 = t.block_off[l];
     const int nblk = (n_l + BLOCK_PTS - 1) / BLOCK_PTS;
+    // Code words: the next block's words are loaded into registers while the
+    // current block, staged in this wave's LDS slice, is scanned.
+    uint32_t* stage = sh.stage[wave];
+    uint32_t nx[W];
+    if (wave < nblk) {
+      const uint32_t* cw = t.codes + (size_t)(blk0 + wave) * W * BLOCK_PTS + ln;
+#pragma unroll
+      for (int w = 0; w < W; ++w) nx[w] = cw[w * BLOCK_PTS];
+    }
+    const unsigned char* lutb = reinterpret_cast<const unsigned char*>(sh.lut16);
 #pragma unroll 1
     for (int bi = wave; bi < nblk; bi += IVF_NWAVES) {
       const int blk = blk0 + bi;
-      const uint32_t* cw = t.codes + (size_t)blk * W * BLOCK_PTS + ln;
+#pragma unroll
+      for (int w = 0; w < W; ++w) stage[w * BLOCK_PTS + ln] = nx[w];
+      if (bi + IVF_NWAVES < nblk) {
+        const uint32_t* cw = t.codes + (size_t)(blk + IVF_NWAVES) * W * BLOCK_PTS + ln;
+#pragma unroll
+        for (int w = 0; w < W; ++w) nx[w] = cw[w * BLOCK_PTS];
+      }
       u16x2 acc[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc[k] = u16x2{0, 0};
-      const unsigned char* lutb = reinterpret_cast<const unsigned char*>(sh.lut16);
-      uint32_t x = cw[0];
 #pragma unroll 1
       for (int w = 0; w < W; ++w) {
-        const uint32_t xn = w + 1 < W ? cw[(w + 1) * BLOCK_PTS] : 0u;
-        const unsigned char* base = lutb + w * 8 * 512;
+        const uint32_t x = stage[w * BLOCK_PTS + ln];
+        const uint32_t base = (uint32_t)(w * 8 * 512);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          const unsigned char* row = base + s * 512 + ((x >> (4 * s)) & 15u) * 16u;
+          const uint32_t nib = __builtin_amdgcn_ubfe(x, 4 * s, 4);
+          const unsigned char* row = lutb + ((nib << 4) + base + s * 512);
           const uint4 lo4 = *reinterpret_cast<const uint4*>(row);
           const uint4 hi4 = *reinterpret_cast<const uint4*>(row + 256);
           acc[0] += __builtin_bit_cast(u16x2, lo4.x);
@@ -321,7 +339,6 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
           acc[6] += __builtin_bit_cast(u16x2, hi4.z);
           acc[7] += __builtin_bit_cast(u16x2, hi4.w);
         }
-        x = xn;
       }
       const bool valid = bi * BLOCK_PTS + ln < n_l;
       // Pre-check in the integer domain; absent queries have smax = none.
@@ -334,14 +351,19 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       }
       if (!valid) cand = 0;
       if (__ballot(cand != 0) == 0) continue;  // the common case: nothing passes
-      const uint32_t id = cand ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
+      // Rare path: exact keys for the candidate (point, query) pairs.
+      uint16_t* sv = reinterpret_cast<uint16_t*>(stage);
 #pragma unroll
+      for (int g = 0; g < BG; ++g) sv[g * BLOCK_PTS + ln] = acc[g >> 1][g & 1];
+      const uint32_t id = cand ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
+#pragma unroll 1
       for (int g = 0; g < BG; ++g) {
-        if (__ballot((cand >> g) & 1u) == 0) continue;
-        const uint32_t S = acc[g >> 1][g & 1];
+        const bool c = (cand >> g) & 1u;
+        if (__ballot(c) == 0) continue;
+        const uint32_t S = sv[g * BLOCK_PTS + ln];
         const float a = plus_zero(sh.B[g] + sh.delta[g] * (float)S);
         const uint64_t key = make_key(a, id);
-        const bool pass = ((cand >> g) & 1u) && key <= sh.thr[g];
+        const bool pass = c && key <= sh.thr[g];
         const uint64_t mask = __ballot(pass);
         if (mask) {
           const int q = sh.qid[g];
