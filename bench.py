@@ -37,7 +37,12 @@ LOOKUP_PEAK_T = 256 * 64 * 2.4e9 * 2 / 1e12
 # and --pmc WRITE_SIZE runs (KiB per dispatch, scaled by the factors a 1 GiB
 # device copy gave: 2.0 and 1.0). Valid only while the kernel source is the
 # one measured (sha256 of the listed files).
-TRAFFIC = {}
+TRAFFIC = {
+    ("c2", "batched"): dict(files=("batched.hip", "common.hpp"), sha="a6bf74250dff637e",
+                            fetch_kib=107976.9, write_kib=1876.7),
+    ("c2", "plain"): dict(files=("scan.hip", "common.hpp"), sha="18d181930b024f9d",
+                          fetch_kib=5550621.1, write_kib=15625.0),
+}
 
 
 def source_sha(files):
