@@ -14,7 +14,9 @@ no value printed by the paper pins it: parity unpinned for the scheme itself.
 """
 
 from .ivfpq import (  # noqa: F401
+    assign_lists,
     brute_force_knn,
+    encode,
     coarse_scores,
     lut_float,
     list_bias,

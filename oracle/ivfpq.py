@@ -285,6 +285,33 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
     return res
 
 
+# --------------------------------------------------------------------------
+# Index construction steps (Alg. 1: list assignment and Quantize).
+# --------------------------------------------------------------------------
+
+def assign_lists(X: np.ndarray, cp: np.ndarray, metric: str) -> np.ndarray:
+    """Nearest list of every row: the top-1 of step 1 (canonical FP32 score,
+    ties to the smaller list index)."""
+    return np.array([select_probes(coarse_scores(x, cp, metric), 1)[0] for x in X],
+                    dtype=np.int64)
+
+
+def encode(X: np.ndarray, cm: np.ndarray, lists: np.ndarray, codebooks: np.ndarray) -> np.ndarray:
+    """PQ codes of the residuals x - cm[list(x)] (Alg. 1 Quantize, section 2.3).
+
+    code_j(x) = argmin_i sum_u (r_{j d'+u} - B[j,i,u])^2 with the residual
+    component rounded once and the sum sequential in u (FP32); ties go to the
+    smallest i.
+    """
+    X = np.asarray(X, dtype=F32)
+    cb = np.asarray(codebooks, dtype=F32)
+    m, K, dsub = cb.shape
+    r = X - np.asarray(cm, dtype=F32)[np.asarray(lists)]
+    diff = r.reshape(len(X), m, 1, dsub) - cb[None]
+    dist = seq_sum(diff * diff)                      # [n, m, K]
+    return np.argmin(dist, axis=2).astype(np.uint8)  # first minimum
+
+
 def brute_force_knn(X: np.ndarray, Q: np.ndarray, k: int, metric: str):
     """Exact k-NN (section 1 problem statement) by exhaustive float64 search.
 

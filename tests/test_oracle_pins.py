@@ -296,3 +296,42 @@ def test_edge_cases_small_pools_and_empty_lists():
     # Fewer candidates than k: padded with (-1, +inf).
     res = oracle.search(idx, X, Q, 1, 5, 3)
     assert np.all(res["ids"][:, 3:] == -1) and np.all(np.isinf(res["dist"][:, 3:]))
+
+
+# ------------------------------------------- index construction (Alg. 1)
+
+def test_encode_against_plain_python_and_reconstruction():
+    rng = make_rng(5)
+    n, m, dsub, L = 40, 6, 3, 4
+    cb = rng.normal(size=(m, 16, dsub)).astype(np.float32)
+    cm = rng.normal(size=(L, m * dsub)).astype(np.float32)
+    lists = rng.integers(0, L, size=n)
+    X = rng.normal(size=(n, m * dsub)).astype(np.float32)
+    # Exact ties: make codeword 5 a copy of codeword 2 in every subspace.
+    cb[:, 5] = cb[:, 2]
+    codes = oracle.encode(X, cm, lists, cb)
+    X64, cb64, cm64 = X.astype(np.float64), cb.astype(np.float64), cm.astype(np.float64)
+    for x in range(n):
+        r = X64[x] - cm64[lists[x]]
+        for j in range(m):
+            d = [sum((r[j * dsub + u] - cb64[j, i, u]) ** 2 for u in range(dsub)) for i in range(16)]
+            best = min(d)
+            # The FP32 choice is a minimiser up to rounding, never 5 (tie -> 2).
+            assert d[codes[x, j]] <= best * (1 + 1e-5) + 1e-6
+            assert codes[x, j] != 5
+    # Lossless case: rows equal to a centroid plus codewords encode to them.
+    want = rng.integers(0, 16, size=(n, m))
+    want[want == 5] = 2
+    Xl = cm[lists] + cb[np.arange(m)[None, :], want].reshape(n, -1)
+    assert np.array_equal(oracle.encode(Xl.astype(np.float32), cm, lists, cb), want)
+
+
+@pytest.mark.parametrize("metric", ["l2", "ip"])
+def test_assign_lists_is_top1_of_float64_ranking(metric):
+    cfg, X, Q, _, index = cached_workload("c1" if metric == "l2" else "c3", 3000, 4, L=16, ncomp=12)
+    a = oracle.assign_lists(X[:300], index["cp"], metric)
+    cp = index["cp"].astype(np.float64)
+    for x, l in zip(X[:300].astype(np.float64), a):
+        s64 = ((cp - x) ** 2).sum(1) if metric == "l2" else -(cp @ x)
+        mag = ((np.abs(cp) + np.abs(x)) ** 2).sum(1) if metric == "l2" else (np.abs(cp) * np.abs(x)).sum(1)
+        assert s64[l] <= s64.min() + 2 * (cfg.d + 2) * EPS32 * mag.max()
