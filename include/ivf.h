@@ -232,6 +232,34 @@ ivf_status ivf_profile_enable(ivf_index* idx, int32_t on);
 ivf_status ivf_profile_read(ivf_index* idx, float* ms /* [IVF_NSTAGES] */,
                             int32_t* count);
 
+/* ---- Index construction on the GPU (Alg. 1) ----------------------------- */
+
+/* Workspace of ivf_assign for `chunk` rows per pass (1..2^20). */
+size_t ivf_assign_workspace_bytes(int32_t L, int32_t d, int32_t chunk,
+                                  int32_t coarse);
+
+/* Nearest list of every row of X [n,d] (FP32, device): out_list[n] int32 =
+ * the list with the smallest (canonical FP32 coarse score, list index)
+ * against centroids [L,d] (device; the probe centroids: normalised for IP),
+ * i.e. the top-1 of search step 1. coarse/widen as in ivf_search_opts: the
+ * MFMA forms pre-select `widen` lists per row from the approximate scores,
+ * then re-score canonically (exact when the canonical best is among them).
+ * Rows are processed `chunk` at a time. Errors as for ivf_search. */
+ivf_status ivf_assign(const float* centroids, int32_t L, int32_t d,
+                      int32_t metric, const float* X, int64_t n, int32_t chunk,
+                      int32_t coarse, int32_t widen, void* workspace,
+                      size_t workspace_bytes, int32_t* out_list, void* stream);
+
+/* PQ codes of residuals (Alg. 1 Quantize): out_codes [n,m] uint8,
+ * code_j(x) = argmin_i sum_u (r_{j d'+u} - codebooks[j,i,u])^2 with
+ * r = x - centroids[lists[x]] (each component rounded once), the sum
+ * sequential in u in FP32, ties to the smallest i. All arrays device:
+ * X [n,d], centroids [L,d] (mean centroids), lists [n], codebooks [m,16,d/m]. */
+ivf_status ivf_encode(const float* X, int64_t n, int32_t d,
+                      const float* centroids, const int32_t* lists,
+                      const float* codebooks, int32_t m, uint8_t* out_codes,
+                      void* stream);
+
 /* Frees the host handle only; table_mem stays the caller's. */
 void ivf_destroy(ivf_index* idx);
 

@@ -27,6 +27,7 @@ EXPORTED = [
     "ivf_search", "ivf_search_with_probes", "ivf_debug_probes", "ivf_debug_luts",
     "ivf_debug_candidates", "ivf_get_table_layout", "ivf_get_device_error", "ivf_destroy",
     "ivf_last_error", "ivf_profile_enable", "ivf_profile_read", "ivf_debug_coarse_scores",
+    "ivf_assign_workspace_bytes", "ivf_assign", "ivf_encode",
 ]
 STAGES = ("coarse", "select", "prep", "scan", "merge", "rerank")
 
@@ -83,6 +84,9 @@ def _declare(lib):
         "ivf_profile_enable": (I32, [P, I32]),
         "ivf_profile_read": (I32, [P, P, P]),
         "ivf_last_error": (ctypes.c_char_p, []),
+        "ivf_assign_workspace_bytes": (SZ, [I32, I32, I32, I32]),
+        "ivf_assign": (I32, [P, I32, I32, I32, P, I64, I32, I32, I32, P, SZ, P, P]),
+        "ivf_encode": (I32, [P, I64, I32, P, P, P, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -339,6 +343,34 @@ class GpuIndex:
         if ws is None:
             return 0
         return int(lib().ivf_get_device_error(self._h, ws.data_ptr(), _stream()))
+
+
+def assign_lists(centroids, X, metric: str, coarse: str = "bf16", widen: int = 4,
+                 chunk: int = 65536):
+    """Nearest list per row of X (device tensors) via ivf_assign; int32 tensor."""
+    import torch
+    L, d = centroids.shape
+    n = X.shape[0]
+    chunk = max(1, min(chunk, n))
+    nb = lib().ivf_assign_workspace_bytes(L, d, chunk, COARSE[coarse])
+    if nb == 0:
+        raise IvfError(IVF_ERR_INVALID_ARG, last_error())
+    ws = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    out = torch.empty(n, dtype=torch.int32, device=X.device)
+    check(lib().ivf_assign(_ptr(centroids), L, d, METRIC[metric], _ptr(X), n, chunk,
+                           COARSE[coarse], widen, ws.data_ptr(), nb, _ptr(out), _stream()))
+    return out
+
+
+def encode_codes(X, centroids, lists, codebooks):
+    """PQ codes [n, m] uint8 of residuals against the lists' mean centroids."""
+    import torch
+    n, d = X.shape
+    m = codebooks.shape[0]
+    out = torch.empty((n, m), dtype=torch.uint8, device=X.device)
+    check(lib().ivf_encode(_ptr(X), n, d, _ptr(centroids), _ptr(lists), _ptr(codebooks), m,
+                           _ptr(out), _stream()))
+    return out
 
 
 def decode_keys(keys):

@@ -15,7 +15,7 @@ OUT = os.path.join(PKG, "libivfpq.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["abi.cpp", "tables.hip", "coarse.hip", "coarse_mfma.hip", "scan.hip", "rerank.hip",
-           "batched.hip"]
+           "batched.hip", "build_index.hip"]
 
 # Canonical FP32 stages must not be contracted into FMAs; packed FP32 VALU
 # instructions are disabled for the device code.

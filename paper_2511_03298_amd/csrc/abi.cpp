@@ -644,6 +644,119 @@ ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries, int3
   return IVF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of ivf_assign: centroid operand tables, then per-chunk buffers.
+struct AssignPlan {
+  Tables t;
+  Workspace w;
+  int32_t* ones;
+  size_t total;
+};
+
+AssignPlan plan_assign(int32_t L, int32_t d, int32_t metric, int32_t chunk, int32_t coarse,
+                       const float* centroids, char* base) {
+  AssignPlan a;
+  std::memset(&a, 0, sizeof(a));
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = align_up(off + bytes);
+    return p;
+  };
+  Tables& t = a.t;
+  t.d = d;
+  t.L = L;
+  t.m = 1;
+  t.dsub = d;
+  t.metric = metric;
+  t.L_pad = round_up_i(L, TILE_L);
+  t.d_pad = round_up_i(d, TILE_D);
+  t.cp = centroids;
+  t.cm = centroids;
+  t.cp_norm2 = (const float*)take((size_t)t.L_pad * 4);
+  t.cp_f32 = (const float*)take((size_t)t.L_pad * t.d_pad * 4);
+  t.cp_bf16 = (const uint16_t*)take((size_t)t.L_pad * t.d_pad * 2);
+  t.cp_fp8 = (const uint8_t*)take((size_t)t.L_pad * t.d_pad);
+  t.cp_fp8_scale = (const float*)take((size_t)t.L_pad * 4);
+  Workspace& w = a.w;
+  const size_t cp = (size_t)round_up_i(chunk, TILE_L);
+  w.err = (int32_t*)take(16);
+  w.scores = (float*)take((size_t)chunk * L * 4);
+  w.nprobe_eff = (int32_t*)take((size_t)chunk * 4);
+  a.ones = (int32_t*)take((size_t)chunk * 4);
+  if (coarse != IVF_COARSE_EXACT) {
+    w.q_lowp = (void*)take(cp * t.d_pad * 4);
+    w.q_scale = (float*)take(cp * 4);
+  }
+  a.total = off;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ivf_assign_workspace_bytes(int32_t L, int32_t d, int32_t chunk, int32_t coarse) {
+  if (L < 1 || L > 16384 || d < 1 || chunk < 1 || chunk > (1 << 20) || coarse < 0 ||
+      coarse > IVF_COARSE_FP8) {
+    g_last_error = "invalid assign sizes";
+    return 0;
+  }
+  return plan_assign(L, d, IVF_METRIC_L2, chunk, coarse, nullptr, nullptr).total;
+}
+
+ivf_status ivf_assign(const float* centroids, int32_t L, int32_t d, int32_t metric,
+                      const float* X, int64_t n, int32_t chunk, int32_t coarse, int32_t widen,
+                      void* workspace, size_t workspace_bytes, int32_t* out_list, void* stream) {
+  if (L < 1 || L > 16384 || d < 1 || n < 0 || chunk < 1 || chunk > (1 << 20))
+    return fail(IVF_ERR_INVALID_ARG, "invalid assign sizes");
+  if (metric != IVF_METRIC_L2 && metric != IVF_METRIC_IP) return fail(IVF_ERR_INVALID_ARG, "unknown metric");
+  if (coarse < IVF_COARSE_EXACT || coarse > IVF_COARSE_FP8 || widen < 1)
+    return fail(IVF_ERR_INVALID_ARG, "invalid coarse form or widen");
+  if (n == 0) return IVF_OK;
+  if (!centroids || !X || !out_list || !workspace) return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  if ((uintptr_t)workspace % ALIGN) return fail(IVF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  AssignPlan a = plan_assign(L, d, metric, chunk, coarse, centroids, (char*)workspace);
+  if (workspace_bytes < a.total) return fail(IVF_ERR_WORKSPACE, "workspace too small");
+  ivf_status st = check_device();
+  if (st != IVF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_aux_tables(a.t, s));
+  IVF_HIP(launch_fill_u32((uint32_t*)a.ones, 1u, (size_t)chunk, s));
+  IVF_HIP(launch_fill_u32((uint32_t*)a.w.err, 0u, 4, s));
+  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+    const int32_t rows = (int32_t)((n - r0) < chunk ? (n - r0) : chunk);
+    const float* Xc = X + r0 * d;
+    Workspace w = a.w;
+    w.probes = out_list + r0;  // max_nprobe = 1: one list per row
+    if (coarse == IVF_COARSE_EXACT) {
+      IVF_HIP(launch_coarse_exact(a.t, Xc, rows, w.scores, s));
+      IVF_HIP(launch_select_probes(a.t, Xc, rows, a.ones, 1, 1, false, w, s));
+    } else {
+      IVF_HIP(launch_coarse_mfma(a.t, Xc, rows, coarse, w, s));
+      IVF_HIP(launch_select_probes(a.t, Xc, rows, a.ones, 1, widen, true, w, s));
+    }
+  }
+  return IVF_OK;
+}
+
+ivf_status ivf_encode(const float* X, int64_t n, int32_t d, const float* centroids,
+                      const int32_t* lists, const float* codebooks, int32_t m,
+                      uint8_t* out_codes, void* stream) {
+  if (n < 0 || d < 1 || m < 1 || m > MAX_M || d % m != 0)
+    return fail(IVF_ERR_INVALID_ARG, "invalid encode sizes");
+  if (n == 0) return IVF_OK;
+  if (!X || !centroids || !lists || !codebooks || !out_codes)
+    return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  ivf_status st = check_device();
+  if (st != IVF_OK) return st;
+  IVF_HIP(launch_encode(X, n, d, m, centroids, lists, codebooks, out_codes, (hipStream_t)stream));
+  return IVF_OK;
+}
+
 int32_t ivf_get_device_error(const ivf_index* idx, void* workspace, void* stream) {
   if (!idx || !workspace) {
     g_last_error = "NULL argument";

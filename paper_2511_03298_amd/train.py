@@ -1,0 +1,109 @@
+"""IVF + residual-PQ index construction on the GPU (Alg. 1).
+
+KMeans over the lists, PQ codebooks per subspace, Quantize. The heavy steps
+run in the library's kernels: nearest-list assignment (`ivf_assign`, the
+coarse-scoring kernels with top-1 selection) and residual encoding
+(`ivf_encode`). The k-means mean updates are small reductions done on the
+host in float64 so the trained index is reproducible. Lists are selected with
+normalised centroids for inner product and residuals use the mean centroids
+(section 4.6.1).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import assign_lists, encode_codes
+
+KSUB = 16
+
+
+def _group_means(X, a, k, chunk=1 << 20):
+    """Per-group float64 sums and counts, in chunks of the group-sorted order."""
+    order = np.argsort(a, kind="stable")
+    counts = np.bincount(a, minlength=k)
+    sums = np.zeros((k, X.shape[1]), dtype=np.float64)
+    for s in range(0, len(order), chunk):
+        idx = order[s:s + chunk]
+        lab = a[idx]
+        starts = np.concatenate(([0], np.nonzero(np.diff(lab))[0] + 1))
+        sums[lab[starts]] += np.add.reduceat(X[idx].astype(np.float64), starts, axis=0)
+    return sums, counts
+
+
+def _normalise(C):
+    nrm = np.linalg.norm(C, axis=1, keepdims=True)
+    nrm[nrm == 0] = 1.0
+    return C / nrm
+
+
+def _host_kmeans(X, k, iters, rng):
+    """Small k-means for the 16-codeword PQ codebooks (host, float64 means)."""
+    C = X[rng.choice(len(X), size=k, replace=len(X) < k)].astype(np.float64)
+    for _ in range(iters):
+        d = ((X[:, None, :].astype(np.float64) - C[None]) ** 2).sum(axis=2)
+        a = np.argmin(d, axis=1)
+        sums, counts = _group_means(X, a, k)
+        C = np.where(counts[:, None] > 0, sums / np.maximum(counts, 1)[:, None], C)
+        empty = counts == 0
+        if empty.any():
+            C[empty] = X[rng.choice(len(X), size=int(empty.sum()))]
+    return C.astype(np.float32)
+
+
+def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
+                    iters: int = 10, pq_iters: int = 12, train_per_list: int = 64,
+                    pq_train: int = 65536, coarse: str = "bf16", widen: int = 4,
+                    device: str = "cuda"):
+    """Train an IVF-PQ index over X (float32 [n, d], host). Returns the same
+    dict layout as the host trainer; `codes` and `list_ids` stay on the GPU
+    (torch tensors), everything else is numpy."""
+    import torch
+
+    n, d = X.shape
+    assert d % m == 0
+    ip = metric == "ip"
+    rng = np.random.default_rng(seed)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(device)
+
+    nt = min(n, max(train_per_list * L, L))
+    tidx = np.sort(rng.choice(n, size=nt, replace=False)) if nt < n else np.arange(n)
+    Xt = X[tidx]
+    Xtd = Xd[torch.from_numpy(tidx).to(device)]
+    C = Xt[rng.choice(nt, size=L, replace=nt < L)].astype(np.float64)
+    for _ in range(iters):
+        Cs = _normalise(C) if ip else C
+        Cd = torch.from_numpy(Cs.astype(np.float32)).to(device)
+        a = assign_lists(Cd, Xtd, metric, coarse=coarse, widen=widen).cpu().numpy().astype(np.int64)
+        sums, counts = _group_means(Xt, a, L)
+        C = np.where(counts[:, None] > 0, sums / np.maximum(counts, 1)[:, None], C)
+        empty = counts == 0
+        if empty.any():
+            C[empty] = Xt[rng.choice(nt, size=int(empty.sum()))]
+    Cs = _normalise(C) if ip else C
+    Cd = torch.from_numpy(Cs.astype(np.float32)).to(device)
+    assign_d = assign_lists(Cd, Xd, metric, coarse=coarse, widen=widen)
+    assign = assign_d.cpu().numpy().astype(np.int64)
+    sums, counts = _group_means(X, assign, L)
+    cm64 = np.where(counts[:, None] > 0, sums / np.maximum(counts, 1)[:, None], C)
+    cm = cm64.astype(np.float32)
+    cp = _normalise(cm.astype(np.float64)).astype(np.float32) if ip else cm.copy()
+
+    dsub = d // m
+    pidx = rng.choice(n, size=min(n, pq_train), replace=False)
+    resid = X[pidx] - cm[assign[pidx]]
+    codebooks = np.empty((m, KSUB, dsub), dtype=np.float32)
+    for j in range(m):
+        codebooks[j] = _host_kmeans(np.ascontiguousarray(resid[:, j * dsub:(j + 1) * dsub]),
+                                    KSUB, pq_iters, rng)
+    cmd = torch.from_numpy(cm).to(device)
+    cbd = torch.from_numpy(codebooks).to(device)
+    codes = encode_codes(Xd, cmd, assign_d, cbd)
+
+    order = np.argsort(assign, kind="stable")
+    offsets = np.zeros(L + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    return dict(cm=cm, cp=cp, codebooks=codebooks, codes=codes,
+                list_offsets=offsets,
+                list_ids=torch.from_numpy(order.astype(np.int32)).to(device),
+                metric=metric, assign=assign)

@@ -392,3 +392,46 @@ def test_graph_replays_match_eager(form):
             # eager work between replays
             g.search(Qd[:5], npd[:5], cfg.k, cfg.R, opts=eager)
             stream.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# Index construction on the GPU (Alg. 1): assignment and encoding.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "c5s"])
+def test_gpu_assign_and_encode_bit_exact(name):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    rows = X[:3000]
+    Xd = torch.from_numpy(np.ascontiguousarray(rows)).cuda()
+    cpd = torch.from_numpy(index["cp"]).cuda()
+    want = oracle.assign_lists(rows, index["cp"], cfg.metric)
+    got = ivf.assign_lists(cpd, Xd, cfg.metric, coarse="exact", chunk=1000).cpu().numpy()
+    assert np.array_equal(got, want)
+    # MFMA pre-selection widened to every list is exact; widened by 4 it is
+    # a valid choice and almost always the canonical one.
+    got = ivf.assign_lists(cpd, Xd, cfg.metric, coarse="bf16", widen=cfg.L, chunk=777).cpu().numpy()
+    assert np.array_equal(got, want)
+    got = ivf.assign_lists(cpd, Xd, cfg.metric, coarse="bf16", widen=4).cpu().numpy()
+    assert (got != want).mean() <= 0.01
+    lists = want.astype(np.int32)
+    codes = ivf.encode_codes(Xd, torch.from_numpy(index["cm"]).cuda(),
+                             torch.from_numpy(lists).cuda(),
+                             torch.from_numpy(index["codebooks"]).cuda()).cpu().numpy()
+    assert np.array_equal(codes, oracle.encode(rows, index["cm"], lists, index["codebooks"]))
+
+
+def test_gpu_trained_index_searches_well():
+    import paper_2511_03298_amd as ivf
+    from paper_2511_03298_amd.train import train_index_gpu
+    from workloads import exact_knn, recall_at_k
+    cfg, X, Q, nprobe, index, _, _ = case("c3s")
+    tr = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=1)
+    lens = np.diff(tr["list_offsets"])
+    assert lens.sum() == len(X) and lens.min() >= 0
+    ids_sorted = np.sort(tr["list_ids"].cpu().numpy())
+    assert np.array_equal(ids_sorted, np.arange(len(X)))
+    g = ivf.GpuIndex.from_index(tr, X)
+    ids, _ = g.search(Q, 16, cfg.k, cfg.R)
+    gt, _ = exact_knn(X, Q, cfg.k, cfg.metric)
+    assert recall_at_k(ids.cpu().numpy(), gt, cfg.k) >= 0.8
