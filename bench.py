@@ -169,12 +169,20 @@ def main():
     X, Q, nprobe = make_workload(cfg)
     log(f"generated in {time.time() - t0:.1f}s; training IVF-PQ (L={cfg.L}, m={cfg.m})")
     t0 = time.time()
-    index = train_index(X, cfg)
+    gpu_trained = cfg.n > 2_000_000
+    if gpu_trained:
+        # 10M-point shapes: assignment and encoding on the GPU (ivf_assign /
+        # ivf_encode); the host trainer would take many minutes.
+        from paper_2511_03298_amd.train import train_index_gpu
+        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index)
+    else:
+        index = train_index(X, cfg)
     lens = np.diff(index["list_offsets"])
-    log(f"trained in {time.time() - t0:.1f}s; list length mean {lens.mean():.0f} max {lens.max()}")
+    log(f"trained in {time.time() - t0:.1f}s ({'GPU' if gpu_trained else 'host'}); "
+        f"list length mean {lens.mean():.0f} max {lens.max()}")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not gpu_trained:
         log("timing the CPU oracle on the host cores")
         cpu = cpu_baseline(index, X, Q, nprobe, cfg.k, cfg.R)
         log(f"oracle: {cpu['value']} q/s on {cpu['cores']} cores")

@@ -640,6 +640,7 @@ ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries, int3
   IVF_HIP(launch_copy_probes(probes, nprobe, nq, max_nprobe, idx->t.L, w, s));
   st = run_scan_and_rerank(idx, queries, nq, max_nprobe, 1, rerank, o, w, nullptr, nullptr, s);
   if (st != IVF_OK) return st;
+  IVF_HIP(launch_sort_rows(w.cand, nq, rerank, s));
   IVF_HIP(hipMemcpyAsync(out_keys, w.cand, (size_t)nq * rerank * 8, hipMemcpyDeviceToDevice, s));
   return IVF_OK;
 }

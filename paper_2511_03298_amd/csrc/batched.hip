@@ -418,9 +418,6 @@ __global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
     n = block_compact_le(keys, n, block_kth(u, (uint32_t)R, &sc), &cnt);
     if (n > (uint32_t)R) n = (uint32_t)R;
   }
-  const uint32_t n2 = pow2_ceil(n > 0 ? n : 1);
-  for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
-  block_bitonic_sort(keys, n2);
   for (int i = tid; i < R; i += blockDim.x)
     cand[(size_t)q * R + i] = (uint32_t)i < n ? keys[i] : KEY_NONE;
 }

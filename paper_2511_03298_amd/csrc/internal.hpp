@@ -127,6 +127,7 @@ hipError_t launch_debug_luts(const Tables& t, const float* Q, int32_t nq, const 
 hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k, int32_t rerank,
                          const Workspace& w, int64_t* out_ids, float* out_dist, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_sort_rows(uint64_t* cand, int32_t nq, int32_t R, hipStream_t s);
 hipError_t launch_encode(const float* X, int64_t n, int32_t d, int32_t m, const float* cm,
                          const int32_t* lists, const float* codebooks, uint8_t* codes,
                          hipStream_t s);

@@ -84,8 +84,17 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
     }
   }
   __syncthreads();
-  const uint32_t n2 = pow2_ceil((uint32_t)R);
-  for (uint32_t i = R + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
+  // Top k: select the k smallest keys, then sort only those.
+  __shared__ SelectScratch sc;
+  __shared__ uint32_t cnt;
+  uint32_t n = (uint32_t)R;
+  if ((uint32_t)k < n) {
+    KeyUnion u{keys, n, nullptr, 0};
+    const uint64_t thr = block_kth(u, (uint32_t)k, &sc);
+    n = block_compact_le(keys, n, thr, &cnt);
+  }
+  const uint32_t n2 = pow2_ceil(n);
+  for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
   block_bitonic_sort(keys, n2);
   for (int i = tid; i < k; i += blockDim.x) {
     const uint64_t kk = i < R ? keys[i] : KEY_NONE;

@@ -233,11 +233,29 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
     }
     return;
   }
-  const uint32_t n2 = pow2_ceil(total > 0 ? total : 1);
-  for (uint32_t i = total + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
-  block_bitonic_sort(keys, n2);
+  // The pool in any order (the re-rank orders its own results; the parity
+  // export sorts it).
   for (int i = tid; i < R; i += blockDim.x)
     cand[(size_t)q * R + i] = (uint32_t)i < total ? keys[i] : KEY_NONE;
+}
+
+// Ascending order of every query's candidate keys (parity export only).
+__global__ void __launch_bounds__(256) sort_rows_kernel(uint64_t* __restrict__ cand, int32_t R) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);
+  const int q = blockIdx.x;
+  const uint32_t n2 = pow2_ceil((uint32_t)R);
+  for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x)
+    keys[i] = i < (uint32_t)R ? cand[(size_t)q * R + i] : KEY_NONE;
+  block_bitonic_sort(keys, n2);
+  for (int i = threadIdx.x; i < R; i += blockDim.x) cand[(size_t)q * R + i] = keys[i];
+}
+
+hipError_t launch_sort_rows(uint64_t* cand, int32_t nq, int32_t R, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(sort_rows_kernel, dim3(nq), dim3(256), (size_t)pow2_ceil((uint32_t)R) * 8, s,
+                     cand, R);
+  return hipGetLastError();
 }
 
 // Candidate-buffer slack beyond R (keys), large enough that a round of one
