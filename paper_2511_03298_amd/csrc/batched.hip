@@ -162,6 +162,39 @@ __device__ __forceinline__ void wave_build_lut(const Tables& t, const float* rq,
   constexpr int MP = W * 8;  // padded subspaces
   const int ln = lane_id();
   const int code = ln & 15;
+  if constexpr (MP <= 64) {
+    // Up to 16 entries per lane: keep them in registers, one pass.
+    constexpr int NR = MP / 4;
+    float T[NR];
+    float mx = 0.0f;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int j = 4 * r + (ln >> 4);
+      T[r] = j < t.m ? lut_entry(t, rq, cb_s, j, code) : 0.0f;
+      float v = T[r];
+      for (int s = 1; s < 16; s <<= 1) v = fminf(v, __shfl_xor(v, s));
+      if (code == 0 && j < t.m) lo_s[j] = v;
+      T[r] = T[r] - v;  // entry minus its subspace minimum (rounded once)
+      mx = fmaxf(mx, T[r]);
+    }
+    for (int s = 1; s < IVF_WAVE; s <<= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
+    const float rng = mx;
+    const bool live = rng > 0.0f;
+    const float sc = live ? 255.0f / rng : 0.0f;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int j = 4 * r + (ln >> 4);
+      uint16_t v = 0;
+      if (live && j < t.m) v = (uint16_t)fminf(rintf(T[r] * sc), 255.0f);
+      lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = v;
+    }
+    const float ls = wave_pairwise_sum(lo_s, t.m);
+    if (ln == 0) {
+      *outB = ls + bias;
+      *outDelta = live ? rng / 255.0f : 0.0f;
+    }
+    return;
+  }
   const int nr = (t.m + 3) / 4;
   float mx = 0.0f;
 #pragma unroll 1
