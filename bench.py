@@ -149,8 +149,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
-    ap.add_argument("--forms", default="plain",
+    ap.add_argument("--forms", default="plain:exact,batched:bf16",
                     help="comma list of form:coarse, e.g. plain:exact,batched:bf16")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuned schedule (paper_2511_03298_amd.tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -228,10 +230,22 @@ def main():
     log(f"points scanned per step {scanned} ({scanned / cfg.nq:.0f} per query); "
         f"batched scan kernel {scanned_main}")
 
-    results = []
+    runs = []
     for spec in args.forms.split(","):
         form, coarse = (spec.split(":") + ["exact"])[:2]
-        opts = ivf.make_opts(coarse=coarse, form=form)
+        runs.append(("fixed", ivf.make_opts(coarse=coarse, form=form)))
+    if not args.no_tune:
+        from paper_2511_03298_amd.tune import autotune
+        t0 = time.time()
+        topts, rep = autotune(g, Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, cache_path=None)
+        log(f"autotuned in {time.time() - t0:.1f}s over {len(rep['trials'])} schedules: "
+            f"{ivf.opts_dict(topts)} ({rep['best_ms']:.3f} ms)")
+        runs.append(("tuned", topts))
+
+    results = []
+    for label, opts in runs:
+        od = ivf.opts_dict(opts)
+        form, coarse = od["form"], od["coarse"]
         for _ in range(args.warmup):
             g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
         torch.cuda.synchronize()
@@ -250,11 +264,12 @@ def main():
         per = {k_: v / max(count, 1) for k_, v in stage_ms.items()}
         scan_ms = per["scan"]
         pts = scanned_main if form == "batched" else scanned
-        r = dict(form=form, coarse=coarse, qps=cfg.nq / (ms_step / 1000.0), ms_per_step=ms_step,
+        r = dict(form=form, coarse=coarse, schedule=label, opts=od,
+                 qps=cfg.nq / (ms_step / 1000.0), ms_per_step=ms_step,
                  recall_at_10=rec, stage_ms=per, scan_points=pts,
                  scan_gbs=pts * code_bytes / (scan_ms / 1e3) / 1e9 if scan_ms > 0 else None,
                  scan_tlookups=pts * cfg.m / (scan_ms / 1e3) / 1e12 if scan_ms > 0 else None)
-        log(f"{form}/{coarse}: {r['qps']:.0f} q/s, {ms_step:.3f} ms/step, recall@10 {rec:.4f}, "
+        log(f"{label} {form}/{coarse}: {r['qps']:.0f} q/s, {ms_step:.3f} ms/step, recall@10 {rec:.4f}, "
             f"stages {', '.join(f'{k_} {v:.3f}ms' for k_, v in per.items())}, scan kernel "
             f"{r['scan_gbs']:.0f} GB/s algorithmic, {r['scan_tlookups']:.2f} T lookups/s")
         results.append(r)
@@ -276,10 +291,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.config, args.config), "n": cfg.n,
                    "d": cfg.d, "nq": cfg.nq, "L": cfg.L, "m": cfg.m, "nprobe": list(cfg.nprobe),
-                   "k": cfg.k, "rerank": cfg.R, "form": best["form"], "coarse": best["coarse"]},
+                   "k": cfg.k, "rerank": cfg.R, "form": best["form"], "coarse": best["coarse"],
+                   "schedule": best["opts"]},
         "recall_at_10": round(best["recall_at_10"], 4),
         "forms": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()
-                   if k_ != "stage_ms"} | {"stage_ms": {s: round(x, 4) for s, x in r["stage_ms"].items()}}
+                   if k_ not in ("stage_ms", "opts")} |
+                  {"stage_ms": {s: round(x, 4) for s, x in r["stage_ms"].items()}}
                   for r in results],
         "roofline": roofline(args.config, cfg, best, code_bytes),
         "cpu_baseline": cpu,

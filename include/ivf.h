@@ -108,11 +108,15 @@ typedef struct {
                         every pointer) and replay it afterwards; needs a
                         non-default stream. Up to 8 graphs are cached per
                         index; per-stage profiling does not see replays.     */
-  int32_t chunk;     /* BATCHED work-item size in 64-point blocks; 0 = auto      */
-  int32_t reserved;
+  int32_t pool_cap;  /* plain scan (and the batched form's first-list pass):
+                        candidate buffer beyond R, in keys, multiple of 256,
+                        256..16384; 0 = auto. Larger = fewer pool reductions,
+                        more LDS per workgroup                                */
+  int32_t grid;      /* BATCHED: persistent workgroups per compute unit, 0..8;
+                        0 = auto (from the kernel's LDS footprint)            */
 } ivf_search_opts;
 
-/* Defaults: EXACT coarse, widen 2, PLAIN form, no graph, auto chunk. */
+/* Defaults: EXACT coarse, widen 2, PLAIN form, no graph, auto pool and grid. */
 void ivf_default_opts(ivf_search_opts* opts);
 
 /* Bytes of device memory ivf_build_tables needs for this index; 0 if the

@@ -50,7 +50,7 @@ class IndexDesc(ctypes.Structure):
 class SearchOpts(ctypes.Structure):
     _fields_ = [("coarse", ctypes.c_int32), ("widen", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("pool_cap", ctypes.c_int32), ("grid", ctypes.c_int32)]
 
 
 class TableLayout(ctypes.Structure):
@@ -118,12 +118,19 @@ def check(status: int):
 
 
 def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
-              use_graph: bool = False, chunk: int = 0) -> SearchOpts:
+              use_graph: bool = False, pool_cap: int = 0, grid: int = 0) -> SearchOpts:
     o = SearchOpts()
     lib().ivf_default_opts(ctypes.byref(o))
     o.coarse, o.widen, o.form = COARSE[coarse], int(widen), FORM[form]
-    o.use_graph, o.chunk = int(bool(use_graph)), int(chunk)
+    o.use_graph, o.pool_cap, o.grid = int(bool(use_graph)), int(pool_cap), int(grid)
     return o
+
+
+def opts_dict(o: SearchOpts) -> dict:
+    inv_c = {v: k for k, v in COARSE.items()}
+    inv_f = {v: k for k, v in FORM.items()}
+    return dict(coarse=inv_c[o.coarse], widen=o.widen, form=inv_f[o.form],
+                use_graph=bool(o.use_graph), pool_cap=o.pool_cap, grid=o.grid)
 
 
 def _ptr(t) -> Optional[int]:

@@ -144,7 +144,9 @@ ivf_status check_opts(const ivf_search_opts& o) {
     return fail(IVF_ERR_INVALID_ARG, "opts.form out of range");
   if (o.use_graph != 0 && o.use_graph != 1)
     return fail(IVF_ERR_INVALID_ARG, "opts.use_graph must be 0 or 1");
-  if (o.chunk < 0) return fail(IVF_ERR_INVALID_ARG, "opts.chunk must be >= 0");
+  if (o.pool_cap < 0 || o.pool_cap > 16384 || o.pool_cap % 256)
+    return fail(IVF_ERR_INVALID_ARG, "opts.pool_cap must be 0 or a multiple of 256 up to 16384");
+  if (o.grid < 0 || o.grid > 8) return fail(IVF_ERR_INVALID_ARG, "opts.grid must be in 0..8");
   return IVF_OK;
 }
 
@@ -193,6 +195,8 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
     w.q_lowp = (void*)take(nq_pad * t.d_pad * 4);
     w.q_scale = (float*)take(nq_pad * 4);
   }
+  w.pool_cap = o.pool_cap;
+  w.grid = o.grid;
   if (o.form == IVF_FORM_BATCHED) {
     w.spill_cap = batched_spill_cap(rerank);
     w.p1 = (int32_t*)take(nqs * 4);
@@ -222,8 +226,8 @@ void ivf_default_opts(ivf_search_opts* o) {
   o->widen = 2;
   o->form = IVF_FORM_PLAIN;
   o->use_graph = 0;
-  o->chunk = 0;
-  o->reserved = 0;
+  o->pool_cap = 0;
+  o->grid = 0;
 }
 
 const char* ivf_last_error(void) { return g_last_error.c_str(); }
@@ -377,11 +381,11 @@ ivf_status ivf_profile_read(ivf_index* idx, float* ms, int32_t* count) {
 
 size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq, int32_t max_nprobe,
                                   int32_t k, int32_t rerank, const ivf_search_opts* opts) {
-  if (check_search(idx, nq, max_nprobe, k, rerank) != IVF_OK) return 0;
   ivf_search_opts o;
   ivf_default_opts(&o);
   if (opts) o = *opts;
   if (check_opts(o) != IVF_OK) return 0;
+  if (check_search(idx, nq, max_nprobe, k, rerank) != IVF_OK) return 0;
   return plan_workspace(idx->t, nq, max_nprobe, k, rerank, o, nullptr).total;
 }
 
@@ -498,7 +502,8 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
     if (!s) return fail(IVF_ERR_INVALID_ARG, "graph capture needs a non-default stream");
     std::vector<uint64_t> key = {(uint64_t)nq, (uint64_t)max_nprobe, (uint64_t)k,
                                  (uint64_t)rerank, (uint64_t)o.coarse, (uint64_t)o.widen,
-                                 (uint64_t)o.form, (uint64_t)o.chunk, (uint64_t)(uintptr_t)queries,
+                                 (uint64_t)o.form, (uint64_t)o.pool_cap, (uint64_t)o.grid,
+                                 (uint64_t)(uintptr_t)queries,
                                  (uint64_t)(uintptr_t)nprobe, (uint64_t)(uintptr_t)workspace,
                                  (uint64_t)(uintptr_t)out_ids, (uint64_t)(uintptr_t)out_dist};
     ivf_index* mi = const_cast<ivf_index*>(idx);

@@ -499,8 +499,9 @@ static hipError_t launch_main_w(const Tables& t, const float* Q, int32_t max_npr
   const size_t lds = (size_t)IVF_NWAVES * t.d * 4 +
                      (cb_in_lds<W>() ? (size_t)t.m * KSUB * t.dsub * 4 : 0);
   const size_t total = sizeof(BatchShared<W>) + lds;
-  const int per_cu = total <= 24 * 1024 ? 6 : total <= 36 * 1024 ? 4 : total <= 52 * 1024 ? 3
-                   : total <= 76 * 1024 ? 2 : 1;
+  int per_cu = total <= 24 * 1024 ? 6 : total <= 36 * 1024 ? 4 : total <= 52 * 1024 ? 3
+             : total <= 76 * 1024 ? 2 : 1;
+  if (w.grid > 0) per_cu = w.grid;
   hipLaunchKernelGGL(batched_scan_kernel<W>, dim3(cus * per_cu), dim3(256), lds, s, t, Q,
                      max_nprobe, w.bias, w.thr, w.list_start, w.item_start, w.item_list, w.pairs,
                      w.queue, w.spill_cnt, w.spill, w.spill_cap);

@@ -84,6 +84,8 @@ struct Workspace {
   float* q_scale;       // [nq_pad]
   size_t total;
   int32_t spill_cap;
+  int32_t pool_cap;  // plain scan candidate buffer beyond R (0 = auto)
+  int32_t grid;      // batched workgroups per CU (0 = auto)
 };
 
 int32_t batched_spill_cap(int32_t rerank);

@@ -258,12 +258,12 @@ hipError_t launch_sort_rows(uint64_t* cand, int32_t nq, int32_t R, hipStream_t s
   return hipGetLastError();
 }
 
-// Candidate-buffer slack beyond R (keys), large enough that a round of one
-// block per wave never overflows and the final sort fits.
-inline int32_t scan_cap(int32_t R) {
-  int32_t p2 = (int32_t)pow2_ceil((uint32_t)R);
-  int32_t cap = 1024;
-  if (p2 - R > cap) cap = p2 - R;
+// Candidate-buffer slack beyond R (keys): the requested size (default 1024),
+// at least one round of one block per wave.
+inline int32_t scan_cap(int32_t R, int32_t requested) {
+  (void)R;
+  int32_t cap = requested > 0 ? requested : 1024;
+  if (cap < IVF_BLOCK) cap = IVF_BLOCK;
   return cap;
 }
 
@@ -272,7 +272,7 @@ static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t n
                                       int32_t max_nprobe, int32_t R, const Workspace& w,
                                       int32_t* p1_out, uint64_t* thr_out, const int32_t* only,
                                       hipStream_t s) {
-  const int32_t cap = scan_cap(R);
+  const int32_t cap = scan_cap(R, w.pool_cap);
   size_t lds = (size_t)(R + cap) * 8 + (size_t)t.m_pad * KSUB * 4 + (size_t)t.d * 4;
   hipLaunchKernelGGL(scan_plain_kernel<W>, dim3(nq), dim3(256), lds, s, t, Q, nq, max_nprobe, R,
                      cap, w.probes, w.nprobe_eff, w.bias, w.cand, p1_out, thr_out, only);

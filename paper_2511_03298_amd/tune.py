@@ -1,0 +1,116 @@
+"""Autotuner for the search schedule.
+
+For one index and one query-batch shape it measures a set of schedules on the
+device and keeps the fastest admissible one:
+  * form: plain (one workgroup per query) or batched (persistent list-major);
+  * coarse precision: exact FP32, or FP32/BF16/FP8 MFMA pre-selection with
+    widening 2 or 4 -- admitted only when its probe sets agree with the exact
+    ones on at least `min_agree` of the queries (results are otherwise
+    bit-identical, the forms only change the schedule);
+  * plain candidate-buffer size (pool_cap) and batched persistent grid size.
+Results are cached in a JSON file keyed by the device architecture and the
+shape (n, d, L, m, metric, nq, max_nprobe, k, rerank).
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Optional
+
+from . import COARSE, GpuIndex, make_opts, opts_dict
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ivfpq", "tune.json")
+
+
+def shape_key(g: GpuIndex, nq: int, max_nprobe: int, k: int, rerank: int) -> str:
+    import torch
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName
+    return f"{arch}|n{g.n}|d{g.d}|L{g.L}|m{g.m}|{g.metric}|nq{nq}|p{max_nprobe}|k{k}|R{rerank}"
+
+
+def default_space():
+    space = []
+    for coarse, widen in (("exact", 2), ("bf16", 2), ("bf16", 4), ("fp8", 4), ("f32", 2)):
+        for pool in (0, 2048, 4096):
+            space.append(dict(form="plain", coarse=coarse, widen=widen, pool_cap=pool))
+        for grid in (0, 2, 3, 4):
+            for pool in (0, 4096):
+                space.append(dict(form="batched", coarse=coarse, widen=widen, grid=grid,
+                                  pool_cap=pool))
+    return space
+
+
+def _time(g, Qd, npd, k, rerank, max_nprobe, opts, ids, dist, reps):
+    import torch
+    g.search(Qd, npd, k, rerank, max_nprobe=max_nprobe, opts=opts, out=(ids, dist))
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        g.search(Qd, npd, k, rerank, max_nprobe=max_nprobe, opts=opts, out=(ids, dist))
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def autotune(g: GpuIndex, queries, nprobe, k: int, rerank: int,
+             max_nprobe: Optional[int] = None, space=None, reps: int = 3,
+             min_agree: float = 0.995, cache_path: Optional[str] = DEFAULT_CACHE,
+             refresh: bool = False, log=None):
+    """Return (opts, report) for the fastest admissible schedule."""
+    import torch
+    Qd = g._queries(queries)
+    nq = Qd.shape[0]
+    npd = g._nprobe(nprobe, nq)
+    if max_nprobe is None:
+        max_nprobe = max(1, min(int(npd.max().item()), g.L))
+    key = shape_key(g, nq, max_nprobe, k, rerank)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+    if not refresh and key in cache:
+        best = cache[key]["best"]
+        return make_opts(**best), dict(cache[key], cached=True)
+
+    exact = g.debug_probes(Qd, npd, max_nprobe=max_nprobe).cpu()
+    agree = {}
+    ids = torch.empty((nq, k), dtype=torch.int64, device=g.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=g.device)
+    trials = []
+    t0 = time.time()
+    for cand in space or default_space():
+        ck = (cand["coarse"], cand["widen"])
+        if ck not in agree:
+            if cand["coarse"] == "exact":
+                agree[ck] = 1.0
+            else:
+                o = make_opts(coarse=cand["coarse"], widen=cand["widen"])
+                p = g.debug_probes(Qd, npd, max_nprobe=max_nprobe, opts=o).cpu()
+                agree[ck] = float((p == exact).all(dim=1).float().mean())
+        if agree[ck] < min_agree:
+            continue
+        opts = make_opts(**cand)
+        ms = _time(g, Qd, npd, k, rerank, max_nprobe, opts, ids, dist, reps)
+        trials.append(dict(cand, ms=ms, probe_agreement=agree[ck]))
+        if log:
+            log(f"tune {cand}: {ms:.3f} ms")
+    best = min(trials, key=lambda r: r["ms"])
+    best_opts = {k_: best[k_] for k_ in ("form", "coarse", "widen", "pool_cap", "grid") if k_ in best}
+    report = dict(key=key, best=opts_dict(make_opts(**best_opts)), best_ms=best["ms"],
+                  trials=trials, seconds=round(time.time() - t0, 2))
+    if cache_path:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        cache[key] = report
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, cache_path)
+    return make_opts(**best_opts), dict(report, cached=False)
+
+
+__all__ = ["autotune", "default_space", "shape_key", "DEFAULT_CACHE", "COARSE"]

@@ -435,3 +435,23 @@ def test_gpu_trained_index_searches_well():
     ids, _ = g.search(Q, 16, cfg.k, cfg.R)
     gt, _ = exact_knn(X, Q, cfg.k, cfg.metric)
     assert recall_at_k(ids.cpu().numpy(), gt, cfg.k) >= 0.8
+
+
+def test_autotuner_picks_measured_schedule_and_caches(tmp_path):
+    import paper_2511_03298_amd as ivf
+    from paper_2511_03298_amd.tune import autotune
+    cfg, X, Q, nprobe, index, g, res = case("c2s")
+    space = [dict(form="plain", coarse="exact", widen=2, pool_cap=0),
+             dict(form="batched", coarse="exact", widen=2, grid=2),
+             dict(form="batched", coarse="bf16", widen=4, grid=0)]
+    path = str(tmp_path / "tune.json")
+    opts, rep = autotune(g, Q, nprobe, cfg.k, cfg.R, space=space, reps=2, cache_path=path)
+    assert not rep["cached"] and len(rep["trials"]) >= 2
+    assert rep["best_ms"] == min(t["ms"] for t in rep["trials"])
+    opts2, rep2 = autotune(g, Q, nprobe, cfg.k, cfg.R, space=space, cache_path=path)
+    assert rep2["cached"] and ivf.opts_dict(opts2) == ivf.opts_dict(opts)
+    # The tuned schedule gives the same results as the plain exact one.
+    a = g.search(Q, nprobe, cfg.k, cfg.R)
+    b = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+    if ivf.opts_dict(opts)["coarse"] == "exact":
+        assert torch.equal(a[0], b[0])
