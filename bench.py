@@ -150,7 +150,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
     ap.add_argument("--forms", default="plain:exact,batched:bf16",
-                    help="comma list of form:coarse, e.g. plain:exact,batched:bf16")
+                    help="comma list of form:coarse[:rN], e.g. plain:exact,batched:bf16:r3 "
+                         "(rN: N threshold-tightening rounds of the batched form)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuned schedule (paper_2511_03298_amd.tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -232,8 +233,10 @@ def main():
 
     runs = []
     for spec in args.forms.split(","):
-        form, coarse = (spec.split(":") + ["exact"])[:2]
-        runs.append(("fixed", ivf.make_opts(coarse=coarse, form=form)))
+        parts = spec.split(":")
+        form, coarse = (parts + ["exact"])[:2]
+        rounds = int(parts[2][1:]) if len(parts) > 2 and parts[2].startswith("r") else 0
+        runs.append(("fixed", ivf.make_opts(coarse=coarse, form=form, rounds=rounds)))
     if not args.no_tune:
         from paper_2511_03298_amd.tune import autotune
         t0 = time.time()

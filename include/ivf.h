@@ -114,6 +114,11 @@ typedef struct {
                         more LDS per workgroup                                */
   int32_t grid;      /* BATCHED: persistent workgroups per compute unit, 0..8;
                         0 = auto (from the kernel's LDS footprint)            */
+  int32_t rounds;    /* BATCHED: list-major rounds over probe ranks [0,4),
+                        [4,16), [16,64), ... (the last takes the rest), each
+                        ending with a merge that tightens the per-query
+                        threshold; 1..8, 0 = auto (1)                         */
+  int32_t reserved;  /* must be 0 */
 } ivf_search_opts;
 
 /* Defaults: EXACT coarse, widen 2, PLAIN form, no graph, auto pool and grid. */
@@ -224,11 +229,13 @@ int32_t ivf_get_device_error(const ivf_index* idx, void* workspace,
 /* Per-stage timing of ivf_search / ivf_search_with_probes. While enabled,
  * every search records HIP events on its stream around its stages
  * (IVF_STAGE_*): coarse scoring, probe selection, scan preparation (IP
- * biases; batched form: first-list pass and work-list build), the scan
- * kernel itself, the merge (batched form), the re-rank. ivf_profile_read
- * waits for the last recorded event and returns, per stage, the summed
- * milliseconds and the number of searches since the previous read (then
- * resets). At most 256 searches are kept between reads. */
+ * biases; batched form: first-list pass and each round's work-list build),
+ * the scan kernel itself (batched: every round's), the merges (batched
+ * form), the re-rank. ivf_profile_read waits for the last recorded event and
+ * returns, per stage, the summed milliseconds and the number of completed
+ * searches since the previous read (then resets). At most 64 searches are
+ * kept between reads (older ones are dropped). Graph replays
+ * (opts.use_graph) are not profiled. */
 enum { IVF_STAGE_COARSE = 0, IVF_STAGE_SELECT = 1, IVF_STAGE_PREP = 2,
        IVF_STAGE_SCAN = 3, IVF_STAGE_MERGE = 4, IVF_STAGE_RERANK = 5,
        IVF_NSTAGES = 6 };

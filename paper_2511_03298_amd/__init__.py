@@ -50,7 +50,8 @@ class IndexDesc(ctypes.Structure):
 class SearchOpts(ctypes.Structure):
     _fields_ = [("coarse", ctypes.c_int32), ("widen", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("pool_cap", ctypes.c_int32), ("grid", ctypes.c_int32)]
+                ("pool_cap", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class TableLayout(ctypes.Structure):
@@ -118,11 +119,13 @@ def check(status: int):
 
 
 def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
-              use_graph: bool = False, pool_cap: int = 0, grid: int = 0) -> SearchOpts:
+              use_graph: bool = False, pool_cap: int = 0, grid: int = 0,
+              rounds: int = 0) -> SearchOpts:
     o = SearchOpts()
     lib().ivf_default_opts(ctypes.byref(o))
     o.coarse, o.widen, o.form = COARSE[coarse], int(widen), FORM[form]
     o.use_graph, o.pool_cap, o.grid = int(bool(use_graph)), int(pool_cap), int(grid)
+    o.rounds = int(rounds)
     return o
 
 
@@ -130,7 +133,8 @@ def opts_dict(o: SearchOpts) -> dict:
     inv_c = {v: k for k, v in COARSE.items()}
     inv_f = {v: k for k, v in FORM.items()}
     return dict(coarse=inv_c[o.coarse], widen=o.widen, form=inv_f[o.form],
-                use_graph=bool(o.use_graph), pool_cap=o.pool_cap, grid=o.grid)
+                use_graph=bool(o.use_graph), pool_cap=o.pool_cap, grid=o.grid,
+                rounds=o.rounds)
 
 
 def _ptr(t) -> Optional[int]:

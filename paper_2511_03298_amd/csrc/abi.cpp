@@ -12,13 +12,17 @@
 
 using namespace ivf;
 
-// Event pairs (start, stop) per stage for up to RING searches.
+// Per search a timeline of stage marks (stage, event); the time between two
+// consecutive marks is attributed to the first one's stage. RING searches
+// are kept between reads.
 struct ivf_profile {
-  static constexpr int RING = 256;
+  static constexpr int RING = 64;
+  static constexpr int MARKS = 32;
   bool on = false;
   int head = 0, count = 0;
-  hipEvent_t ev[RING][IVF_NSTAGES + 1] = {};
-  bool used[RING][IVF_NSTAGES + 1] = {};  // boundary recorded in this search
+  hipEvent_t ev[RING][MARKS] = {};
+  int stage[RING][MARKS] = {};
+  int nmarks[RING] = {};
   int cur = -1;
 };
 
@@ -147,6 +151,8 @@ ivf_status check_opts(const ivf_search_opts& o) {
   if (o.pool_cap < 0 || o.pool_cap > 16384 || o.pool_cap % 256)
     return fail(IVF_ERR_INVALID_ARG, "opts.pool_cap must be 0 or a multiple of 256 up to 16384");
   if (o.grid < 0 || o.grid > 8) return fail(IVF_ERR_INVALID_ARG, "opts.grid must be in 0..8");
+  if (o.rounds < 0 || o.rounds > 8) return fail(IVF_ERR_INVALID_ARG, "opts.rounds must be in 0..8");
+  if (o.reserved != 0) return fail(IVF_ERR_INVALID_ARG, "opts.reserved must be 0");
   return IVF_OK;
 }
 
@@ -228,6 +234,8 @@ void ivf_default_opts(ivf_search_opts* o) {
   o->use_graph = 0;
   o->pool_cap = 0;
   o->grid = 0;
+  o->rounds = 0;
+  o->reserved = 0;
 }
 
 const char* ivf_last_error(void) { return g_last_error.c_str(); }
@@ -358,22 +366,21 @@ ivf_status ivf_profile_read(ivf_index* idx, float* ms, int32_t* count) {
   ivf_profile* p = idx->prof;
   if (!p || p->count == 0) return IVF_OK;
   const int first = (p->head - p->count + ivf_profile::RING) % ivf_profile::RING;
-  const int last = (p->head - 1 + ivf_profile::RING) % ivf_profile::RING;
-  IVF_HIP(hipEventSynchronize(p->ev[last][IVF_NSTAGES]));
+  int done = 0;
   for (int c = 0; c < p->count; ++c) {
     const int slot = (first + c) % ivf_profile::RING;
-    // A stage runs from its boundary to the next recorded one.
-    for (int i = 0; i < IVF_NSTAGES; ++i) {
-      if (!p->used[slot][i]) continue;
-      int j = i + 1;
-      while (j < IVF_NSTAGES && !p->used[slot][j]) ++j;
-      if (!p->used[slot][j]) continue;
+    const int n = p->nmarks[slot];
+    if (n < 2 || p->stage[slot][n - 1] != IVF_NSTAGES) continue;  // incomplete
+    IVF_HIP(hipEventSynchronize(p->ev[slot][n - 1]));
+    for (int k = 0; k + 1 < n; ++k) {
       float t = 0.0f;
-      IVF_HIP(hipEventElapsedTime(&t, p->ev[slot][i], p->ev[slot][j]));
-      ms[i] += t;
+      IVF_HIP(hipEventElapsedTime(&t, p->ev[slot][k], p->ev[slot][k + 1]));
+      const int st = p->stage[slot][k];
+      if (st >= 0 && st < IVF_NSTAGES) ms[st] += t;
     }
+    ++done;
   }
-  *count = p->count;
+  *count = done;
   p->count = 0;
   p->cur = -1;
   return IVF_OK;
@@ -393,31 +400,33 @@ size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq, int32_t max_
 
 namespace {
 
-// Stage marks: mark(idx, s, i) records boundary i (stage i starts; stage
-// i-1 ends) of the current search when profiling is on.
+// Stage marks of the current search (no-ops unless profiling is on).
 hipError_t prof_begin(const ivf_index* idx) {
   ivf_profile* p = idx->prof;
   if (!p || !p->on) return hipSuccess;
-  int slot = p->head;
+  const int slot = p->head;
   p->head = (p->head + 1) % ivf_profile::RING;
   if (p->count < ivf_profile::RING) ++p->count;
-  for (int i = 0; i <= IVF_NSTAGES; ++i) {
-    if (!p->ev[slot][i]) {
-      hipError_t e = hipEventCreate(&p->ev[slot][i]);
-      if (e != hipSuccess) return e;
-    }
-  }
-  for (int i = 0; i <= IVF_NSTAGES; ++i) p->used[slot][i] = false;
+  p->nmarks[slot] = 0;
   p->cur = slot;
   return hipSuccess;
 }
 
-hipError_t prof_mark(const ivf_index* idx, hipStream_t s, int boundary) {
+// Time from now on counts for `stage`; IVF_NSTAGES ends the search.
+hipError_t prof_mark(const ivf_index* idx, hipStream_t s, int stage) {
   ivf_profile* p = idx->prof;
   if (!p || !p->on || p->cur < 0) return hipSuccess;
-  p->used[p->cur][boundary] = true;
-  hipError_t e = hipEventRecord(p->ev[p->cur][boundary], s);
-  if (boundary == IVF_NSTAGES) p->cur = -1;  // this search is complete
+  const int slot = p->cur;
+  const int k = p->nmarks[slot];
+  if (k >= ivf_profile::MARKS) return hipSuccess;
+  if (!p->ev[slot][k]) {
+    hipError_t e = hipEventCreate(&p->ev[slot][k]);
+    if (e != hipSuccess) return e;
+  }
+  p->stage[slot][k] = stage;
+  p->nmarks[slot] = k + 1;
+  hipError_t e = hipEventRecord(p->ev[slot][k], s);
+  if (stage == IVF_NSTAGES) p->cur = -1;  // this search is complete
   return e;
 }
 
@@ -427,6 +436,7 @@ ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, in
                         size_t workspace_bytes, ivf_search_opts* o, Workspace* w) {
   ivf_status st = check_search(idx, nq, max_nprobe, k, rerank);
   if (st != IVF_OK) return st;
+  if (idx->prof) idx->prof->cur = -1;  // only entries that call prof_begin are timed
   ivf_default_opts(o);
   if (opts) *o = *opts;
   st = check_opts(*o);
@@ -449,11 +459,23 @@ ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, int32_t nq,
   IVF_HIP(prof_mark(idx, s, IVF_STAGE_PREP));
   IVF_HIP(launch_bias(t, Q, nq, max_nprobe, w, s));
   if (o.form == IVF_FORM_BATCHED) {
-    IVF_HIP(launch_batched_prep(t, Q, nq, max_nprobe, rerank, w, s));
-    IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
-    IVF_HIP(launch_batched_main(t, Q, nq, max_nprobe, rerank, w, s));
-    IVF_HIP(prof_mark(idx, s, IVF_STAGE_MERGE));
-    IVF_HIP(launch_batched_merge(t, Q, nq, max_nprobe, rerank, w, s));
+    // Rounds over probe ranks [b_r, b_{r+1}) with b = 0, 4, 16, 64, ...:
+    // each round's merge publishes a tighter threshold for the next.
+    const int rounds = o.rounds > 0 ? o.rounds : 1;
+    IVF_HIP(launch_batched_first(t, Q, nq, max_nprobe, rerank, w, s));
+    int lo = 0;
+    for (int r = 0; r < rounds; ++r) {
+      const int hi = r + 1 == rounds ? max_nprobe : (lo == 0 ? 4 : lo * 4);
+      if (r > 0) IVF_HIP(prof_mark(idx, s, IVF_STAGE_PREP));
+      IVF_HIP(launch_batched_pairs(t, nq, max_nprobe, lo, hi, w, s));
+      IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
+      IVF_HIP(launch_batched_main(t, Q, nq, max_nprobe, rerank, w, s));
+      IVF_HIP(prof_mark(idx, s, IVF_STAGE_MERGE));
+      IVF_HIP(launch_batched_merge(t, nq, rerank, w, s));
+      lo = hi;
+      if (lo >= max_nprobe) break;
+    }
+    IVF_HIP(launch_batched_redo(t, Q, nq, max_nprobe, rerank, w, s));
   } else {
     IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
     IVF_HIP(launch_scan_plain(t, Q, nq, max_nprobe, rerank, w, s));
@@ -503,6 +525,7 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
     std::vector<uint64_t> key = {(uint64_t)nq, (uint64_t)max_nprobe, (uint64_t)k,
                                  (uint64_t)rerank, (uint64_t)o.coarse, (uint64_t)o.widen,
                                  (uint64_t)o.form, (uint64_t)o.pool_cap, (uint64_t)o.grid,
+                                 (uint64_t)o.rounds,
                                  (uint64_t)(uintptr_t)queries,
                                  (uint64_t)(uintptr_t)nprobe, (uint64_t)(uintptr_t)workspace,
                                  (uint64_t)(uintptr_t)out_ids, (uint64_t)(uintptr_t)out_dist};

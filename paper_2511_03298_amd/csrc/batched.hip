@@ -6,13 +6,16 @@
 //   phase 1  per query, the plain scan of its first probed lists until at
 //            least R points are seen: pool P1 and threshold thr = R-th key
 //            (no key above thr can enter the final pool);
-//   phase 2  the remaining (query, list) pairs are grouped by list into
-//            work items of up to 16 queries; persistent workgroups pull items
-//            from an atomic counter, build the 16 queries' tables, stream the
-//            list's code blocks once, and append every key <= thr of its
-//            query to a per-query survivor buffer;
-//   merge    per query, the R smallest keys of P1 and its survivors. A query
-//            whose buffer overflowed is recomputed by the plain scan.
+//   rounds   the remaining (query, list) pairs, restricted to a range of
+//            probe ranks per round, are grouped by list into work items of
+//            up to 16 queries; persistent workgroups pull items from an
+//            atomic counter, build the 16 queries' tables, stream the list's
+//            code blocks once, and append every key <= thr of its query to a
+//            per-query survivor buffer;
+//   merge    after each round, per query, the R smallest keys of the pool and
+//            its survivors become the new pool and its R-th key the new thr,
+//            so later rounds keep fewer survivors. A query whose buffer
+//            overflowed is recomputed by the plain scan at the end.
 //
 // Table layout for the scan: entry (query g, subspace j, code c) is a u16 at
 // ((j*2 + g/8)*16 + c)*8 + g%8. The 16 rows of one (j, half) span 256 bytes,
@@ -29,17 +32,28 @@ constexpr int BG = 16;  // queries per work item
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------
-// Work list: (query, probe slot) pairs of phase 2 grouped by list.
+// Work list: (query, probe slot) pairs of one round grouped by list. A pair
+// belongs to the round [lo, hi) when p1[q] <= p < nprobe_eff[q], lo <= p < hi
+// and the query has not overflowed.
 // ---------------------------------------------------------------------------
 
 constexpr int PAIR_CHUNK = 4096;  // (query, probe) entries per workgroup
+
+struct RoundSel {
+  const int32_t* nprobe_eff;
+  const int32_t* p1;
+  const int32_t* redo;
+  int32_t lo, hi;
+  __device__ __forceinline__ bool operator()(int q, int p) const {
+    return p >= lo && p < hi && p >= p1[q] && p < nprobe_eff[q] && redo[q] == 0;
+  }
+};
 
 // Per-list counts of phase-2 pairs: a workgroup histograms its chunk in LDS
 // and adds each non-zero bin to the global count once.
 __global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t max_nprobe, int32_t L,
                                                           const int32_t* __restrict__ probes,
-                                                          const int32_t* __restrict__ nprobe_eff,
-                                                          const int32_t* __restrict__ p1,
+                                                          RoundSel sel,
                                                           int32_t* __restrict__ cnt) {
   extern __shared__ int32_t hist[];  // [L]
   for (int l = threadIdx.x; l < L; l += blockDim.x) hist[l] = 0;
@@ -48,7 +62,7 @@ __global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t ma
   const int64_t b = (int64_t)blockIdx.x * PAIR_CHUNK;
   for (int64_t i = b + threadIdx.x; i < b + PAIR_CHUNK && i < n; i += blockDim.x) {
     const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
-    if (p >= p1[q] && p < nprobe_eff[q]) atomicAdd(&hist[probes[i]], 1);
+    if (sel(q, p)) atomicAdd(&hist[probes[i]], 1);
   }
   __syncthreads();
   for (int l = threadIdx.x; l < L; l += blockDim.x)
@@ -100,8 +114,7 @@ __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, const int32
 // one range for its whole chunk, then places entries with LDS atomics.
 __global__ void __launch_bounds__(256) pairs_fill_kernel(int32_t nq, int32_t max_nprobe, int32_t L,
                                                          const int32_t* __restrict__ probes,
-                                                         const int32_t* __restrict__ nprobe_eff,
-                                                         const int32_t* __restrict__ p1,
+                                                         RoundSel sel,
                                                          const int32_t* __restrict__ list_start,
                                                          int32_t* __restrict__ cursor,
                                                          int32_t* __restrict__ pairs) {
@@ -112,7 +125,7 @@ __global__ void __launch_bounds__(256) pairs_fill_kernel(int32_t nq, int32_t max
   const int64_t b = (int64_t)blockIdx.x * PAIR_CHUNK;
   for (int64_t i = b + threadIdx.x; i < b + PAIR_CHUNK && i < n; i += blockDim.x) {
     const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
-    if (p >= p1[q] && p < nprobe_eff[q]) atomicAdd(&hist[probes[i]], 1);
+    if (sel(q, p)) atomicAdd(&hist[probes[i]], 1);
   }
   __syncthreads();
   for (int l = threadIdx.x; l < L; l += blockDim.x)
@@ -120,7 +133,7 @@ __global__ void __launch_bounds__(256) pairs_fill_kernel(int32_t nq, int32_t max
   __syncthreads();
   for (int64_t i = b + threadIdx.x; i < b + PAIR_CHUNK && i < n; i += blockDim.x) {
     const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
-    if (p >= p1[q] && p < nprobe_eff[q]) {
+    if (sel(q, p)) {
       const int pos = atomicAdd(&hist[probes[i]], 1);
       pairs[2 * pos] = q;
       pairs[2 * pos + 1] = p;
@@ -413,7 +426,10 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Merge: pool of phase 1 plus survivors -> the R smallest keys.
+// Merge after a round: pool plus survivors -> the R smallest keys, and their
+// largest as the next round's threshold. The pool is full whenever survivors
+// exist (the first pass stops only after R points, or at the last list), and
+// keys are unique, so exactly R keys remain.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
@@ -421,6 +437,7 @@ __global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
                                                     const int32_t* __restrict__ spill_cnt,
                                                     const uint64_t* __restrict__ spill,
                                                     uint64_t* __restrict__ cand,
+                                                    uint64_t* __restrict__ thr,
                                                     int32_t* __restrict__ redo) {
   extern __shared__ __align__(16) unsigned char dyn[];
   uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);  // [pow2(R + cap)]
@@ -428,13 +445,11 @@ __global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
   __shared__ uint32_t cnt;
   const int q = blockIdx.x, tid = threadIdx.x;
   const int ns = spill_cnt[q];
-  if (tid == 0) redo[q] = 0;
-  if (nprobe_eff[q] < 0) return;
+  if (nprobe_eff[q] < 0 || redo[q] != 0 || ns == 0) return;  // uniform
   if (ns > cap) {
-    if (tid == 0) redo[q] = 1;
+    if (tid == 0) redo[q] = 1;  // recomputed at the end; skipped from now on
     return;
   }
-  uint32_t n = 0;
   if (tid == 0) cnt = 0;
   __syncthreads();
   for (int i = tid; i < R; i += blockDim.x) {
@@ -442,17 +457,20 @@ __global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
     wave_append(k != KEY_NONE, k, keys, &cnt);
   }
   __syncthreads();
-  n = cnt;
+  uint32_t n = cnt;
   for (int i = tid; i < ns; i += blockDim.x) keys[n + i] = spill[(size_t)q * cap + i];
   __syncthreads();
   n += (uint32_t)ns;
+  uint64_t kth = KEY_NONE;
   if (n > (uint32_t)R) {
     KeyUnion u{keys, n, nullptr, 0};
-    n = block_compact_le(keys, n, block_kth(u, (uint32_t)R, &sc), &cnt);
+    kth = block_kth(u, (uint32_t)R, &sc);
+    n = block_compact_le(keys, n, kth, &cnt);
     if (n > (uint32_t)R) n = (uint32_t)R;
   }
   for (int i = tid; i < R; i += blockDim.x)
     cand[(size_t)q * R + i] = (uint32_t)i < n ? keys[i] : KEY_NONE;
+  if (tid == 0 && n == (uint32_t)R && kth != KEY_NONE) thr[q] = kth;
 }
 
 // ---------------------------------------------------------------------------
@@ -468,25 +486,32 @@ int32_t batched_spill_cap(int32_t R) {
   return c;
 }
 
-hipError_t launch_batched_prep(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
-                               int32_t R, const Workspace& w, hipStream_t s) {
+hipError_t launch_batched_first(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                                int32_t R, const Workspace& w, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  hipError_t e;
+  if ((e = launch_fill_u32((uint32_t*)w.redo, 0u, (size_t)nq, s)) != hipSuccess) return e;
+  // First lists per query -> pool, threshold, first probe rank of the rounds.
+  return launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, w.p1, w.thr, nullptr, s);
+}
+
+hipError_t launch_batched_pairs(const Tables& t, int32_t nq, int32_t max_nprobe, int32_t lo,
+                                int32_t hi, const Workspace& w, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   hipError_t e;
   if ((e = launch_fill_u32((uint32_t*)w.list_cnt, 0u, (size_t)t.L, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32((uint32_t*)w.spill_cnt, 0u, (size_t)nq, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(w.queue, 0u, 4, s)) != hipSuccess) return e;
-  // Phase 1: first lists per query -> pool, threshold, first probe of phase 2.
-  if ((e = launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, w.p1, w.thr, nullptr, s)) != hipSuccess)
-    return e;
+  const RoundSel sel{w.nprobe_eff, w.p1, w.redo, lo, hi};
   const int64_t np_total = (int64_t)nq * max_nprobe;
   const unsigned g1 = (unsigned)((np_total + PAIR_CHUNK - 1) / PAIR_CHUNK);
   const size_t hist_lds = (size_t)t.L * 4;
   hipLaunchKernelGGL(pairs_count_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
-                     w.probes, w.nprobe_eff, w.p1, w.list_cnt);
+                     w.probes, sel, w.list_cnt);
   hipLaunchKernelGGL(pairs_scan_kernel, dim3(1), dim3(1024), 0, s, t.L, w.list_cnt, w.list_start,
                      w.item_start, w.list_cursor, w.item_list);
   hipLaunchKernelGGL(pairs_fill_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
-                     w.probes, w.nprobe_eff, w.p1, w.list_start, w.list_cursor, w.pairs);
+                     w.probes, sel, w.list_start, w.list_cursor, w.pairs);
   return hipGetLastError();
 }
 
@@ -522,13 +547,20 @@ hipError_t launch_batched_main(const Tables& t, const float* Q, int32_t nq, int3
   }
 }
 
-hipError_t launch_batched_merge(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
-                                int32_t R, const Workspace& w, hipStream_t s) {
+hipError_t launch_batched_merge(const Tables& t, int32_t nq, int32_t R, const Workspace& w,
+                                hipStream_t s) {
+  (void)t;
   if (nq == 0) return hipSuccess;
   const size_t lds = (size_t)pow2_ceil((uint32_t)(R + w.spill_cap)) * 8;
   hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, w.spill_cap, w.nprobe_eff,
-                     w.spill_cnt, w.spill, w.cand, w.redo);
-  // Queries whose survivors overflowed: recompute with the plain scan.
+                     w.spill_cnt, w.spill, w.cand, w.thr, w.redo);
+  return hipGetLastError();
+}
+
+// Queries whose survivors overflowed in any round: the plain scan again.
+hipError_t launch_batched_redo(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                               int32_t R, const Workspace& w, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
   return launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, nullptr, nullptr, w.redo, s);
 }
 

@@ -115,14 +115,20 @@ hipError_t launch_bias(const Tables& t, const float* Q, int32_t nq, int32_t max_
                        const Workspace& w, hipStream_t s);
 hipError_t launch_scan_plain(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
                              int32_t rerank, const Workspace& w, hipStream_t s);
-// Batched form in three parts: first-list pass + work list, the persistent
-// list-major scan, and the merge (+ recompute of overflowed queries).
-hipError_t launch_batched_prep(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
-                               int32_t rerank, const Workspace& w, hipStream_t s);
+// Batched form: first-list pass (pool + threshold per query), then per
+// round: work list for probe ranks [lo, hi), persistent list-major scan,
+// merge (new pool and threshold); finally the plain recompute of queries
+// whose survivors overflowed.
+hipError_t launch_batched_first(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                                int32_t rerank, const Workspace& w, hipStream_t s);
+hipError_t launch_batched_pairs(const Tables& t, int32_t nq, int32_t max_nprobe, int32_t lo,
+                                int32_t hi, const Workspace& w, hipStream_t s);
 hipError_t launch_batched_main(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
                                int32_t rerank, const Workspace& w, hipStream_t s);
-hipError_t launch_batched_merge(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
-                                int32_t rerank, const Workspace& w, hipStream_t s);
+hipError_t launch_batched_merge(const Tables& t, int32_t nq, int32_t rerank, const Workspace& w,
+                                hipStream_t s);
+hipError_t launch_batched_redo(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
+                               int32_t rerank, const Workspace& w, hipStream_t s);
 hipError_t launch_debug_luts(const Tables& t, const float* Q, int32_t nq, const int32_t* probes,
                              const int32_t* nprobe, int32_t max_nprobe, uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
                              hipStream_t s);

@@ -7,7 +7,8 @@ device and keeps the fastest admissible one:
     widening 2 or 4 -- admitted only when its probe sets agree with the exact
     ones on at least `min_agree` of the queries (results are otherwise
     bit-identical, the forms only change the schedule);
-  * plain candidate-buffer size (pool_cap) and batched persistent grid size.
+  * plain candidate-buffer size (pool_cap), batched persistent grid size and
+    number of threshold-tightening rounds.
 Results are cached in a JSON file keyed by the device architecture and the
 shape (n, d, L, m, metric, nq, max_nprobe, k, rerank).
 """
@@ -35,10 +36,10 @@ def default_space():
     for coarse, widen in (("exact", 2), ("bf16", 2), ("bf16", 4), ("fp8", 4), ("f32", 2)):
         for pool in (0, 2048, 4096):
             space.append(dict(form="plain", coarse=coarse, widen=widen, pool_cap=pool))
-        for grid in (0, 2, 3, 4):
-            for pool in (0, 4096):
+        for rounds in (1, 3):
+            for grid, pool in ((0, 0), (2, 0), (4, 0), (0, 4096)):
                 space.append(dict(form="batched", coarse=coarse, widen=widen, grid=grid,
-                                  pool_cap=pool))
+                                  pool_cap=pool, rounds=rounds))
     return space
 
 
@@ -100,7 +101,7 @@ def autotune(g: GpuIndex, queries, nprobe, k: int, rerank: int,
         if log:
             log(f"tune {cand}: {ms:.3f} ms")
     best = min(trials, key=lambda r: r["ms"])
-    best_opts = {k_: best[k_] for k_ in ("form", "coarse", "widen", "pool_cap", "grid") if k_ in best}
+    best_opts = {k_: best[k_] for k_ in ("form", "coarse", "widen", "pool_cap", "grid", "rounds") if k_ in best}
     report = dict(key=key, best=opts_dict(make_opts(**best_opts)), best_ms=best["ms"],
                   trials=trials, seconds=round(time.time() - t0, 2))
     if cache_path:

@@ -117,11 +117,13 @@ def test_default_opts():
     ivf, lib = _lib()
     o = ivf.SearchOpts()
     lib.ivf_default_opts(ctypes.byref(o))
-    assert (o.coarse, o.widen, o.form, o.use_graph, o.pool_cap, o.grid) == (0, 2, 0, 0, 0, 0)
+    assert (o.coarse, o.widen, o.form, o.use_graph, o.pool_cap, o.grid, o.rounds) == \
+        (0, 2, 0, 0, 0, 0, 0)
 
 
 @pytest.mark.parametrize("field,value", [("pool_cap", 100), ("pool_cap", 20000), ("grid", 9),
-                                         ("coarse", 7), ("widen", 0), ("form", 3)])
+                                         ("coarse", 7), ("widen", 0), ("form", 3),
+                                         ("rounds", 9), ("reserved", 1)])
 def test_invalid_opts_rejected(field, value):
     ivf, lib = _lib()
     o = ivf.make_opts()

@@ -332,7 +332,27 @@ def test_batched_search_identical_to_plain(name):
                 exact_ids=(cfg.dist == "int255"))
 
 
-def test_batched_survivor_overflow_recomputes():
+@pytest.mark.parametrize("rounds", [2, 3, 4])
+@pytest.mark.parametrize("name", ["c1", "c3s", "c4s", "c5s"])
+def test_batched_rounds_candidates_bit_exact(name, rounds):
+    # Rounds over probe ranks [0,4), [4,16), [16,64), ... tighten the
+    # threshold between them; the pool is still the exact R smallest keys.
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    P = probes_tensor(res, nprobe)
+    opts = ivf.make_opts(form="batched", rounds=rounds)
+    keys = g.debug_candidates(Q, P, nprobe, cfg.R, opts=opts).cpu().numpy()
+    a, ids = ivf.decode_keys(keys)
+    assert np.array_equal(ids, res["cand_id"])
+    assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+    ib, db = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+    ip, dp = g.search(Q, nprobe, cfg.k, cfg.R)
+    assert torch.equal(ib, ip) and torch.equal(db.view(torch.int32), dp.view(torch.int32))
+    assert g.device_error() == 0
+
+
+@pytest.mark.parametrize("rounds", [1, 3])
+def test_batched_survivor_overflow_recomputes(rounds):
     # The first probed list is the farthest one, so the phase-1 threshold is
     # loose and the near lists' survivors overflow their buffer (4R, at
     # least 1024 keys): those queries go through the plain recompute.
@@ -349,7 +369,8 @@ def test_batched_survivor_overflow_recomputes():
     lens = np.diff(index["list_offsets"])
     assert all(lens[r[1:]].sum() > 1024 for r in rows)
     kp = g.debug_candidates(Q[:nq], P, npb, cfg.R).cpu().numpy()
-    kb = g.debug_candidates(Q[:nq], P, npb, cfg.R, opts=ivf.make_opts(form="batched")).cpu().numpy()
+    kb = g.debug_candidates(Q[:nq], P, npb, cfg.R,
+                            opts=ivf.make_opts(form="batched", rounds=rounds)).cpu().numpy()
     assert np.array_equal(kp, kb)
     res = oracle.search(index, X, Q[:nq], 1, cfg.k, cfg.R)  # shape only
     # Pool against the oracle on the same visiting order.
@@ -368,15 +389,15 @@ def test_batched_survivor_overflow_recomputes():
     del res
 
 
-@pytest.mark.parametrize("form", ["plain", "batched"])
-def test_graph_replays_match_eager(form):
+@pytest.mark.parametrize("form,rounds", [("plain", 0), ("batched", 1), ("batched", 3)])
+def test_graph_replays_match_eager(form, rounds):
     import paper_2511_03298_amd as ivf
     cfg, X, Q, nprobe, index, g, res = case("c3s")
     stream = torch.cuda.Stream()
     Qd = torch.from_numpy(Q).cuda()
     npd = torch.from_numpy(nprobe).cuda()
-    eager = ivf.make_opts(form=form, coarse="bf16", widen=4)
-    graph = ivf.make_opts(form=form, coarse="bf16", widen=4, use_graph=True)
+    eager = ivf.make_opts(form=form, coarse="bf16", widen=4, rounds=rounds)
+    graph = ivf.make_opts(form=form, coarse="bf16", widen=4, use_graph=True, rounds=rounds)
     ids = torch.empty((len(Q), cfg.k), dtype=torch.int64, device="cuda")
     dist = torch.empty((len(Q), cfg.k), dtype=torch.float32, device="cuda")
     with torch.cuda.stream(stream):
@@ -392,6 +413,28 @@ def test_graph_replays_match_eager(form):
             # eager work between replays
             g.search(Qd[:5], npd[:5], cfg.k, cfg.R, opts=eager)
             stream.synchronize()
+
+
+def test_stage_profile_sums_rounds():
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case("c3s")
+    Qd = torch.from_numpy(Q).cuda()
+    npd = torch.from_numpy(nprobe).cuda()
+    g.profile(True)
+    try:
+        g.profile_read()
+        for form, rounds in (("plain", 0), ("batched", 1), ("batched", 3)):
+            opts = ivf.make_opts(form=form, rounds=rounds)
+            for _ in range(3):
+                g.search(Qd, npd, cfg.k, cfg.R, opts=opts)
+            g.debug_candidates(Q, probes_tensor(res, nprobe), nprobe, cfg.R, opts=opts)
+            ms, cnt = g.profile_read()
+            assert cnt == 3, (form, rounds, cnt)
+            for st in ("coarse", "select", "prep", "scan", "rerank"):
+                assert ms[st] > 0.0, (form, rounds, st)
+            assert (ms["merge"] > 0.0) == (form == "batched")
+    finally:
+        g.profile(False)
 
 
 # ---------------------------------------------------------------------------
@@ -443,7 +486,7 @@ def test_autotuner_picks_measured_schedule_and_caches(tmp_path):
     cfg, X, Q, nprobe, index, g, res = case("c2s")
     space = [dict(form="plain", coarse="exact", widen=2, pool_cap=0),
              dict(form="batched", coarse="exact", widen=2, grid=2),
-             dict(form="batched", coarse="bf16", widen=4, grid=0)]
+             dict(form="batched", coarse="bf16", widen=4, grid=0, rounds=3)]
     path = str(tmp_path / "tune.json")
     opts, rep = autotune(g, Q, nprobe, cfg.k, cfg.R, space=space, reps=2, cache_path=path)
     assert not rep["cached"] and len(rep["trials"]) >= 2
