@@ -118,7 +118,10 @@ typedef struct {
                         [4,16), [16,64), ... (the last takes the rest), each
                         ending with a merge that tightens the per-query
                         threshold; 1..8, 0 = auto (1)                         */
-  int32_t reserved;  /* must be 0 */
+  int32_t spill_cap; /* BATCHED: survivor keys kept per query and round; a
+                        query with more is recomputed by the plain scan.
+                        0 = auto (a 2 GiB buffer for the batch, at most
+                        16384 - rerank), else 256..16384 - rerank            */
 } ivf_search_opts;
 
 /* Defaults: EXACT coarse, widen 2, PLAIN form, no graph, auto pool and grid. */

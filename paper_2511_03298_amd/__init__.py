@@ -51,7 +51,7 @@ class SearchOpts(ctypes.Structure):
     _fields_ = [("coarse", ctypes.c_int32), ("widen", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("pool_cap", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("rounds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("rounds", ctypes.c_int32), ("spill_cap", ctypes.c_int32)]
 
 
 class TableLayout(ctypes.Structure):
@@ -120,12 +120,12 @@ def check(status: int):
 
 def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
               use_graph: bool = False, pool_cap: int = 0, grid: int = 0,
-              rounds: int = 0) -> SearchOpts:
+              rounds: int = 0, spill_cap: int = 0) -> SearchOpts:
     o = SearchOpts()
     lib().ivf_default_opts(ctypes.byref(o))
     o.coarse, o.widen, o.form = COARSE[coarse], int(widen), FORM[form]
     o.use_graph, o.pool_cap, o.grid = int(bool(use_graph)), int(pool_cap), int(grid)
-    o.rounds = int(rounds)
+    o.rounds, o.spill_cap = int(rounds), int(spill_cap)
     return o
 
 
@@ -134,7 +134,7 @@ def opts_dict(o: SearchOpts) -> dict:
     inv_f = {v: k for k, v in FORM.items()}
     return dict(coarse=inv_c[o.coarse], widen=o.widen, form=inv_f[o.form],
                 use_graph=bool(o.use_graph), pool_cap=o.pool_cap, grid=o.grid,
-                rounds=o.rounds)
+                rounds=o.rounds, spill_cap=o.spill_cap)
 
 
 def _ptr(t) -> Optional[int]:

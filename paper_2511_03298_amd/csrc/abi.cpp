@@ -152,7 +152,8 @@ ivf_status check_opts(const ivf_search_opts& o) {
     return fail(IVF_ERR_INVALID_ARG, "opts.pool_cap must be 0 or a multiple of 256 up to 16384");
   if (o.grid < 0 || o.grid > 8) return fail(IVF_ERR_INVALID_ARG, "opts.grid must be in 0..8");
   if (o.rounds < 0 || o.rounds > 8) return fail(IVF_ERR_INVALID_ARG, "opts.rounds must be in 0..8");
-  if (o.reserved != 0) return fail(IVF_ERR_INVALID_ARG, "opts.reserved must be 0");
+  if (o.spill_cap != 0 && (o.spill_cap < 256 || o.spill_cap > 16384 - 256))
+    return fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be 0 or in 256..16128");
   return IVF_OK;
 }
 
@@ -204,7 +205,7 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   w.pool_cap = o.pool_cap;
   w.grid = o.grid;
   if (o.form == IVF_FORM_BATCHED) {
-    w.spill_cap = batched_spill_cap(rerank);
+    w.spill_cap = o.spill_cap > 0 ? o.spill_cap : batched_spill_cap(rerank, nq);
     w.p1 = (int32_t*)take(nqs * 4);
     w.thr = (uint64_t*)take(nqs * 8);
     w.list_cnt = (int32_t*)take((size_t)t.L * 4);
@@ -217,6 +218,11 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
     w.spill_cnt = (int32_t*)take(nqs * 4);
     w.spill = (uint64_t*)take(nqs * w.spill_cap * 8);
     w.redo = (int32_t*)take(nqs * 4);
+    if (t.metric == IVF_METRIC_IP) {
+      w.qlut = (uint8_t*)take(nqs * KSUB * t.m_pad);
+      w.qlo_sum = (float*)take(nqs * 4);
+      w.qdelta = (float*)take(nqs * 4);
+    }
   }
   w.total = off;
   return w;
@@ -235,7 +241,7 @@ void ivf_default_opts(ivf_search_opts* o) {
   o->pool_cap = 0;
   o->grid = 0;
   o->rounds = 0;
-  o->reserved = 0;
+  o->spill_cap = 0;
 }
 
 const char* ivf_last_error(void) { return g_last_error.c_str(); }
@@ -393,6 +399,10 @@ size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq, int32_t max_
   if (opts) o = *opts;
   if (check_opts(o) != IVF_OK) return 0;
   if (check_search(idx, nq, max_nprobe, k, rerank) != IVF_OK) return 0;
+  if (o.spill_cap > 16384 - rerank) {
+    (void)fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be at most 16384 - rerank");
+    return 0;
+  }
   return plan_workspace(idx->t, nq, max_nprobe, k, rerank, o, nullptr).total;
 }
 
@@ -441,6 +451,8 @@ ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, in
   if (opts) *o = *opts;
   st = check_opts(*o);
   if (st != IVF_OK) return st;
+  if (o->spill_cap > 16384 - rerank)
+    return fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be at most 16384 - rerank");
   st = check_form(idx, *o);
   if (st != IVF_OK) return st;
   Workspace need = plan_workspace(idx->t, nq, max_nprobe, k, rerank, *o, nullptr);
@@ -525,7 +537,7 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
     std::vector<uint64_t> key = {(uint64_t)nq, (uint64_t)max_nprobe, (uint64_t)k,
                                  (uint64_t)rerank, (uint64_t)o.coarse, (uint64_t)o.widen,
                                  (uint64_t)o.form, (uint64_t)o.pool_cap, (uint64_t)o.grid,
-                                 (uint64_t)o.rounds,
+                                 (uint64_t)o.rounds, (uint64_t)o.spill_cap,
                                  (uint64_t)(uintptr_t)queries,
                                  (uint64_t)(uintptr_t)nprobe, (uint64_t)(uintptr_t)workspace,
                                  (uint64_t)(uintptr_t)out_ids, (uint64_t)(uintptr_t)out_dist};

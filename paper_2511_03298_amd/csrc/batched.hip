@@ -168,9 +168,27 @@ __device__ __forceinline__ float lut_entry(const Tables& t, const float* rq, con
   return plus_zero(-acc);
 }
 
-template <int W>
+// Destination of a built table: the interleaved u16 scan layout (slot g of
+// the item) or, for inner product, the per-query table in global memory
+// (code-major: entry (j, c) at c*m_pad + j).
+struct ItemStore {
+  uint16_t* lut16;
+  int g;
+  __device__ __forceinline__ void operator()(int j, int code, uint32_t v) const {
+    lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = (uint16_t)v;
+  }
+};
+struct QueryStore {
+  uint8_t* row;  // [16][m_pad]
+  int m_pad;
+  __device__ __forceinline__ void operator()(int j, int code, uint32_t v) const {
+    row[code * m_pad + j] = (uint8_t)v;
+  }
+};
+
+template <int W, class Store>
 __device__ __forceinline__ void wave_build_lut(const Tables& t, const float* rq, const float* cb_s,
-                                               float bias, int g, uint16_t* lut16, float* lo_s,
+                                               float bias, const Store& store, float* lo_s,
                                                float* outB, float* outDelta) {
   constexpr int MP = W * 8;  // padded subspaces
   const int ln = lane_id();
@@ -197,9 +215,9 @@ __device__ __forceinline__ void wave_build_lut(const Tables& t, const float* rq,
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int j = 4 * r + (ln >> 4);
-      uint16_t v = 0;
-      if (live && j < t.m) v = (uint16_t)fminf(rintf(T[r] * sc), 255.0f);
-      lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = v;
+      uint32_t v = 0;
+      if (live && j < t.m) v = (uint32_t)fminf(rintf(T[r] * sc), 255.0f);
+      store(j, code, v);
     }
     const float ls = wave_pairwise_sum(lo_s, t.m);
     if (ln == 0) {
@@ -226,16 +244,32 @@ __device__ __forceinline__ void wave_build_lut(const Tables& t, const float* rq,
 #pragma unroll 1
   for (int r = 0; r < MP / 4; ++r) {
     const int j = 4 * r + (ln >> 4);
-    uint16_t v = 0;
+    uint32_t v = 0;
     if (live && j < t.m)
-      v = (uint16_t)fminf(rintf((lut_entry(t, rq, cb_s, j, code) - lo_s[j]) * sc), 255.0f);
-    lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = v;
+      v = (uint32_t)fminf(rintf((lut_entry(t, rq, cb_s, j, code) - lo_s[j]) * sc), 255.0f);
+    store(j, code, v);
   }
   const float ls = wave_pairwise_sum(lo_s, t.m);
   if (ln == 0) {
     *outB = ls + bias;
     *outDelta = live ? rng / 255.0f : 0.0f;
   }
+}
+
+// Inner product: the table does not depend on the list (only the bias
+// does), so it is built once per query: one wave per query writes the u8
+// table, the pairwise sum of the subspace minima and delta.
+template <int W>
+__global__ void __launch_bounds__(256) query_lut_kernel(Tables t, const float* __restrict__ Q,
+                                                        int32_t nq, uint8_t* __restrict__ qlut,
+                                                        float* __restrict__ qlo_sum,
+                                                        float* __restrict__ qdelta) {
+  __shared__ float lo[IVF_NWAVES][W * 8];
+  const int q = blockIdx.x * IVF_NWAVES + wave_index();
+  if (q >= nq) return;  // per wave; no barriers below
+  const QueryStore store{qlut + (size_t)q * KSUB * t.m_pad, t.m_pad};
+  wave_build_lut<W>(t, Q + (size_t)q * t.d, t.codebooks, 0.0f, store, lo[wave_index()],
+                    qlo_sum + q, qdelta + q);
 }
 
 // ---------------------------------------------------------------------------
@@ -260,22 +294,28 @@ struct BatchShared {
 template <int W>
 constexpr bool cb_in_lds() { return W <= 16; }
 
-template <int W>
+// PER_QUERY (inner product): the tables come from query_lut_kernel and are
+// only copied per item; otherwise (L2) each item builds its residual tables.
+template <int W, bool PER_QUERY>
 __global__ void __launch_bounds__(256) batched_scan_kernel(
     Tables t, const float* __restrict__ Q, int32_t max_nprobe, const float* __restrict__ bias,
     const uint64_t* __restrict__ thr, const int32_t* __restrict__ list_start,
     const int32_t* __restrict__ item_start, const int32_t* __restrict__ item_list,
     const int32_t* __restrict__ pairs, uint32_t* __restrict__ queue,
-    int32_t* __restrict__ spill_cnt, uint64_t* __restrict__ spill, int32_t cap) {
+    int32_t* __restrict__ spill_cnt, uint64_t* __restrict__ spill, int32_t cap,
+    const uint32_t* __restrict__ qlut, const float* __restrict__ qlo_sum,
+    const float* __restrict__ qdelta) {
   __shared__ BatchShared<W> sh;
   extern __shared__ __align__(16) unsigned char dyn[];
+  // L2 only: per-wave residual operand and (when they fit) the codebooks.
+  constexpr bool per_query = PER_QUERY;
   float* rq_all = reinterpret_cast<float*>(dyn);         // [4][d] per-wave query operand
   float* cb_s = rq_all + IVF_NWAVES * t.d;               // [m*16*d'] (when staged)
   const float* cb = cb_in_lds<W>() ? cb_s : t.codebooks;
   float* rq = rq_all + wave_index() * t.d;
   const int tid = threadIdx.x, wave = tid / IVF_WAVE, ln = lane_id();
   const int n_items = item_start[t.L];
-  if (cb_in_lds<W>())
+  if constexpr (cb_in_lds<W>() && !per_query)
     for (int i = tid; i < t.m * KSUB * t.dsub; i += blockDim.x) cb_s[i] = t.codebooks[i];
   if (tid == 0) sh.next = (int32_t)atomicAdd(queue, 1u);
   __syncthreads();
@@ -300,21 +340,44 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
     __syncthreads();
     if (tid == 0) sh.next = (int32_t)atomicAdd(queue, 1u);  // overlaps this item
     const int l = sh.l, nqi = sh.nqi;
-    // Tables: wave w builds queries w, w+4, w+8, w+12; absent queries get an
-    // all-zero table and no passing S.
+    if constexpr (per_query) {
+      // Copy the 16 queries' tables into the interleaved layout. Lane
+      // (c, pp) of task (subspaces 4jg..4jg+3, half h) moves code c of
+      // queries g0 = 8h + 2pp and g0 + 1: each store is one u32 holding both
+      // u16 entries, and the 64 lanes of a store hit 64 distinct banks.
+      constexpr int MP = W * 8;
+      const int c = ln >> 2, pp = ln & 3;
 #pragma unroll 1
-    for (int g = wave; g < BG; g += IVF_NWAVES) {
-      if (g < nqi) {
-        const int q = sh.qid[g];
-        const float* qg = Q + (size_t)q * t.d;
-        if (t.metric == IVF_METRIC_L2) {
-          const float* c = t.cm + (size_t)l * t.d;
-          for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
-        } else {
-          for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i];
+      for (int task = wave; task < MP / 2; task += IVF_NWAVES) {
+        const int jg = task >> 1, h = task & 1;
+        const int g0 = 8 * h + 2 * pp;
+        const uint32_t a0 = g0 < nqi ? qlut[((size_t)sh.qid[g0] * KSUB + c) * (MP / 4) + jg] : 0u;
+        const uint32_t a1 =
+            g0 + 1 < nqi ? qlut[((size_t)sh.qid[g0 + 1] * KSUB + c) * (MP / 4) + jg] : 0u;
+        uint32_t* dst = reinterpret_cast<uint32_t*>(sh.lut16);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int j = 4 * jg + jj;
+          const uint32_t v = ((a0 >> (8 * jj)) & 0xffu) | (((a1 >> (8 * jj)) & 0xffu) << 16);
+          dst[(((j * 2 + h) * 16 + c) * 8 + (g0 & 7)) >> 1] = v;
         }
-        const float b = t.metric == IVF_METRIC_IP ? bias[(size_t)q * max_nprobe + sh.slot[g]] : 0.0f;
-        wave_build_lut<W>(t, rq, cb, b, g, sh.lut16, sh.lo[wave], &sh.B[g], &sh.delta[g]);
+      }
+      if (tid < nqi) {
+        const int q = sh.qid[tid];
+        sh.B[tid] = qlo_sum[q] + bias[(size_t)q * max_nprobe + sh.slot[tid]];
+        sh.delta[tid] = qdelta[q];
+      }
+    }
+    // L2 tables: wave w builds queries w, w+4, w+8, w+12; absent queries get
+    // an all-zero table and no passing S.
+#pragma unroll 1
+    for (int g = wave; g < BG && !per_query; g += IVF_NWAVES) {
+      if (g < nqi) {
+        const float* qg = Q + (size_t)sh.qid[g] * t.d;
+        const float* c = t.cm + (size_t)l * t.d;
+        for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
+        wave_build_lut<W>(t, rq, cb, 0.0f, ItemStore{sh.lut16, g}, sh.lo[wave], &sh.B[g],
+                          &sh.delta[g]);
       } else {
         for (int e = ln; e < W * 8 * 16; e += IVF_WAVE)
           sh.lut16[(((e >> 4) * 2 + (g >> 3)) * 16 + (e & 15)) * 8 + (g & 7)] = 0;
@@ -432,7 +495,8 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
 // keys are unique, so exactly R keys remain.
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
+__global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap, int32_t ns_lo,
+                                                    int32_t ns_hi,
                                                     const int32_t* __restrict__ nprobe_eff,
                                                     const int32_t* __restrict__ spill_cnt,
                                                     const uint64_t* __restrict__ spill,
@@ -440,16 +504,17 @@ __global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap,
                                                     uint64_t* __restrict__ thr,
                                                     int32_t* __restrict__ redo) {
   extern __shared__ __align__(16) unsigned char dyn[];
-  uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);  // [pow2(R + cap)]
+  uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);  // [pow2(R + ns_hi)]
   __shared__ SelectScratch sc;
   __shared__ uint32_t cnt;
   const int q = blockIdx.x, tid = threadIdx.x;
   const int ns = spill_cnt[q];
-  if (nprobe_eff[q] < 0 || redo[q] != 0 || ns == 0) return;  // uniform
+  if (nprobe_eff[q] < 0 || redo[q] != 0 || ns <= ns_lo) return;  // uniform
   if (ns > cap) {
     if (tid == 0) redo[q] = 1;  // recomputed at the end; skipped from now on
     return;
   }
+  if (ns > ns_hi) return;  // a later launch with more LDS takes it
   if (tid == 0) cnt = 0;
   __syncthreads();
   for (int i = tid; i < R; i += blockDim.x) {
@@ -479,11 +544,24 @@ hipError_t launch_scan_plain_ex(const Tables& t, const float* Q, int32_t nq, int
                                 int32_t rerank, const Workspace& w, int32_t* p1_out,
                                 uint64_t* thr_out, const int32_t* only, hipStream_t s);
 
-int32_t batched_spill_cap(int32_t R) {
-  int32_t c = 4 * R;
+// Survivor capacity per query: as many keys as the merge can hold in LDS
+// beside the pool (MERGE_KEYS in all), within SPILL_BUDGET bytes for the batch.
+constexpr int32_t MERGE_KEYS = 16384;  // 128 KiB of LDS
+constexpr int64_t SPILL_BUDGET = 2ll << 30;
+
+int32_t batched_spill_cap(int32_t R, int32_t nq) {
+  int64_t c = SPILL_BUDGET / (8 * (int64_t)(nq > 0 ? nq : 1));
+  if (c > MERGE_KEYS - R) c = MERGE_KEYS - R;
   if (c < 1024) c = 1024;
-  if (c > 8192) c = 8192;
-  return c;
+  return (int32_t)c;
+}
+
+// The first merge launch takes queries with up to this many survivors, with
+// a small LDS footprint (many workgroups per CU); a second one the rest.
+static int32_t merge_small_ns(int32_t R, int32_t cap) {
+  const int32_t keys = (int32_t)pow2_ceil((uint32_t)(R + 2048));
+  const int32_t n = keys - R;
+  return n < cap ? n : cap;
 }
 
 hipError_t launch_batched_first(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
@@ -491,6 +569,20 @@ hipError_t launch_batched_first(const Tables& t, const float* Q, int32_t nq, int
   if (nq == 0) return hipSuccess;
   hipError_t e;
   if ((e = launch_fill_u32((uint32_t*)w.redo, 0u, (size_t)nq, s)) != hipSuccess) return e;
+  if (t.metric == IVF_METRIC_IP) {
+    switch (t.words) {
+#define X(N)                                                                                   \
+  case N:                                                                                      \
+    hipLaunchKernelGGL(query_lut_kernel<N>, dim3((nq + IVF_NWAVES - 1) / IVF_NWAVES), dim3(256), \
+                       0, s, t, Q, nq, w.qlut, w.qlo_sum, w.qdelta);                            \
+    break;
+      X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+      X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
+#undef X
+      default: return hipErrorNotSupported;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   // First lists per query -> pool, threshold, first probe rank of the rounds.
   return launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, w.p1, w.thr, nullptr, s);
 }
@@ -521,15 +613,24 @@ static hipError_t launch_main_w(const Tables& t, const float* Q, int32_t max_npr
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const size_t lds = (size_t)IVF_NWAVES * t.d * 4 +
-                     (cb_in_lds<W>() ? (size_t)t.m * KSUB * t.dsub * 4 : 0);
+  const size_t lds = t.metric == IVF_METRIC_IP
+                         ? 0
+                         : (size_t)IVF_NWAVES * t.d * 4 +
+                               (cb_in_lds<W>() ? (size_t)t.m * KSUB * t.dsub * 4 : 0);
   const size_t total = sizeof(BatchShared<W>) + lds;
   int per_cu = total <= 24 * 1024 ? 6 : total <= 36 * 1024 ? 4 : total <= 52 * 1024 ? 3
              : total <= 76 * 1024 ? 2 : 1;
   if (w.grid > 0) per_cu = w.grid;
-  hipLaunchKernelGGL(batched_scan_kernel<W>, dim3(cus * per_cu), dim3(256), lds, s, t, Q,
-                     max_nprobe, w.bias, w.thr, w.list_start, w.item_start, w.item_list, w.pairs,
-                     w.queue, w.spill_cnt, w.spill, w.spill_cap);
+  const dim3 grid(cus * per_cu), block(256);
+  const uint32_t* qlut = reinterpret_cast<const uint32_t*>(w.qlut);
+  if (t.metric == IVF_METRIC_IP)
+    hipLaunchKernelGGL((batched_scan_kernel<W, true>), grid, block, lds, s, t, Q, max_nprobe,
+                       w.bias, w.thr, w.list_start, w.item_start, w.item_list, w.pairs, w.queue,
+                       w.spill_cnt, w.spill, w.spill_cap, qlut, w.qlo_sum, w.qdelta);
+  else
+    hipLaunchKernelGGL((batched_scan_kernel<W, false>), grid, block, lds, s, t, Q, max_nprobe,
+                       w.bias, w.thr, w.list_start, w.item_start, w.item_list, w.pairs, w.queue,
+                       w.spill_cnt, w.spill, w.spill_cap, qlut, w.qlo_sum, w.qdelta);
   return hipGetLastError();
 }
 
@@ -551,9 +652,15 @@ hipError_t launch_batched_merge(const Tables& t, int32_t nq, int32_t R, const Wo
                                 hipStream_t s) {
   (void)t;
   if (nq == 0) return hipSuccess;
-  const size_t lds = (size_t)pow2_ceil((uint32_t)(R + w.spill_cap)) * 8;
-  hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, w.spill_cap, w.nprobe_eff,
+  const int32_t cap = w.spill_cap, small = merge_small_ns(R, cap);
+  size_t lds = (size_t)pow2_ceil((uint32_t)(R + small)) * 8;
+  hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, cap, 0, small, w.nprobe_eff,
                      w.spill_cnt, w.spill, w.cand, w.thr, w.redo);
+  if (cap > small) {
+    lds = (size_t)pow2_ceil((uint32_t)(R + cap)) * 8;
+    hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, cap, small, cap,
+                       w.nprobe_eff, w.spill_cnt, w.spill, w.cand, w.thr, w.redo);
+  }
   return hipGetLastError();
 }
 

@@ -80,6 +80,9 @@ struct Workspace {
   int32_t* spill_cnt;   // [nq] survivors per query
   uint64_t* spill;      // [nq][spill_cap] survivors
   int32_t* redo;        // [nq] 1 = survivors overflowed, recompute
+  uint8_t* qlut;        // IP: [nq][16][m_pad] per-query u8 tables (code-major)
+  float* qlo_sum;       // IP: [nq] pairwise sum of the subspace minima
+  float* qdelta;        // IP: [nq] quantisation step
   void* q_lowp;         // [nq_pad][d_pad] queries converted for MFMA coarse
   float* q_scale;       // [nq_pad]
   size_t total;
@@ -88,7 +91,7 @@ struct Workspace {
   int32_t grid;      // batched workgroups per CU (0 = auto)
 };
 
-int32_t batched_spill_cap(int32_t rerank);
+int32_t batched_spill_cap(int32_t rerank, int32_t nq);
 
 Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_t k,
                          int32_t rerank, const ivf_search_opts& o, char* base);

@@ -123,7 +123,8 @@ def test_default_opts():
 
 @pytest.mark.parametrize("field,value", [("pool_cap", 100), ("pool_cap", 20000), ("grid", 9),
                                          ("coarse", 7), ("widen", 0), ("form", 3),
-                                         ("rounds", 9), ("reserved", 1)])
+                                         ("rounds", 9), ("spill_cap", 100),
+                                         ("spill_cap", 20000)])
 def test_invalid_opts_rejected(field, value):
     ivf, lib = _lib()
     o = ivf.make_opts()

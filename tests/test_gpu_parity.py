@@ -351,11 +351,12 @@ def test_batched_rounds_candidates_bit_exact(name, rounds):
     assert g.device_error() == 0
 
 
-@pytest.mark.parametrize("rounds", [1, 3])
-def test_batched_survivor_overflow_recomputes(rounds):
+@pytest.mark.parametrize("rounds,spill_cap", [(1, 1024), (3, 1024), (3, 2048), (1, 0), (3, 0)])
+def test_batched_survivor_overflow_recomputes(rounds, spill_cap):
     # The first probed list is the farthest one, so the phase-1 threshold is
-    # loose and the near lists' survivors overflow their buffer (4R, at
-    # least 1024 keys): those queries go through the plain recompute.
+    # loose and the near lists' survivors overflow a 1024-key buffer: those
+    # queries go through the plain recompute. With the automatic capacity
+    # nothing overflows and the merge takes its large-LDS launch.
     import paper_2511_03298_amd as ivf
     cfg, X, Q, nprobe, index, g, _ = case("c2s")
     nq = 6
@@ -370,7 +371,8 @@ def test_batched_survivor_overflow_recomputes(rounds):
     assert all(lens[r[1:]].sum() > 1024 for r in rows)
     kp = g.debug_candidates(Q[:nq], P, npb, cfg.R).cpu().numpy()
     kb = g.debug_candidates(Q[:nq], P, npb, cfg.R,
-                            opts=ivf.make_opts(form="batched", rounds=rounds)).cpu().numpy()
+                            opts=ivf.make_opts(form="batched", rounds=rounds,
+                                               spill_cap=spill_cap)).cpu().numpy()
     assert np.array_equal(kp, kb)
     res = oracle.search(index, X, Q[:nq], 1, cfg.k, cfg.R)  # shape only
     # Pool against the oracle on the same visiting order.
