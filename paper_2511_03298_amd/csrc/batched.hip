@@ -282,7 +282,9 @@ struct BatchShared {
   float lo[IVF_NWAVES][W * 8];
   float B[BG], delta[BG];
   uint64_t thr[BG];
-  uint32_t smax[BG];  // largest S whose value can still pass (0xffffffff: none)
+  // Per query pair k (queries 2k, 2k+1 in the low, high half): 1 + the
+  // largest S whose value can still pass, 0 if none can (S < 2^16 always).
+  uint32_t slim[BG / 2];
   int32_t qid[BG], slot[BG];
   int32_t item, next, l, nqi;
   // Per wave: the current block's code words, then (after the word loop)
@@ -400,7 +402,11 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
         }
         smax = lo < 0 ? 0xffffffffu : (uint32_t)lo;
       }
-      sh.smax[g] = smax;
+      // 1 + smax in the query's u16 half (0: none). Sums are at most
+      // 255 * 192 < 65534, so clamping smax to 65534 changes no outcome.
+      const uint32_t lim = smax == 0xffffffffu ? 0u : (smax < 65534u ? smax : 65534u) + 1u;
+      const uint32_t other = __shfl_xor(lim, 1);
+      if ((g & 1) == 0) sh.slim[g >> 1] = lim | (other << 16);
     }
     __syncthreads();
     const int n_l = t.list_len[l];
@@ -426,44 +432,61 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
 #pragma unroll
         for (int w = 0; w < W; ++w) nx[w] = cw[w * BLOCK_PTS];
       }
-      u16x2 acc[8];
+      // acc[k] holds the sums of queries 2k (low half) and 2k+1 (high half).
+      // Plain 32-bit adds are exact on the packed pairs: a half never exceeds
+      // 255 * 192 < 2^16, so no carry crosses into the high half, and two
+      // subspaces fold into one three-input add.
+      uint32_t acc[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) acc[k] = u16x2{0, 0};
+      for (int k = 0; k < 8; ++k) acc[k] = 0u;
 #pragma unroll 1
       for (int w = 0; w < W; ++w) {
         const uint32_t x = stage[w * BLOCK_PTS + ln];
         const uint32_t base = (uint32_t)(w * 8 * 512);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const uint32_t nib = __builtin_amdgcn_ubfe(x, 4 * s, 4);
-          const unsigned char* row = lutb + ((nib << 4) + base + s * 512);
-          const uint4 lo4 = *reinterpret_cast<const uint4*>(row);
-          const uint4 hi4 = *reinterpret_cast<const uint4*>(row + 256);
-          acc[0] += __builtin_bit_cast(u16x2, lo4.x);
-          acc[1] += __builtin_bit_cast(u16x2, lo4.y);
-          acc[2] += __builtin_bit_cast(u16x2, lo4.z);
-          acc[3] += __builtin_bit_cast(u16x2, lo4.w);
-          acc[4] += __builtin_bit_cast(u16x2, hi4.x);
-          acc[5] += __builtin_bit_cast(u16x2, hi4.y);
-          acc[6] += __builtin_bit_cast(u16x2, hi4.z);
-          acc[7] += __builtin_bit_cast(u16x2, hi4.w);
+        for (int s = 0; s < 8; s += 2) {
+          const uint32_t n0 = __builtin_amdgcn_ubfe(x, 4 * s, 4);
+          const uint32_t n1 = __builtin_amdgcn_ubfe(x, 4 * s + 4, 4);
+          const unsigned char* r0 = lutb + ((n0 << 4) + base + s * 512);
+          const unsigned char* r1 = lutb + ((n1 << 4) + base + (s + 1) * 512);
+          const uint4 a0 = *reinterpret_cast<const uint4*>(r0);
+          const uint4 a1 = *reinterpret_cast<const uint4*>(r0 + 256);
+          const uint4 b0 = *reinterpret_cast<const uint4*>(r1);
+          const uint4 b1 = *reinterpret_cast<const uint4*>(r1 + 256);
+          acc[0] = acc[0] + a0.x + b0.x;
+          acc[1] = acc[1] + a0.y + b0.y;
+          acc[2] = acc[2] + a0.z + b0.z;
+          acc[3] = acc[3] + a0.w + b0.w;
+          acc[4] = acc[4] + a1.x + b1.x;
+          acc[5] = acc[5] + a1.y + b1.y;
+          acc[6] = acc[6] + a1.z + b1.z;
+          acc[7] = acc[7] + a1.w + b1.w;
         }
       }
       const bool valid = bi * BLOCK_PTS + ln < n_l;
-      // Pre-check in the integer domain; absent queries have smax = none.
+      // Pre-check in the integer domain: per half, the saturating difference
+      // (1 + smax) - S is non-zero exactly when S <= smax (absent queries
+      // have 1 + smax = 0).
+      uint32_t hit = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        hit |= __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
+                                                __builtin_bit_cast(u16x2, sh.slim[k]),
+                                                __builtin_bit_cast(u16x2, acc[k])));
+      if (__ballot(valid && hit != 0) == 0) continue;  // the common case: nothing passes
       uint32_t cand = 0;
 #pragma unroll
       for (int g = 0; g < BG; ++g) {
-        const uint32_t S = acc[g >> 1][g & 1];
-        const uint32_t sm = sh.smax[g];
-        cand |= (sm != 0xffffffffu && S <= sm) ? (1u << g) : 0u;
+        const uint32_t S = (acc[g >> 1] >> (16 * (g & 1))) & 0xffffu;
+        const uint32_t lim = (sh.slim[g >> 1] >> (16 * (g & 1))) & 0xffffu;
+        cand |= S < lim ? (1u << g) : 0u;
       }
       if (!valid) cand = 0;
-      if (__ballot(cand != 0) == 0) continue;  // the common case: nothing passes
       // Rare path: exact keys for the candidate (point, query) pairs.
       uint16_t* sv = reinterpret_cast<uint16_t*>(stage);
 #pragma unroll
-      for (int g = 0; g < BG; ++g) sv[g * BLOCK_PTS + ln] = acc[g >> 1][g & 1];
+      for (int g = 0; g < BG; ++g)
+        sv[g * BLOCK_PTS + ln] = (uint16_t)((acc[g >> 1] >> (16 * (g & 1))) & 0xffffu);
       const uint32_t id = cand ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
 #pragma unroll 1
       for (int g = 0; g < BG; ++g) {
