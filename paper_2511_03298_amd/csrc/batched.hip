@@ -488,22 +488,32 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       for (int g = 0; g < BG; ++g)
         sv[g * BLOCK_PTS + ln] = (uint16_t)((acc[g >> 1] >> (16 * (g & 1))) & 0xffffu);
       const uint32_t id = cand ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
+      // Which candidates pass on the full key; lane g collects query g's count.
+      uint32_t passbits = 0, count = 0;
 #pragma unroll 1
       for (int g = 0; g < BG; ++g) {
         const bool c = (cand >> g) & 1u;
         if (__ballot(c) == 0) continue;
         const uint32_t S = sv[g * BLOCK_PTS + ln];
-        const float a = plus_zero(sh.B[g] + sh.delta[g] * (float)S);
-        const uint64_t key = make_key(a, id);
+        const uint64_t key = make_key(plus_zero(sh.B[g] + sh.delta[g] * (float)S), id);
         const bool pass = c && key <= sh.thr[g];
+        passbits |= pass ? 1u << g : 0u;
+        const uint32_t n = (uint32_t)__popcll(__ballot(pass));
+        count = ln == g ? n : count;
+      }
+      // One reservation per query with survivors, all issued together.
+      uint32_t base = 0;
+      if (ln < BG && count) base = (uint32_t)atomicAdd(&spill_cnt[sh.qid[ln]], (int)count);
+#pragma unroll 1
+      for (int g = 0; g < BG; ++g) {
+        const bool pass = (passbits >> g) & 1u;
         const uint64_t mask = __ballot(pass);
-        if (mask) {
-          const int q = sh.qid[g];
-          uint32_t base = 0;
-          if (ln == 0) base = (uint32_t)atomicAdd(&spill_cnt[q], (int)__popcll(mask));
-          base = __shfl(base, 0);
-          const uint32_t pos = base + lanes_below(mask);
-          if (pass && pos < (uint32_t)cap) spill[(size_t)q * cap + pos] = key;
+        if (mask == 0) continue;
+        const uint32_t pos = (uint32_t)__shfl((int)base, g) + lanes_below(mask);
+        if (pass && pos < (uint32_t)cap) {
+          const uint32_t S = sv[g * BLOCK_PTS + ln];
+          spill[(size_t)sh.qid[g] * cap + pos] =
+              make_key(plus_zero(sh.B[g] + sh.delta[g] * (float)S), id);
         }
       }
     }
@@ -518,8 +528,10 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
 // keys are unique, so exactly R keys remain.
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap, int32_t ns_lo,
-                                                    int32_t ns_hi,
+// Grid-stride over queries: a launch with a large LDS footprint runs one
+// workgroup per CU and skips the queries another launch takes.
+__global__ void __launch_bounds__(256) merge_kernel(int32_t nq, int32_t R, int32_t cap,
+                                                    int32_t ns_lo, int32_t ns_hi,
                                                     const int32_t* __restrict__ nprobe_eff,
                                                     const int32_t* __restrict__ spill_cnt,
                                                     const uint64_t* __restrict__ spill,
@@ -530,35 +542,52 @@ __global__ void __launch_bounds__(256) merge_kernel(int32_t R, int32_t cap, int3
   uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);  // [pow2(R + ns_hi)]
   __shared__ SelectScratch sc;
   __shared__ uint32_t cnt;
-  const int q = blockIdx.x, tid = threadIdx.x;
-  const int ns = spill_cnt[q];
-  if (nprobe_eff[q] < 0 || redo[q] != 0 || ns <= ns_lo) return;  // uniform
-  if (ns > cap) {
-    if (tid == 0) redo[q] = 1;  // recomputed at the end; skipped from now on
-    return;
+  __shared__ unsigned long long maxkey;
+  const int tid = threadIdx.x;
+  for (int q = blockIdx.x; q < nq; q += gridDim.x) {  // q is uniform: barriers are safe
+    const int ns = spill_cnt[q];
+    if (nprobe_eff[q] < 0 || redo[q] != 0 || ns <= ns_lo) continue;
+    if (ns > cap) {
+      if (tid == 0) redo[q] = 1;  // recomputed at the end; skipped from now on
+      continue;
+    }
+    if (ns > ns_hi) continue;  // a later launch with more LDS takes it
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+    for (int i = tid; i < R; i += blockDim.x) {
+      const uint64_t k = cand[(size_t)q * R + i];
+      wave_append(k != KEY_NONE, k, keys, &cnt);
+    }
+    __syncthreads();
+    uint32_t n = cnt;
+    for (int i = tid; i < ns; i += blockDim.x) keys[n + i] = spill[(size_t)q * cap + i];
+    __syncthreads();
+    n += (uint32_t)ns;
+    if (n > (uint32_t)R) {
+      KeyUnion u{keys, n, nullptr, 0};
+      const uint64_t kth = block_kth(u, (uint32_t)R, &sc);
+      n = block_compact_le(keys, n, kth, &cnt);
+      if (n > (uint32_t)R) n = (uint32_t)R;
+    }
+    for (int i = tid; i < R; i += blockDim.x)
+      cand[(size_t)q * R + i] = (uint32_t)i < n ? keys[i] : KEY_NONE;
+    if (n == (uint32_t)R) {
+      // Its largest key, the R-th smallest so far, bounds every key that can
+      // still enter the pool (block_kth may return a looser bound).
+      if (tid == 0) maxkey = 0;
+      __syncthreads();
+      uint64_t mk = 0;
+      for (uint32_t i = tid; i < n; i += blockDim.x) mk = keys[i] > mk ? keys[i] : mk;
+      for (int off = 1; off < IVF_WAVE; off <<= 1) {
+        const uint64_t o = __shfl_xor(mk, off);
+        mk = o > mk ? o : mk;
+      }
+      if (lane_id() == 0) atomicMax(&maxkey, (unsigned long long)mk);
+      __syncthreads();
+      if (tid == 0) thr[q] = maxkey;
+    }
+    __syncthreads();  // LDS is reused by the next query
   }
-  if (ns > ns_hi) return;  // a later launch with more LDS takes it
-  if (tid == 0) cnt = 0;
-  __syncthreads();
-  for (int i = tid; i < R; i += blockDim.x) {
-    const uint64_t k = cand[(size_t)q * R + i];
-    wave_append(k != KEY_NONE, k, keys, &cnt);
-  }
-  __syncthreads();
-  uint32_t n = cnt;
-  for (int i = tid; i < ns; i += blockDim.x) keys[n + i] = spill[(size_t)q * cap + i];
-  __syncthreads();
-  n += (uint32_t)ns;
-  uint64_t kth = KEY_NONE;
-  if (n > (uint32_t)R) {
-    KeyUnion u{keys, n, nullptr, 0};
-    kth = block_kth(u, (uint32_t)R, &sc);
-    n = block_compact_le(keys, n, kth, &cnt);
-    if (n > (uint32_t)R) n = (uint32_t)R;
-  }
-  for (int i = tid; i < R; i += blockDim.x)
-    cand[(size_t)q * R + i] = (uint32_t)i < n ? keys[i] : KEY_NONE;
-  if (tid == 0 && n == (uint32_t)R && kth != KEY_NONE) thr[q] = kth;
 }
 
 // ---------------------------------------------------------------------------
@@ -677,11 +706,15 @@ hipError_t launch_batched_merge(const Tables& t, int32_t nq, int32_t R, const Wo
   if (nq == 0) return hipSuccess;
   const int32_t cap = w.spill_cap, small = merge_small_ns(R, cap);
   size_t lds = (size_t)pow2_ceil((uint32_t)(R + small)) * 8;
-  hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, cap, 0, small, w.nprobe_eff,
-                     w.spill_cnt, w.spill, w.cand, w.thr, w.redo);
+  hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, nq, R, cap, 0, small,
+                     w.nprobe_eff, w.spill_cnt, w.spill, w.cand, w.thr, w.redo);
   if (cap > small) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     lds = (size_t)pow2_ceil((uint32_t)(R + cap)) * 8;
-    hipLaunchKernelGGL(merge_kernel, dim3(nq), dim3(256), lds, s, R, cap, small, cap,
+    const int grid = nq < cus ? nq : cus;
+    hipLaunchKernelGGL(merge_kernel, dim3(grid), dim3(256), lds, s, nq, R, cap, small, cap,
                        w.nprobe_eff, w.spill_cnt, w.spill, w.cand, w.thr, w.redo);
   }
   return hipGetLastError();

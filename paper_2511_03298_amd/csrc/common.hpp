@@ -53,7 +53,7 @@ __device__ __forceinline__ void wave_append(bool pred, uint64_t key, uint64_t* b
 }
 
 // Scratch a workgroup needs for block_kth.
-struct SelectScratch {
+struct alignas(8) SelectScratch {
   uint32_t hist[256];
   uint32_t bin, below, cnt, pad;
 };
@@ -74,13 +74,44 @@ struct KeyUnion {
 // Returns the smallest threshold t such that exactly K keys of `keys` are
 // <= t, by MSB-first radix selection in 8-bit digits. Keys must be unique,
 // 1 <= K <= keys.size(). Must be called by all threads of the workgroup.
+// Digits above the highest byte in which the smallest and largest key differ
+// are common to every key, so selection starts at that byte.
 template <class Keys>
 __device__ uint64_t block_kth(const Keys& keys, uint32_t K, SelectScratch* sc) {
   const int tid = threadIdx.x;
   const uint32_t n = keys.size();
-  uint64_t prefix = 0, mask = 0;
+  uint64_t lo = ~0ull, hi = 0;
+  for (uint32_t i = tid; i < n; i += blockDim.x) {
+    const uint64_t k = keys[i];
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  }
+  for (int off = 1; off < IVF_WAVE; off <<= 1) {
+    const uint64_t a = __shfl_xor(lo, off), c = __shfl_xor(hi, off);
+    lo = a < lo ? a : lo;
+    hi = c > hi ? c : hi;
+  }
+  uint64_t* mm = reinterpret_cast<uint64_t*>(sc->hist);  // [waves][2], before the histograms
+  const int nw = (int)(blockDim.x / IVF_WAVE);
+  if (lane_id() == 0) {
+    mm[2 * wave_index()] = lo;
+    mm[2 * wave_index() + 1] = hi;
+  }
+  __syncthreads();
+  lo = mm[0];
+  hi = mm[1];
+  for (int w = 1; w < nw; ++w) {
+    lo = mm[2 * w] < lo ? mm[2 * w] : lo;
+    hi = mm[2 * w + 1] > hi ? mm[2 * w + 1] : hi;
+  }
+  __syncthreads();
+  const uint64_t diff = lo ^ hi;
+  if (diff == 0) return lo;  // a single distinct key (K == 1)
+  const int top = (63 - __builtin_clzll(diff)) & ~7;  // lowest bit of the first differing byte
+  uint64_t mask = top == 56 ? 0ull : ~0ull << (top + 8);
+  uint64_t prefix = lo & mask;
   uint32_t need = K;
-  for (int shift = 56; shift >= 0; shift -= 8) {
+  for (int shift = top; shift >= 0; shift -= 8) {
     for (int i = tid; i < 256; i += blockDim.x) sc->hist[i] = 0;
     __syncthreads();
     for (uint32_t i = tid; i < n; i += blockDim.x) {
