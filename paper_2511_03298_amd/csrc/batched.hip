@@ -256,6 +256,72 @@ __device__ __forceinline__ void wave_build_lut(const Tables& t, const float* rq,
   }
 }
 
+// L2 table of one (query, list) with one lane per subspace (m_pad <= 64):
+// the 16 entries of subspace j stay in lane j's registers, so its minimum is
+// local and a single cross-lane max gives the range. Lane j visits the codes
+// in the rotated order (k + j) mod 16, which spreads every store into the
+// interleaved table over 16 LDS banks (and every codebook read over 64).
+// Same canonical arithmetic as lut_entry: r_u = q_u - c_u rounded once,
+// T = sum_u (r_u - B_u)^2 sequentially in u. cbT: codebooks transposed in
+// LDS, entry (j, code, u) at (code*d' + u)*m_pad + j.
+template <int W>
+__device__ __forceinline__ void wave_build_lut_lanes(const Tables& t, const float* qg,
+                                                     const float* cl, const float* cbT, int g,
+                                                     uint16_t* lut16, float* outB,
+                                                     float* outDelta) {
+  constexpr int MP = W * 8;
+  static_assert(MP <= IVF_WAVE, "one lane per subspace");
+  const int j = lane_id();
+  const int ds = t.dsub;
+  const bool has = j < t.m;
+  float T[KSUB];
+#pragma unroll
+  for (int k = 0; k < KSUB; ++k) T[k] = 0.0f;
+  float lo = 0.0f, mx = 0.0f;
+  if (has) {
+    for (int u = 0; u < ds; ++u) {
+      const float r = qg[j * ds + u] - cl[j * ds + u];
+#pragma unroll
+      for (int k = 0; k < KSUB; ++k) {
+        const int code = (k + j) & 15;
+        const float df = r - cbT[(code * ds + u) * MP + j];
+        T[k] = T[k] + df * df;
+      }
+    }
+    lo = T[0];
+#pragma unroll
+    for (int k = 1; k < KSUB; ++k) lo = fminf(lo, T[k]);
+#pragma unroll
+    for (int k = 0; k < KSUB; ++k) {
+      T[k] = T[k] - lo;  // entry minus its subspace minimum (rounded once)
+      mx = fmaxf(mx, T[k]);
+    }
+  }
+  for (int s = 1; s < IVF_WAVE; s <<= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
+  const float rng = mx;
+  const bool live = rng > 0.0f;
+  const float sc = live ? 255.0f / rng : 0.0f;
+  if (j < MP) {
+#pragma unroll
+    for (int k = 0; k < KSUB; ++k) {
+      const int code = (k + j) & 15;
+      uint32_t v = 0;
+      if (live && has) v = (uint32_t)fminf(rintf(T[k] * sc), 255.0f);
+      lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = (uint16_t)v;
+    }
+  }
+  // Pairwise sum of lo_j over j < m (zeros beyond): the butterfly pairs the
+  // same operands in every lane, so lane 0 holds the canonical tree sum.
+  const int width = (int)pow2_ceil((uint32_t)t.m);
+  float x = has ? lo : 0.0f;
+  for (int s = 1; s < width; s <<= 1) x = x + __shfl_xor(x, s);
+  const float ls = __shfl(x, 0);
+  if (j == 0) {
+    *outB = ls + 0.0f;
+    *outDelta = live ? rng / 255.0f : 0.0f;
+  }
+}
+
 // Inner product: the table does not depend on the list (only the bias
 // does), so it is built once per query: one wave per query writes the u8
 // table, the pairwise sum of the subspace minima and delta.
@@ -295,6 +361,9 @@ struct BatchShared {
 // Codebooks are staged in LDS when they fit beside the tables.
 template <int W>
 constexpr bool cb_in_lds() { return W <= 16; }
+// L2 tables are built one lane per subspace when m_pad <= 64.
+template <int W>
+constexpr bool lane_build() { return W * 8 <= IVF_WAVE; }
 
 // PER_QUERY (inner product): the tables come from query_lut_kernel and are
 // only copied per item; otherwise (L2) each item builds its residual tables.
@@ -317,8 +386,17 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
   float* rq = rq_all + wave_index() * t.d;
   const int tid = threadIdx.x, wave = tid / IVF_WAVE, ln = lane_id();
   const int n_items = item_start[t.L];
-  if constexpr (cb_in_lds<W>() && !per_query)
+  float* cbT = reinterpret_cast<float*>(dyn);  // lane builder: [16*d'][m_pad]
+  if constexpr (!per_query && lane_build<W>()) {
+    constexpr int MP = W * 8;
+    const int per = KSUB * t.dsub;  // floats per subspace
+    for (int i = tid; i < t.m * per; i += blockDim.x) {
+      const int j = i / per, cu = i % per;  // cu = code * d' + u
+      cbT[cu * MP + j] = t.codebooks[i];
+    }
+  } else if constexpr (cb_in_lds<W>() && !per_query) {
     for (int i = tid; i < t.m * KSUB * t.dsub; i += blockDim.x) cb_s[i] = t.codebooks[i];
+  }
   if (tid == 0) sh.next = (int32_t)atomicAdd(queue, 1u);
   __syncthreads();
   for (;;) {
@@ -377,9 +455,13 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       if (g < nqi) {
         const float* qg = Q + (size_t)sh.qid[g] * t.d;
         const float* c = t.cm + (size_t)l * t.d;
-        for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
-        wave_build_lut<W>(t, rq, cb, 0.0f, ItemStore{sh.lut16, g}, sh.lo[wave], &sh.B[g],
-                          &sh.delta[g]);
+        if constexpr (lane_build<W>()) {
+          wave_build_lut_lanes<W>(t, qg, c, cbT, g, sh.lut16, &sh.B[g], &sh.delta[g]);
+        } else {
+          for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
+          wave_build_lut<W>(t, rq, cb, 0.0f, ItemStore{sh.lut16, g}, sh.lo[wave], &sh.B[g],
+                            &sh.delta[g]);
+        }
       } else {
         for (int e = ln; e < W * 8 * 16; e += IVF_WAVE)
           sh.lut16[(((e >> 4) * 2 + (g >> 3)) * 16 + (e & 15)) * 8 + (g & 7)] = 0;
@@ -665,8 +747,9 @@ static hipError_t launch_main_w(const Tables& t, const float* Q, int32_t max_npr
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const size_t lds = t.metric == IVF_METRIC_IP
-                         ? 0
+  const size_t lds = t.metric == IVF_METRIC_IP ? 0
+                     : lane_build<W>()
+                         ? (size_t)W * 8 * KSUB * t.dsub * 4
                          : (size_t)IVF_NWAVES * t.d * 4 +
                                (cb_in_lds<W>() ? (size_t)t.m * KSUB * t.dsub * 4 : 0);
   const size_t total = sizeof(BatchShared<W>) + lds;

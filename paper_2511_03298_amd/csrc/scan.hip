@@ -108,31 +108,12 @@ struct ScanShared {
   uint32_t cnt;
 };
 
-// Scan the 64-point blocks [b_begin, b_end) of list l with the table in LDS;
-// append keys <= thr to keys[] (counter st.total). One wave per block.
+// Code words of one 64-point block: word w of this lane's point.
 template <int W>
-__device__ __forceinline__ void scan_block(const Tables& t, const uint8_t* lut8, int blk,
-                                           int p_in_list, int n_l, float B, float delta,
-                                           uint64_t thr, uint64_t* keys, uint32_t* total) {
-  const int lane = lane_id();
-  const uint32_t* cw = t.codes + (size_t)blk * W * BLOCK_PTS + lane;
-  uint32_t words[W];
+__device__ __forceinline__ void load_words(const Tables& t, int blk, uint32_t (&words)[W]) {
+  const uint32_t* cw = t.codes + (size_t)blk * W * BLOCK_PTS + lane_id();
 #pragma unroll
   for (int w = 0; w < W; ++w) words[w] = cw[w * BLOCK_PTS];
-  uint32_t S = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    const uint32_t x = words[w];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) S += lut8[(w * 8 + s) * KSUB + ((x >> (4 * s)) & 15u)];
-  }
-  const bool valid = p_in_list + lane < n_l;
-  const float a = plus_zero(B + delta * (float)S);
-  const uint32_t oa = f2ord(a);
-  const bool maybe = valid && oa <= (uint32_t)(thr >> 32);
-  const uint32_t id = maybe ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + lane] : 0u;
-  const uint64_t key = ((uint64_t)oa << 32) | id;
-  wave_append(maybe && key <= thr, key, keys, total);
 }
 
 template <int W>
@@ -160,6 +141,20 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
   if (only && only[q] == 0) return;
   const int np = nprobe_eff[q];
 
+  // Software pipeline: each wave holds the code words of the next block it
+  // will scan (the first one before any table is built, then one ahead,
+  // reaching into the next probed list), so global loads overlap the table
+  // build, the lookups and the pool maintenance.
+  const int32_t* qprobes = probes + (size_t)q * max_nprobe;
+  uint32_t nx[W];
+  bool have = false;
+  if (np > 0) {
+    const int l0 = qprobes[0];
+    if (wave < (t.list_len[l0] + BLOCK_PTS - 1) / BLOCK_PTS) {
+      load_words<W>(t, t.block_off[l0] + wave, nx);
+      have = true;
+    }
+  }
   for (int i = tid; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
   if (tid == 0) sh.total = 0;
   __syncthreads();
@@ -172,13 +167,17 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
     __syncthreads();
     lut_quantize(t, Tf, sh.lo, sh.lut8, &sh.st);
   }
+  const int lane = lane_id();
   int seen = 0, p_end = np;
   for (int p = 0; p < np; ++p) {
     if (p1_out && seen >= R) {
       p_end = p;
       break;
     }
-    const int l = probes[(size_t)q * max_nprobe + p];
+    const int l = qprobes[p];
+    const int l_next = p + 1 < np ? qprobes[p + 1] : -1;
+    const int nblk_next = l_next >= 0 ? (t.list_len[l_next] + BLOCK_PTS - 1) / BLOCK_PTS : 0;
+    const int blk0_next = l_next >= 0 ? t.block_off[l_next] : 0;
     float b = 0.0f;
     if (!ip) {
       lut_float(t, qv, l, Tf);
@@ -195,8 +194,34 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
     const int nblk = (n_l + BLOCK_PTS - 1) / BLOCK_PTS;
     for (int b0 = 0; b0 < nblk; b0 += IVF_NWAVES) {
       const int bi = b0 + wave;
-      if (bi < nblk) scan_block<W>(t, sh.lut8, blk0 + bi, bi * BLOCK_PTS, n_l, B, delta, thr, keys,
-                                   &sh.total);
+      if (bi < nblk) {
+        if (!have) load_words<W>(t, blk0 + bi, nx);
+        uint32_t cur[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) cur[w] = nx[w];
+        // Request the wave's next block now, without branching (a branch
+        // makes the compiler wait for these loads before the lookups); when
+        // there is none, the current block is read again and not used.
+        const bool more = bi + IVF_NWAVES < nblk;
+        have = more || wave < nblk_next;
+        load_words<W>(t, more ? blk0 + bi + IVF_NWAVES
+                              : (wave < nblk_next ? blk0_next + wave : blk0 + bi), nx);
+        uint32_t S = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint32_t x = cur[w];
+#pragma unroll
+          for (int s8 = 0; s8 < 8; ++s8)
+            S += sh.lut8[(w * 8 + s8) * KSUB + ((x >> (4 * s8)) & 15u)];
+        }
+        const bool valid = bi * BLOCK_PTS + lane < n_l;
+        const float a = plus_zero(B + delta * (float)S);
+        const uint32_t oa = f2ord(a);
+        const bool maybe = valid && oa <= (uint32_t)(thr >> 32);
+        const uint32_t id = maybe ? (uint32_t)t.slot_ids[(size_t)(blk0 + bi) * BLOCK_PTS + lane] : 0u;
+        const uint64_t key = ((uint64_t)oa << 32) | id;
+        wave_append(maybe && key <= thr, key, keys, &sh.total);
+      }
       __syncthreads();
       const uint32_t total = sh.total;
       if (total > limit) {
