@@ -15,10 +15,45 @@ __device__ __forceinline__ float load_base(const Tables& t, int64_t row, int c) 
   return reinterpret_cast<const float*>(t.base)[row * t.d + c];
 }
 
-// One workgroup per query. Candidates are spread over groups of G lanes
-// (G = 64, 32 or 16 depending on d); each lane sums a strided slice of the
-// row and the group reduces with a butterfly in a fixed order.
-template <int G>
+// Sum over one 16-byte vector of the row: 4 FP32 values, or 8 BF16 values
+// widened exactly, in element order.
+__device__ __forceinline__ float vec_term(const float* qv, const uint4& x, int e0, bool ip,
+                                          bool bf16) {
+  float acc = 0.0f;
+  if (bf16) {
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const float v = __uint_as_float(h & 1 ? (w[h >> 1] & 0xffff0000u) : (w[h >> 1] << 16));
+      if (ip) {
+        acc = acc + qv[e0 + h] * v;
+      } else {
+        const float df = qv[e0 + h] - v;
+        acc = acc + df * df;
+      }
+    }
+  } else {
+    const float v[4] = {__uint_as_float(x.x), __uint_as_float(x.y), __uint_as_float(x.z),
+                        __uint_as_float(x.w)};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      if (ip) {
+        acc = acc + qv[e0 + h] * v[h];
+      } else {
+        const float df = qv[e0 + h] - v[h];
+        acc = acc + df * df;
+      }
+    }
+  }
+  return acc;
+}
+
+// One workgroup per query. A candidate row is read by a group of G = 8
+// lanes in 16-byte vectors (lane gl takes vectors gl, gl + 8, ...), U rows
+// per group at a time, so every lane keeps several loads in flight; the
+// group reduces its partial sums with a butterfly in a fixed order. Rows
+// whose byte size is not a multiple of 16 take the scalar path.
+template <int U>
 __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __restrict__ Q,
                                                      int32_t k, int32_t R,
                                                      const int32_t* __restrict__ nprobe_eff,
@@ -31,6 +66,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   const int q = blockIdx.x;
   const int tid = threadIdx.x;
   const bool ip = t.metric == IVF_METRIC_IP;
+  const bool bf16 = t.base_dtype == IVF_DTYPE_BF16;
   if (nprobe_eff[q] < 0) {  // invalid request row
     for (int i = tid; i < k; i += blockDim.x) {
       out_ids[(size_t)q * k + i] = -1;
@@ -40,9 +76,14 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   }
   for (int i = tid; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
   __syncthreads();
+  constexpr int G = 8;
   constexpr int GROUPS = IVF_BLOCK / G;
-  constexpr int U = 4;  // candidates in flight per lane group
   const int g = tid / G, gl = tid % G;
+  const int per_vec = bf16 ? 8 : 4;                       // elements per 16 bytes
+  const size_t row_bytes = (size_t)t.d * (bf16 ? 2 : 4);
+  const bool vec = row_bytes % 16 == 0;
+  const int nvec = t.d / per_vec;
+  const unsigned char* base = reinterpret_cast<const unsigned char*>(t.base);
   for (int c0 = 0; c0 < R; c0 += GROUPS * U) {
     uint64_t key[U];
     float acc[U];
@@ -52,18 +93,32 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
       key[u] = c < R ? cand[(size_t)q * R + c] : KEY_NONE;
       acc[u] = 0.0f;
     }
-    for (int i = gl; i < t.d; i += G) {
-      float x[U];
+    if (vec) {
+      for (int v0 = gl; v0 < nvec; v0 += G) {
+        uint4 x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        x[u] = key[u] != KEY_NONE ? load_base(t, (int64_t)(uint32_t)key[u], i) : 0.0f;
+        for (int u = 0; u < U; ++u) {
+          x[u] = make_uint4(0, 0, 0, 0);
+          if (key[u] != KEY_NONE)
+            x[u] = *reinterpret_cast<const uint4*>(base + (size_t)(uint32_t)key[u] * row_bytes +
+                                                   (size_t)v0 * 16);
+        }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (ip) {
-          acc[u] = acc[u] + qv[i] * x[u];
-        } else {
-          const float df = qv[i] - x[u];
-          acc[u] = acc[u] + df * df;
+        for (int u = 0; u < U; ++u)
+          if (key[u] != KEY_NONE) acc[u] = acc[u] + vec_term(qv, x[u], v0 * per_vec, ip, bf16);
+      }
+    } else {
+      for (int i = gl; i < t.d; i += G) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (key[u] == KEY_NONE) continue;
+          const float x = load_base(t, (int64_t)(uint32_t)key[u], i);
+          if (ip) {
+            acc[u] = acc[u] + qv[i] * x;
+          } else {
+            const float df = qv[i] - x;
+            acc[u] = acc[u] + df * df;
+          }
         }
       }
     }
@@ -113,16 +168,8 @@ hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k,
                          const Workspace& w, int64_t* out_ids, float* out_dist, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   size_t lds = (size_t)pow2_ceil((uint32_t)rerank) * 8 + (size_t)t.d * 4;
-  if (t.d >= 256) {
-    hipLaunchKernelGGL(rerank_kernel<64>, dim3(nq), dim3(256), lds, s, t, Q, k, rerank,
-                       w.nprobe_eff, w.cand, out_ids, out_dist);
-  } else if (t.d >= 64) {
-    hipLaunchKernelGGL(rerank_kernel<32>, dim3(nq), dim3(256), lds, s, t, Q, k, rerank,
-                       w.nprobe_eff, w.cand, out_ids, out_dist);
-  } else {
-    hipLaunchKernelGGL(rerank_kernel<16>, dim3(nq), dim3(256), lds, s, t, Q, k, rerank,
-                       w.nprobe_eff, w.cand, out_ids, out_dist);
-  }
+  hipLaunchKernelGGL(rerank_kernel<4>, dim3(nq), dim3(256), lds, s, t, Q, k, rerank, w.nprobe_eff,
+                     w.cand, out_ids, out_dist);
   return hipGetLastError();
 }
 
