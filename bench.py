@@ -169,7 +169,7 @@ def main():
     cfg = CONFIGS[args.config]
     t0 = time.time()
     log(f"generating {args.config}: n={cfg.n} d={cfg.d} nq={cfg.nq}")
-    X, Q, nprobe = make_workload(cfg)
+    X, Q, nprobe = make_workload(cfg, log=log)
     log(f"generated in {time.time() - t0:.1f}s; training IVF-PQ (L={cfg.L}, m={cfg.m})")
     t0 = time.time()
     gpu_trained = cfg.n > 2_000_000
@@ -177,7 +177,7 @@ def main():
         # 10M-point shapes: assignment and encoding on the GPU (ivf_assign /
         # ivf_encode); the host trainer would take many minutes.
         from paper_2511_03298_amd.train import train_index_gpu
-        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index)
+        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index, log=log)
     else:
         index = train_index(X, cfg)
     lens = np.diff(index["list_offsets"])
@@ -192,7 +192,7 @@ def main():
 
     nrec = min(args.recall_queries, cfg.nq)
     t0 = time.time()
-    gt_ids, _ = exact_knn(X, Q[:nrec], 10, cfg.metric)
+    gt_ids, _ = exact_knn(X, Q[:nrec], 10, cfg.metric, log=log)
     log(f"FP64 ground truth for {nrec} queries in {time.time() - t0:.1f}s")
 
     import torch

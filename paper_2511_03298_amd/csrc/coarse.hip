@@ -224,29 +224,47 @@ hipError_t launch_copy_probes(const int32_t* probes, const int32_t* nprobe, int3
   return hipGetLastError();
 }
 
-// Inner-product list constant b = -<q, cm_l> (sequential over t, FP32), one
-// thread per (query, probe slot).
-__global__ void bias_kernel(Tables t, const float* __restrict__ Q, int32_t nq, int32_t max_nprobe,
-                            const int32_t* __restrict__ probes,
-                            const int32_t* __restrict__ nprobe_eff, float* __restrict__ bias) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nq * max_nprobe) return;
-  const int q = (int)(i / max_nprobe), p = (int)(i % max_nprobe);
-  if (p >= nprobe_eff[q]) return;
-  const int l = probes[i];
-  const float* qq = Q + (size_t)q * t.d;
-  const float* c = t.cm + (size_t)l * t.d;
-  float acc = 0.0f;
-  for (int k = 0; k < t.d; ++k) acc = acc + qq[k] * c[k];
-  bias[i] = plus_zero(-acc);
+// Inner-product list constant b = -<q, cm_l> (sequential over t, FP32, every
+// product and sum rounded on its own). One workgroup per query with the query
+// in LDS; one thread per probe slot walks its centroid row with 16-byte loads
+// (scalar loads when rows are not 16-byte multiples), in the same order.
+__global__ void __launch_bounds__(256) bias_kernel(Tables t, const float* __restrict__ Q,
+                                                   int32_t max_nprobe,
+                                                   const int32_t* __restrict__ probes,
+                                                   const int32_t* __restrict__ nprobe_eff,
+                                                   float* __restrict__ bias) {
+  extern __shared__ __align__(16) float qs[];  // [d]
+  const int q = blockIdx.x;
+  const int np = nprobe_eff[q];
+  if (np <= 0) return;  // uniform
+  for (int i = threadIdx.x; i < t.d; i += blockDim.x) qs[i] = Q[(size_t)q * t.d + i];
+  __syncthreads();
+  const bool vec = (t.d & 3) == 0;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    const int l = probes[(size_t)q * max_nprobe + p];
+    const float* c = t.cm + (size_t)l * t.d;
+    float acc = 0.0f;
+    if (vec) {
+      const float4* c4 = reinterpret_cast<const float4*>(c);
+      for (int k4 = 0; k4 < t.d / 4; ++k4) {
+        const float4 v = c4[k4];
+        acc = acc + qs[4 * k4 + 0] * v.x;
+        acc = acc + qs[4 * k4 + 1] * v.y;
+        acc = acc + qs[4 * k4 + 2] * v.z;
+        acc = acc + qs[4 * k4 + 3] * v.w;
+      }
+    } else {
+      for (int k = 0; k < t.d; ++k) acc = acc + qs[k] * c[k];
+    }
+    bias[(size_t)q * max_nprobe + p] = plus_zero(-acc);
+  }
 }
 
 hipError_t launch_bias(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
                        const Workspace& w, hipStream_t s) {
   if (t.metric != IVF_METRIC_IP || nq == 0) return hipSuccess;
-  int64_t n = (int64_t)nq * max_nprobe;
-  hipLaunchKernelGGL(bias_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, Q, nq,
-                     max_nprobe, w.probes, w.nprobe_eff, w.bias);
+  hipLaunchKernelGGL(bias_kernel, dim3(nq), dim3(256), (size_t)t.d * 4, s, t, Q, max_nprobe,
+                     w.probes, w.nprobe_eff, w.bias);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ def _host_kmeans(X, k, iters, rng):
 def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
                     iters: int = 10, pq_iters: int = 12, train_per_list: int = 64,
                     pq_train: int = 65536, coarse: str = "bf16", widen: int = 4,
-                    device: str = "cuda"):
+                    device: str = "cuda", log=None):
     """Train an IVF-PQ index over X (float32 [n, d], host). Returns the same
     dict layout as the host trainer; `codes` and `list_ids` stay on the GPU
     (torch tensors), everything else is numpy."""
@@ -71,7 +71,9 @@ def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
     Xt = X[tidx]
     Xtd = Xd[torch.from_numpy(tidx).to(device)]
     C = Xt[rng.choice(nt, size=L, replace=nt < L)].astype(np.float64)
-    for _ in range(iters):
+    for it in range(iters):
+        if log:
+            log(f"k-means iteration {it + 1} of {iters}")
         Cs = _normalise(C) if ip else C
         Cd = torch.from_numpy(Cs.astype(np.float32)).to(device)
         a = assign_lists(Cd, Xtd, metric, coarse=coarse, widen=widen).cpu().numpy().astype(np.int64)
@@ -84,6 +86,8 @@ def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
     Cd = torch.from_numpy(Cs.astype(np.float32)).to(device)
     assign_d = assign_lists(Cd, Xd, metric, coarse=coarse, widen=widen)
     assign = assign_d.cpu().numpy().astype(np.int64)
+    if log:
+        log("list means over all rows")
     sums, counts = _group_means(X, assign, L)
     cm64 = np.where(counts[:, None] > 0, sums / np.maximum(counts, 1)[:, None], C)
     cm = cm64.astype(np.float32)
@@ -92,6 +96,8 @@ def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
     dsub = d // m
     pidx = rng.choice(n, size=min(n, pq_train), replace=False)
     resid = X[pidx] - cm[assign[pidx]]
+    if log:
+        log(f"PQ codebooks: {m} subspaces")
     codebooks = np.empty((m, KSUB, dsub), dtype=np.float32)
     for j in range(m):
         codebooks[j] = _host_kmeans(np.ascontiguousarray(resid[:, j * dsub:(j + 1) * dsub]),

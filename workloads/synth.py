@@ -16,6 +16,8 @@ Every random draw comes from numpy's PCG64 seeded with
 from __future__ import annotations
 
 import dataclasses
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import Optional, Tuple
 
 import numpy as np
@@ -130,7 +132,8 @@ def _rotation(cfg: WorkloadConfig) -> np.ndarray:
 def _draw(cfg: WorkloadConfig, mu, w, rot, count: int,
           rng: np.random.Generator) -> np.ndarray:
     comp = rng.choice(cfg.ncomp, size=count, p=w)
-    noise = rng.standard_normal((count, cfg.d))
+    noise = rng.standard_normal((count, cfg.d),
+                                dtype=np.float32 if cfg.dist == "aniso" else np.float64)
     if cfg.dist == "gauss":
         x = mu[comp] + cfg.sigma * noise
     elif cfg.dist == "int255":
@@ -139,9 +142,11 @@ def _draw(cfg: WorkloadConfig, mu, w, rot, count: int,
         x = mu[comp] + cfg.sigma * noise / np.sqrt(cfg.d)
         x = _normalize(x)
     elif cfg.dist == "aniso":
-        lam = (1.0 + np.arange(cfg.d)) ** -0.5
-        x = (mu[comp] + cfg.sigma * lam[None, :] * noise) @ rot.T
-        x = _normalize(x)
+        # FP32 arithmetic (the rows are rounded to BF16 afterwards anyway).
+        lam = ((1.0 + np.arange(cfg.d)) ** -0.5).astype(np.float32)
+        x = (mu[comp].astype(np.float32) + np.float32(cfg.sigma) * lam[None, :]
+             * noise.astype(np.float32)) @ rot.T.astype(np.float32)
+        x = x / np.sqrt(np.einsum("ij,ij->i", x, x))[:, None]
     else:
         raise ValueError(cfg.dist)
     return np.ascontiguousarray(x, dtype=np.float32)
@@ -158,19 +163,40 @@ def bf16_bits_to_f32(b: np.ndarray) -> np.ndarray:
     return (b.astype(np.uint32) << 16).view(np.float32)
 
 
-def make_workload(cfg: WorkloadConfig, chunk: int = 200_000):
+CHUNK = 200_000  # base rows per random stream
+
+
+def make_workload(cfg: WorkloadConfig, threads: int = 0, log=None):
     """Return (X, Q, nprobe) for ``cfg``.
 
     X is float32 [n, d] (for BF16 workloads: the float32 values of the BF16
     rows, which are the dataset itself), Q float32 [nq, d], nprobe int32 [nq].
+    Base rows are drawn in chunks of CHUNK rows, chunk c from its own stream
+    SeedSequence([2511, 3298, config, STREAM_BASE, c]), so chunks can be drawn
+    on several threads (numpy's generators and BLAS release the GIL) with the
+    same result.
     """
     mu, w = _means(cfg)
     rot = _rotation(cfg) if cfg.dist == "aniso" else None
-    rng_b = rng_for(cfg, STREAM_BASE)
     X = np.empty((cfg.n, cfg.d), dtype=np.float32)
-    for s in range(0, cfg.n, chunk):
-        e = min(cfg.n, s + chunk)
-        X[s:e] = _draw(cfg, mu, w, rot, e - s, rng_b)
+    nchunk = (cfg.n + CHUNK - 1) // CHUNK
+
+    def draw_chunk(c):
+        s, e = c * CHUNK, min(cfg.n, (c + 1) * CHUNK)
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(
+            [2511, 3298, cfg.index, STREAM_BASE, c])))
+        X[s:e] = _draw(cfg, mu, w, rot, e - s, rng)
+        if log and (c + 1) % 10 == 0:
+            log(f"drew {e} of {cfg.n} rows")
+
+    if threads <= 0:
+        threads = min(16, os.cpu_count() or 1)
+    if nchunk == 1 or threads == 1:
+        for c in range(nchunk):
+            draw_chunk(c)
+    else:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(draw_chunk, range(nchunk)))
     Q = _draw(cfg, mu, w, rot, cfg.nq, rng_for(cfg, STREAM_QUERY))
     if cfg.base_dtype == "bf16":
         X = bf16_bits_to_f32(to_bf16_bits(X))

@@ -12,7 +12,7 @@ import numpy as np
 
 
 def exact_knn(X: np.ndarray, Q: np.ndarray, k: int, metric: str,
-              chunk: int = 65536):
+              chunk: int = 65536, log=None):
     """Return (ids [nq,k] int64, dist [nq,k] float64) by FP64 exhaustive search.
 
     For L2 the distance is the squared Euclidean distance; for IP it is the
@@ -24,6 +24,8 @@ def exact_knn(X: np.ndarray, Q: np.ndarray, k: int, metric: str,
     best_d = np.full((nq, 0), 0.0)
     best_i = np.zeros((nq, 0), dtype=np.int64)
     for s in range(0, len(X), chunk):
+        if log and s and s % (chunk * 32) == 0:
+            log(f"ground truth: {s} of {len(X)} rows")
         Xc = X[s:s + chunk].astype(np.float64)
         g = Q64 @ Xc.T
         if metric == "l2":
