@@ -38,10 +38,10 @@ LOOKUP_PEAK_T = 256 * 64 * 2.4e9 * 2 / 1e12
 # device copy gave: 2.0 and 1.0). Valid only while the kernel source is the
 # one measured (sha256 of the listed files).
 TRAFFIC = {
-    ("c2", "batched"): dict(files=("batched.hip", "common.hpp"), sha="a6bf74250dff637e",
-                            fetch_kib=107976.9, write_kib=1876.7),
-    ("c2", "plain"): dict(files=("scan.hip", "common.hpp"), sha="18d181930b024f9d",
-                          fetch_kib=5550621.1, write_kib=15625.0),
+    ("c2", "batched"): dict(files=("batched.hip", "common.hpp"), sha="f28d7a5d243fa4af",
+                            fetch_kib=109676.8, write_kib=1727.1),
+    ("c2", "plain"): dict(files=("scan.hip", "common.hpp"), sha="0d81da5cf7e0188b",
+                          fetch_kib=5188205.3, write_kib=15625.0),
 }
 
 

@@ -8,6 +8,7 @@
 // ties go to the smaller list index.
 #include "common.hpp"
 #include "internal.hpp"
+#include "rank_sort.hpp"
 
 namespace ivf {
 
@@ -174,11 +175,21 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
       n = block_compact_le(keys, n, block_kth(u, (uint32_t)np, &sc), &cnt);
     }
   }
-  const uint32_t n2 = pow2_ceil(n);
-  for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
-  block_bitonic_sort(keys, n2);
+  // Ascending (score, list): by rank into the free space behind the keys
+  // when there is room (n <= 512 and 2n <= the key array), else bitonic.
+  const uint64_t* sorted = keys;
+  const uint32_t cap = pow2_ceil((uint32_t)L);
+  if (n <= 512 && 2 * n <= cap) {
+    __syncthreads();
+    block_rank_sort(keys, n, keys + n);
+    sorted = keys + n;
+  } else {
+    const uint32_t n2 = pow2_ceil(n);
+    for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
+    block_bitonic_sort(keys, n2);
+  }
   for (int p = tid; p < max_nprobe; p += blockDim.x)
-    probes[(size_t)q * max_nprobe + p] = p < np ? (int32_t)(uint32_t)keys[p] : -1;
+    probes[(size_t)q * max_nprobe + p] = p < np ? (int32_t)(uint32_t)sorted[p] : -1;
   if (tid == 0) nprobe_eff[q] = np;
 }
 

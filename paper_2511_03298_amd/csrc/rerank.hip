@@ -4,6 +4,7 @@
 // descending inner product.
 #include "common.hpp"
 #include "internal.hpp"
+#include "rank_sort.hpp"
 
 namespace ivf {
 
@@ -148,11 +149,20 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
     const uint64_t thr = block_kth(u, (uint32_t)k, &sc);
     n = block_compact_le(keys, n, thr, &cnt);
   }
-  const uint32_t n2 = pow2_ceil(n);
-  for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
-  block_bitonic_sort(keys, n2);
+  // Ascending order of the (at most k) kept keys: by rank into the free space
+  // behind them when there is room, else bitonic.
+  const uint64_t* sorted = keys;
+  if (n <= 512 && 2 * n <= pow2_ceil((uint32_t)R)) {
+    __syncthreads();
+    block_rank_sort(keys, n, keys + n);
+    sorted = keys + n;
+  } else {
+    const uint32_t n2 = pow2_ceil(n);
+    for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
+    block_bitonic_sort(keys, n2);
+  }
   for (int i = tid; i < k; i += blockDim.x) {
-    const uint64_t kk = i < R ? keys[i] : KEY_NONE;
+    const uint64_t kk = (uint32_t)i < n ? sorted[i] : KEY_NONE;
     if (kk == KEY_NONE) {
       out_ids[(size_t)q * k + i] = -1;
       out_dist[(size_t)q * k + i] = ip ? -INFINITY : INFINITY;
