@@ -27,7 +27,11 @@
 
 namespace ivf {
 
-constexpr int BG = 16;  // queries per work item
+// Queries per work item: 16 (two 8-query halves of the table), or 8 when the
+// 16-query table would leave room for only one workgroup per CU (m_pad > 96).
+template <int W>
+constexpr int item_queries() { return W * 8 > 96 ? 8 : 16; }
+inline int item_queries_rt(int W) { return W * 8 > 96 ? 8 : 16; }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
@@ -70,7 +74,8 @@ __global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t ma
 }
 
 // Exclusive scans of per-list pair counts and item counts (one workgroup).
-__global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, const int32_t* __restrict__ cnt,
+__global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, int32_t BG,
+                                                         const int32_t* __restrict__ cnt,
                                                          int32_t* __restrict__ list_start,
                                                          int32_t* __restrict__ item_start,
                                                          int32_t* __restrict__ cursor,
@@ -174,8 +179,9 @@ __device__ __forceinline__ float lut_entry(const Tables& t, const float* rq, con
 struct ItemStore {
   uint16_t* lut16;
   int g;
+  int halves;  // 8-query halves of the item table (1 or 2)
   __device__ __forceinline__ void operator()(int j, int code, uint32_t v) const {
-    lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = (uint16_t)v;
+    lut16[((j * halves + (g >> 3)) * 16 + code) * 8 + (g & 7)] = (uint16_t)v;
   }
 };
 struct QueryStore {
@@ -307,7 +313,7 @@ __device__ __forceinline__ void wave_build_lut_lanes(const Tables& t, const floa
       const int code = (k + j) & 15;
       uint32_t v = 0;
       if (live && has) v = (uint32_t)fminf(rintf(T[k] * sc), 255.0f);
-      lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = (uint16_t)v;
+      lut16[((j * 2 + (g >> 3)) * 16 + code) * 8 + (g & 7)] = (uint16_t)v;  // 16-query items
     }
   }
   // Pairwise sum of lo_j over j < m (zeros beyond): the butterfly pairs the
@@ -342,9 +348,9 @@ __global__ void __launch_bounds__(256) query_lut_kernel(Tables t, const float* _
 // Phase 2: persistent list-major scan.
 // ---------------------------------------------------------------------------
 
-template <int W>
+template <int W, int BG>
 struct BatchShared {
-  uint16_t lut16[W * 8 * 2 * 16 * 8];
+  uint16_t lut16[W * 8 * (BG / 8) * 16 * 8];
   float lo[IVF_NWAVES][W * 8];
   float B[BG], delta[BG];
   uint64_t thr[BG];
@@ -354,7 +360,7 @@ struct BatchShared {
   int32_t qid[BG], slot[BG];
   int32_t item, next, l, nqi;
   // Per wave: the current block's code words, then (after the word loop)
-  // its 16 sums per point for the rare exact-key path.
+  // its BG sums per point for the rare exact-key path.
   uint32_t stage[IVF_NWAVES][(W * 2 > BG ? W * 2 : BG) * BLOCK_PTS / 2];
 };
 
@@ -367,7 +373,7 @@ constexpr bool lane_build() { return W * 8 <= IVF_WAVE; }
 
 // PER_QUERY (inner product): the tables come from query_lut_kernel and are
 // only copied per item; otherwise (L2) each item builds its residual tables.
-template <int W, bool PER_QUERY>
+template <int W, bool PER_QUERY, int BG>
 __global__ void __launch_bounds__(256) batched_scan_kernel(
     Tables t, const float* __restrict__ Q, int32_t max_nprobe, const float* __restrict__ bias,
     const uint64_t* __restrict__ thr, const int32_t* __restrict__ list_start,
@@ -376,7 +382,8 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
     int32_t* __restrict__ spill_cnt, uint64_t* __restrict__ spill, int32_t cap,
     const uint32_t* __restrict__ qlut, const float* __restrict__ qlo_sum,
     const float* __restrict__ qdelta) {
-  __shared__ BatchShared<W> sh;
+  __shared__ BatchShared<W, BG> sh;
+  constexpr int HALVES = BG / 8;
   extern __shared__ __align__(16) unsigned char dyn[];
   // L2 only: per-wave residual operand and (when they fit) the codebooks.
   constexpr bool per_query = PER_QUERY;
@@ -421,15 +428,15 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
     if (tid == 0) sh.next = (int32_t)atomicAdd(queue, 1u);  // overlaps this item
     const int l = sh.l, nqi = sh.nqi;
     if constexpr (per_query) {
-      // Copy the 16 queries' tables into the interleaved layout. Lane
-      // (c, pp) of task (subspaces 4jg..4jg+3, half h) moves code c of
-      // queries g0 = 8h + 2pp and g0 + 1: each store is one u32 holding both
-      // u16 entries, and the 64 lanes of a store hit 64 distinct banks.
+      // Copy the queries' tables into the interleaved layout. Lane (c, pp)
+      // of task (subspaces 4jg..4jg+3, half h) moves code c of queries
+      // g0 = 8h + 2pp and g0 + 1: each store is one u32 holding both u16
+      // entries, and the 64 lanes of a store hit 64 distinct banks.
       constexpr int MP = W * 8;
       const int c = ln >> 2, pp = ln & 3;
 #pragma unroll 1
-      for (int task = wave; task < MP / 2; task += IVF_NWAVES) {
-        const int jg = task >> 1, h = task & 1;
+      for (int task = wave; task < MP / 4 * HALVES; task += IVF_NWAVES) {
+        const int jg = task / HALVES, h = task % HALVES;
         const int g0 = 8 * h + 2 * pp;
         const uint32_t a0 = g0 < nqi ? qlut[((size_t)sh.qid[g0] * KSUB + c) * (MP / 4) + jg] : 0u;
         const uint32_t a1 =
@@ -439,7 +446,7 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
         for (int jj = 0; jj < 4; ++jj) {
           const int j = 4 * jg + jj;
           const uint32_t v = ((a0 >> (8 * jj)) & 0xffu) | (((a1 >> (8 * jj)) & 0xffu) << 16);
-          dst[(((j * 2 + h) * 16 + c) * 8 + (g0 & 7)) >> 1] = v;
+          dst[(((j * HALVES + h) * 16 + c) * 8 + (g0 & 7)) >> 1] = v;
         }
       }
       if (tid < nqi) {
@@ -456,15 +463,16 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
         const float* qg = Q + (size_t)sh.qid[g] * t.d;
         const float* c = t.cm + (size_t)l * t.d;
         if constexpr (lane_build<W>()) {
+          static_assert(BG == 16, "the lane builder writes 16-query items");
           wave_build_lut_lanes<W>(t, qg, c, cbT, g, sh.lut16, &sh.B[g], &sh.delta[g]);
         } else {
           for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
-          wave_build_lut<W>(t, rq, cb, 0.0f, ItemStore{sh.lut16, g}, sh.lo[wave], &sh.B[g],
-                            &sh.delta[g]);
+          wave_build_lut<W>(t, rq, cb, 0.0f, ItemStore{sh.lut16, g, HALVES}, sh.lo[wave],
+                            &sh.B[g], &sh.delta[g]);
         }
       } else {
         for (int e = ln; e < W * 8 * 16; e += IVF_WAVE)
-          sh.lut16[(((e >> 4) * 2 + (g >> 3)) * 16 + (e & 15)) * 8 + (g & 7)] = 0;
+          sh.lut16[(((e >> 4) * HALVES + (g >> 3)) * 16 + (e & 15)) * 8 + (g & 7)] = 0;
       }
     }
     __syncthreads();
@@ -518,31 +526,30 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       // Plain 32-bit adds are exact on the packed pairs: a half never exceeds
       // 255 * 192 < 2^16, so no carry crosses into the high half, and two
       // subspaces fold into one three-input add.
-      uint32_t acc[8];
+      constexpr int NACC = BG / 2;
+      constexpr uint32_t SUBB = HALVES * 256;  // bytes of one subspace's rows
+      uint32_t acc[NACC];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) acc[k] = 0u;
+      for (int k = 0; k < NACC; ++k) acc[k] = 0u;
 #pragma unroll 1
       for (int w = 0; w < W; ++w) {
         const uint32_t x = stage[w * BLOCK_PTS + ln];
-        const uint32_t base = (uint32_t)(w * 8 * 512);
+        const uint32_t base = (uint32_t)(w * 8 * SUBB);
 #pragma unroll
         for (int s = 0; s < 8; s += 2) {
           const uint32_t n0 = __builtin_amdgcn_ubfe(x, 4 * s, 4);
           const uint32_t n1 = __builtin_amdgcn_ubfe(x, 4 * s + 4, 4);
-          const unsigned char* r0 = lutb + ((n0 << 4) + base + s * 512);
-          const unsigned char* r1 = lutb + ((n1 << 4) + base + (s + 1) * 512);
-          const uint4 a0 = *reinterpret_cast<const uint4*>(r0);
-          const uint4 a1 = *reinterpret_cast<const uint4*>(r0 + 256);
-          const uint4 b0 = *reinterpret_cast<const uint4*>(r1);
-          const uint4 b1 = *reinterpret_cast<const uint4*>(r1 + 256);
-          acc[0] = acc[0] + a0.x + b0.x;
-          acc[1] = acc[1] + a0.y + b0.y;
-          acc[2] = acc[2] + a0.z + b0.z;
-          acc[3] = acc[3] + a0.w + b0.w;
-          acc[4] = acc[4] + a1.x + b1.x;
-          acc[5] = acc[5] + a1.y + b1.y;
-          acc[6] = acc[6] + a1.z + b1.z;
-          acc[7] = acc[7] + a1.w + b1.w;
+          const unsigned char* r0 = lutb + ((n0 << 4) + base + s * SUBB);
+          const unsigned char* r1 = lutb + ((n1 << 4) + base + (s + 1) * SUBB);
+#pragma unroll
+          for (int h = 0; h < HALVES; ++h) {
+            const uint4 a = *reinterpret_cast<const uint4*>(r0 + 256 * h);
+            const uint4 b = *reinterpret_cast<const uint4*>(r1 + 256 * h);
+            acc[4 * h + 0] = acc[4 * h + 0] + a.x + b.x;
+            acc[4 * h + 1] = acc[4 * h + 1] + a.y + b.y;
+            acc[4 * h + 2] = acc[4 * h + 2] + a.z + b.z;
+            acc[4 * h + 3] = acc[4 * h + 3] + a.w + b.w;
+          }
         }
       }
       const bool valid = bi * BLOCK_PTS + ln < n_l;
@@ -551,7 +558,7 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       // have 1 + smax = 0).
       uint32_t hit = 0;
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
+      for (int k = 0; k < NACC; ++k)
         hit |= __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
                                                 __builtin_bit_cast(u16x2, sh.slim[k]),
                                                 __builtin_bit_cast(u16x2, acc[k])));
@@ -734,8 +741,8 @@ hipError_t launch_batched_pairs(const Tables& t, int32_t nq, int32_t max_nprobe,
   const size_t hist_lds = (size_t)t.L * 4;
   hipLaunchKernelGGL(pairs_count_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
                      w.probes, sel, w.list_cnt);
-  hipLaunchKernelGGL(pairs_scan_kernel, dim3(1), dim3(1024), 0, s, t.L, w.list_cnt, w.list_start,
-                     w.item_start, w.list_cursor, w.item_list);
+  hipLaunchKernelGGL(pairs_scan_kernel, dim3(1), dim3(1024), 0, s, t.L, item_queries_rt(t.words),
+                     w.list_cnt, w.list_start, w.item_start, w.list_cursor, w.item_list);
   hipLaunchKernelGGL(pairs_fill_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
                      w.probes, sel, w.list_start, w.list_cursor, w.pairs);
   return hipGetLastError();
@@ -744,6 +751,7 @@ hipError_t launch_batched_pairs(const Tables& t, int32_t nq, int32_t max_nprobe,
 template <int W>
 static hipError_t launch_main_w(const Tables& t, const float* Q, int32_t max_nprobe,
                                 const Workspace& w, hipStream_t s) {
+  constexpr int BG = item_queries<W>();
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -752,21 +760,24 @@ static hipError_t launch_main_w(const Tables& t, const float* Q, int32_t max_npr
                          ? (size_t)W * 8 * KSUB * t.dsub * 4
                          : (size_t)IVF_NWAVES * t.d * 4 +
                                (cb_in_lds<W>() ? (size_t)t.m * KSUB * t.dsub * 4 : 0);
-  const size_t total = sizeof(BatchShared<W>) + lds;
-  int per_cu = total <= 24 * 1024 ? 6 : total <= 36 * 1024 ? 4 : total <= 52 * 1024 ? 3
-             : total <= 76 * 1024 ? 2 : 1;
-  if (w.grid > 0) per_cu = w.grid;
-  const dim3 grid(cus * per_cu), block(256);
+  const dim3 block(256);
   const uint32_t* qlut = reinterpret_cast<const uint32_t*>(w.qlut);
-  if (t.metric == IVF_METRIC_IP)
-    hipLaunchKernelGGL((batched_scan_kernel<W, true>), grid, block, lds, s, t, Q, max_nprobe,
-                       w.bias, w.thr, w.list_start, w.item_start, w.item_list, w.pairs, w.queue,
+  auto launch = [&](auto kernel) -> hipError_t {
+    // Persistent grid: as many workgroups per CU as registers and LDS allow
+    // (at most 6), unless the caller fixed it.
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (per_cu > 6) per_cu = 6;
+    if (w.grid > 0) per_cu = w.grid;
+    hipLaunchKernelGGL(kernel, dim3(cus * per_cu), block, lds, s, t, Q, max_nprobe, w.bias,
+                       w.thr, w.list_start, w.item_start, w.item_list, w.pairs, w.queue,
                        w.spill_cnt, w.spill, w.spill_cap, qlut, w.qlo_sum, w.qdelta);
-  else
-    hipLaunchKernelGGL((batched_scan_kernel<W, false>), grid, block, lds, s, t, Q, max_nprobe,
-                       w.bias, w.thr, w.list_start, w.item_start, w.item_list, w.pairs, w.queue,
-                       w.spill_cnt, w.spill, w.spill_cap, qlut, w.qlo_sum, w.qdelta);
-  return hipGetLastError();
+    return hipGetLastError();
+  };
+  if (t.metric == IVF_METRIC_IP) return launch(batched_scan_kernel<W, true, BG>);
+  return launch(batched_scan_kernel<W, false, BG>);
 }
 
 hipError_t launch_batched_main(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
