@@ -11,10 +11,16 @@ lossless constructed cases, full sorts). The u8 LUT quantisation *scheme*
 even) is a reading of a passage that only says the LUT entries are 8-bit
 unsigned integers; it is pinned by invariants and a lossless grid case, but
 no value printed by the paper pins it: parity unpinned for the scheme itself.
+The adaptive nprobe/reorder stand-in (hardness, eq2) follows Eq. 2 with a
+closed-form p in place of the paper's trained model; Eq. 2 itself is pinned
+by hand-worked values and its limits, the choice of p is a reading.
 """
 
 from .ivfpq import (  # noqa: F401
+    adaptive_params,
     assign_lists,
+    eq2,
+    hardness,
     brute_force_knn,
     encode,
     coarse_scores,

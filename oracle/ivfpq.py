@@ -31,9 +31,15 @@ Readings where the paper is silent (all also listed in the design notes):
     (query, list) from the largest per-subspace range, round half to even,
     clamp at 255. The constant part B = (tree sum of lo_j) + bias.
   * Ties are broken by the smaller list index / point id everywhere.
+  * Adaptive nprobe / reorder (section 4.2, Eq. 2): the trained classifier
+    is replaced by a closed form of its "centroid distances" feature,
+    p = e_1 / e_K (see hardness); Eq. 2 is read as
+    min(v_max, v_min + floor(D * ReLU(p - p0) * (p + p1))).
 """
 
 from __future__ import annotations
+
+from typing import Optional
 
 import numpy as np
 
@@ -230,11 +236,65 @@ def rerank(q: np.ndarray, X: np.ndarray, cand_ids: np.ndarray, k: int,
 
 
 # --------------------------------------------------------------------------
+# Adaptive probing depth and re-rank size (section 4.2, Eq. 2).
+# --------------------------------------------------------------------------
+
+def hardness(sorted_scores: np.ndarray, K: int, metric: str):
+    """Closed-form stand-in for the trained easy/hard classifier of section
+    4.2.1, from its "centroid distances" feature (Table 3): the ratio of the
+    nearest to the K-th nearest centroid distance, p = e_1 / e_K in [0, 1]
+    (near 1: many lists about as near as the nearest one, a hard query).
+    e_i = s_i for L2 (squared distances); for inner product e_i = 1 + s_i,
+    which is half the squared distance to a normalised centroid for a unit
+    query. FP32, in this order: e = (1 + s); p = e_1 / e_K if e_K > 0 else 1;
+    clamped to [0, 1]."""
+    s1 = F32(sorted_scores[0])
+    sK = F32(sorted_scores[K - 1])
+    if metric == "ip":
+        e1, eK = F32(1.0) + s1, F32(1.0) + sK
+    else:
+        e1, eK = s1, sK
+    with np.errstate(divide="ignore", invalid="ignore"):
+        p = e1 / eK if eK > F32(0.0) else F32(1.0)
+    p = F32(p)
+    if not (p >= F32(0.0)):  # NaN or negative
+        p = F32(0.0) if p < F32(0.0) else F32(1.0)
+    return F32(min(p, F32(1.0)))
+
+
+def eq2(p, vmin: int, vmax: int, p0, p1) -> int:
+    """Eq. 2: min(v_max, v_min + floor(D * ReLU(p - p0) * (p + p1))), with
+    D = v_max - v_min, the products taken in this order in FP32; v_min is
+    first clamped to [1, v_max]."""
+    vmin = max(1, min(int(vmin), int(vmax)))
+    relu = F32(max(F32(p) - F32(p0), F32(0.0)))
+    g = F32(relu * (F32(p) + F32(p1)))
+    x = F32(F32(vmax - vmin) * g)
+    return int(min(vmax, vmin + int(np.floor(x))))
+
+
+def adaptive_params(scores: np.ndarray, nprobe_max: int, metric: str, nprobe_init: int,
+                    nprobe_min: int, reorder_min: int, R: int, k: int, p0, p1):
+    """Per-query (nprobe, reorder) of Alg. 2 (nprob from the initial clusters,
+    reorder from the same hardness): the coarse scores sorted by (score,
+    list), K = min(nprobe_init, nprobe_max) of them feed p, then Eq. 2 with
+    nprob_max = nprobe_max and reorder_max = R (reorder_min clamped to
+    [k, R])."""
+    P = select_probes(scores, nprobe_max)
+    K = max(1, min(int(nprobe_init), int(nprobe_max)))
+    p = hardness(scores[P], K, metric)
+    npb = eq2(p, nprobe_min, nprobe_max, p0, p1)
+    rmin = max(int(k), min(int(reorder_min), int(R)))
+    reo = eq2(p, rmin, R, p0, p1) if R > 0 else 0
+    return npb, reo, p
+
+
+# --------------------------------------------------------------------------
 # The whole search and the exhaustive reference.
 # --------------------------------------------------------------------------
 
 def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
-           want_stages: bool = False):
+           want_stages: bool = False, adaptive: Optional[dict] = None):
     """Run stages 1-6 for every query.
 
     index: dict with cm, cp [L,d] f32, codebooks [m,16,d'] f32, codes [n,m]
@@ -242,6 +302,10 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
     array. Returns dict with ids [nq,k] int64, dist [nq,k] f64, cand_a
     [nq,R] f32 (+inf padded), cand_id [nq,R] int64 (-1 padded) and, when
     want_stages, probes (list of arrays) and luts {(qi, list): (q8, lo, delta, B)}.
+    adaptive: dict(nprobe_init, nprobe_min, reorder_min, p0, p1) -- per query,
+    nprobe[qi] is nprob_max and R is reorder_max of Eq. 2; the pool keeps the
+    R best as always and the re-rank takes its reorder best (the same set a
+    pool of size reorder would hold). Adds nprobe_used, reorder_used.
     """
     metric = index["metric"]
     cm, cp = index["cm"], index["cp"]
@@ -255,10 +319,18 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
     cand_a = np.full((nq, R), np.inf, dtype=F32)
     cand_id = np.full((nq, R), -1, dtype=np.int64)
     probes, luts = [], {}
+    np_used = np.zeros(nq, dtype=np.int64)
+    reo_used = np.full(nq, R, dtype=np.int64)
     for qi in range(nq):
         q = np.asarray(Q[qi], dtype=F32)
         s = coarse_scores(q, cp, metric)
-        P = select_probes(s, int(nprobe[qi]))
+        npq = int(nprobe[qi])
+        if adaptive is not None:
+            npq, reo_used[qi], _ = adaptive_params(
+                s, npq, metric, adaptive["nprobe_init"], adaptive["nprobe_min"],
+                adaptive["reorder_min"], R, k, adaptive["p0"], adaptive["p1"])
+        np_used[qi] = npq
+        P = select_probes(s, npq)
         if want_stages:
             probes.append(P)
         T_ip = lut_float(q, None, codebooks, metric) if metric == "ip" else None
@@ -277,8 +349,11 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
         ca, cid = top_r(a, ids, R)
         cand_a[qi, :len(ca)] = ca
         cand_id[qi, :len(cid)] = cid
-        out_ids[qi], out_d[qi] = rerank(q, X, cid, k, metric)
+        out_ids[qi], out_d[qi] = rerank(q, X, cid[:reo_used[qi]], k, metric)
     res = dict(ids=out_ids, dist=out_d, cand_a=cand_a, cand_id=cand_id)
+    if adaptive is not None:
+        res["nprobe_used"] = np_used
+        res["reorder_used"] = reo_used
     if want_stages:
         res["probes"] = probes
         res["luts"] = luts

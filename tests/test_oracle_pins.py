@@ -335,3 +335,73 @@ def test_assign_lists_is_top1_of_float64_ranking(metric):
         s64 = ((cp - x) ** 2).sum(1) if metric == "l2" else -(cp @ x)
         mag = ((np.abs(cp) + np.abs(x)) ** 2).sum(1) if metric == "l2" else (np.abs(cp) * np.abs(x)).sum(1)
         assert s64[l] <= s64.min() + 2 * (cfg.d + 2) * EPS32 * mag.max()
+
+
+# ---------------------------------------------------------------------------
+# Adaptive probing depth and re-rank size (section 4.2, Eq. 2).
+# ---------------------------------------------------------------------------
+
+def test_eq2_hand_worked_values_and_limits():
+    F = np.float32
+    # v_min 8, v_max 64, p0 0.25, p1 0.5, p 0.75: ReLU(0.5) * 1.25 = 0.625,
+    # 56 * 0.625 = 35 (all exact in binary) -> 8 + 35 = 43.
+    assert oracle.eq2(F(0.75), 8, 64, 0.25, 0.5) == 43
+    # p <= p0: ReLU is 0 -> v_min.
+    for p in (0.0, 0.1, 0.25):
+        assert oracle.eq2(F(p), 8, 64, 0.25, 0.5) == 8
+    # p = 1, p0 = 0, p1 = 0: the full range -> v_max; the min() caps overshoot.
+    assert oracle.eq2(F(1.0), 8, 64, 0.0, 0.0) == 64
+    assert oracle.eq2(F(1.0), 8, 64, 0.0, 3.0) == 64
+    # v_min is clamped into [1, v_max]; the result never leaves [v_min, v_max].
+    assert oracle.eq2(F(0.0), 0, 10, 0.5, 0.0) == 1
+    assert oracle.eq2(F(0.9), 20, 10, 0.0, 0.0) == 10
+    prev = 0
+    for p in np.linspace(0, 1, 101, dtype=F):
+        v = oracle.eq2(p, 4, 256, 0.2, 0.3)
+        assert 4 <= v <= 256 and v >= prev  # non-decreasing in p for p1 >= -p0
+        prev = v
+    # floor, not rounding: 0.5 * (0.5 + 0.0) * 10 = 2.5 -> 2.
+    assert oracle.eq2(F(0.5), 0 + 1, 11, 0.0, 0.0) == 1 + 2
+
+
+def test_hardness_closed_form():
+    F = np.float32
+    # L2: ratio of nearest to K-th squared distance.
+    assert oracle.hardness(np.array([1, 2, 4, 8], F), 3, "l2") == F(0.25)
+    assert oracle.hardness(np.array([3, 3, 3], F), 3, "l2") == F(1.0)
+    # K = 1: the nearest against itself -> 1 (hardest) unless it is 0.
+    assert oracle.hardness(np.array([5, 9], F), 1, "l2") == F(1.0)
+    assert oracle.hardness(np.array([0, 9], F), 2, "l2") == F(0.0)
+    # IP: e = 1 + s (s = -<q, c_hat>), half the squared distance for unit q.
+    p = oracle.hardness(np.array([-0.9, -0.5], F), 2, "ip")
+    assert abs(float(p) - 0.2) < 1e-6
+    # Negative e (non-unit query) clamps to 0; e_K <= 0 gives 1.
+    assert oracle.hardness(np.array([-1.5, -0.5], F), 2, "ip") == F(0.0)
+    assert oracle.hardness(np.array([-1.5, -1.2], F), 2, "ip") == F(1.0)
+
+
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_adaptive_search_is_static_search_at_chosen_parameters(name):
+    cfg, X, Q, nprobe, index = cached_workload(name, 3000, 10, L=24, ncomp=16)
+    ad = dict(nprobe_init=3, nprobe_min=2, reorder_min=cfg.k, p0=0.3, p1=0.5)
+    npmax = np.full(len(Q), 12, dtype=np.int64)
+    res = oracle.search(index, X, Q, npmax, cfg.k, 60, adaptive=ad)
+    used, reo = res["nprobe_used"], res["reorder_used"]
+    assert ((used >= 2) & (used <= 12)).all() and ((reo >= cfg.k) & (reo <= 60)).all()
+    assert len(set(used.tolist())) > 1  # the queries differ in difficulty
+    # The same pools as the static search with the chosen nprobe, and the
+    # re-rank over the reorder best of them.
+    st = oracle.search(index, X, Q, used, cfg.k, 60)
+    assert np.array_equal(st["cand_id"], res["cand_id"])
+    for qi in range(len(Q)):
+        ids, _ = oracle.rerank(Q[qi], X, st["cand_id"][qi][:reo[qi]], cfg.k, index["metric"])
+        assert np.array_equal(ids, res["ids"][qi])
+    # Limits: p0 above every p -> the minima; p0 below, p1 large -> static.
+    lo = oracle.search(index, X, Q, npmax, cfg.k, 60,
+                       adaptive=dict(ad, p0=2.0))
+    assert (lo["nprobe_used"] == 2).all() and (lo["reorder_used"] == cfg.k).all()
+    hi = oracle.search(index, X, Q, npmax, cfg.k, 60,
+                       adaptive=dict(ad, p0=-1.0, p1=100.0))
+    full = oracle.search(index, X, Q, npmax, cfg.k, 60)
+    assert (hi["nprobe_used"] == 12).all() and (hi["reorder_used"] == 60).all()
+    assert np.array_equal(hi["ids"], full["ids"])
