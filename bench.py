@@ -42,6 +42,10 @@ TRAFFIC = {
                             fetch_kib=109676.8, write_kib=1727.1),
     ("c2", "plain"): dict(files=("scan.hip", "common.hpp"), sha="0d81da5cf7e0188b",
                           fetch_kib=5188205.3, write_kib=15625.0),
+    ("c5", "plain"): dict(files=("scan.hip", "common.hpp"), sha="0d81da5cf7e0188b",
+                          fetch_kib=48323161.8, write_kib=8192.0),
+    ("c5", "batched"): dict(files=("batched.hip", "common.hpp"), sha="e0b5458056e63aa8",
+                            fetch_kib=3828540.5, write_kib=3191.5),
 }
 
 
@@ -67,6 +71,8 @@ WORKLOAD_TEXT = {
           "PQ 50x4-bit, nprobe U{8..128}, k 10, rerank 200",
     "c4": "10M x 96 unit vectors (DEEP-like), IP, 10k queries, 4096 lists, PQ 48x4-bit, "
           "nprobe 64, k 100, rerank 1000",
+    "c5": "10M x 768 BF16 anisotropic unit vectors, IP, batch of 4096 queries, 8192 lists, "
+          "PQ 192x4-bit, nprobe U{4..256}, k 10, rerank 256",
 }
 
 
@@ -143,6 +149,58 @@ def roofline(config, cfg, r, code_bytes):
     return out
 
 
+def sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args):
+    """Static nprobe values (scaled per query for per-query workloads) and
+    adaptive settings (section 4.2, Eq. 2) of the batched BF16 form: QPS,
+    Recall@10 and the mean number of probed lists per query."""
+    import torch
+
+    import paper_2511_03298_amd as ivf
+    base = npd.to(torch.int64)
+    out = []
+
+    def run(label, opts, nprobe, max_np):
+        for _ in range(2):
+            g.search(Qd, nprobe, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = max(3, args.steps // 2)
+        for _ in range(steps):
+            g.search(Qd, nprobe, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        rec = recall_at_k(ids[:nrec].cpu().numpy(), gt_ids, 10)
+        if opts.adaptive:
+            used, reo = g.debug_adaptive(Qd, nprobe, cfg.k, cfg.R, max_nprobe=max_np, opts=opts)
+            mean_np, mean_reo = float(used.float().mean()), float(reo.float().mean())
+        else:
+            mean_np, mean_reo = float(nprobe.float().mean()), float(cfg.R)
+        r = dict(label=label, qps=round(cfg.nq / (ms / 1e3), 1), ms_per_step=round(ms, 4),
+                 recall_at_10=round(rec, 4), mean_nprobe=round(mean_np, 2),
+                 mean_reorder=round(mean_reo, 1), opts=ivf.opts_dict(opts))
+        log(f"sweep {label}: {r['qps']:.0f} q/s, recall@10 {rec:.4f}, mean nprobe {mean_np:.1f}, "
+            f"mean reorder {mean_reo:.0f}")
+        out.append(r)
+
+    top = int(base.max())
+    seen = set()
+    for f in (1 / 32, 1 / 16, 1 / 8, 1 / 4, 1 / 2, 1.0, 1.5, 2.0):
+        nprobe = torch.clamp((base.double() * f).round().to(torch.int32), 1, cfg.L)
+        sig = (int(nprobe.min()), int(nprobe.max()), int(nprobe.sum()))
+        if sig in seen:
+            continue
+        seen.add(sig)
+        run(f"static x{f:g}", ivf.make_opts(form="batched", coarse="bf16"), nprobe,
+            int(nprobe.max()))
+    # Adaptive (Eq. 2): the configured nprobe is the maximum per query.
+    for nmin, p0 in ((1, 0.3), (1, 0.6), (1, 0.9), (max(1, top // 8), 0.6)):
+        ad = dict(nprobe_init=8, nprobe_min=nmin, reorder_min=max(cfg.k, cfg.R // 2),
+                  p0=p0, p1=0.5)
+        run(f"adaptive min={nmin} p0={p0}",
+            ivf.make_opts(form="batched", coarse="bf16", adaptive=ad), npd, top)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +214,9 @@ def main():
                     help="skip the autotuned schedule (paper_2511_03298_amd.tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-queries", type=int, default=1000)
+    ap.add_argument("--sweep", action="store_true",
+                    help="also measure static nprobe values and adaptive (Eq. 2) settings with "
+                         "the batched BF16 form; adds a 'sweep' list to the JSON line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB before timing (a kernel of "
                          "known traffic for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -299,11 +360,14 @@ def main():
         "recall_at_10": round(best["recall_at_10"], 4),
         "forms": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()
                    if k_ not in ("stage_ms", "opts")} |
-                  {"stage_ms": {s: round(x, 4) for s, x in r["stage_ms"].items()}}
+                  {"stage_ms": {s: round(x, 4) for s, x in r["stage_ms"].items()},
+                   "roofline": roofline(args.config, cfg, r, code_bytes)}
                   for r in results],
         "roofline": roofline(args.config, cfg, best, code_bytes),
         "cpu_baseline": cpu,
     }
+    if args.sweep:
+        line["sweep"] = sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args)
     print(json.dumps(line), flush=True)
 
 

@@ -122,6 +122,24 @@ typedef struct {
                         query with more is recomputed by the plain scan.
                         0 = auto (a 2 GiB buffer for the batch, at most
                         16384 - rerank), else 256..16384 - rerank            */
+  /* Adaptive probing depth and re-rank size (section 4.2, Eq. 2), computed
+   * on the device after step 1 (ivf_search only). The paper's trained
+   * easy/hard classifier is replaced by a closed form of its centroid-
+   * distance feature: with the coarse scores s_1 <= s_2 <= ... of the query,
+   * e = s (L2) or 1 + s (IP), p = e_1 / e_K clamped to [0, 1] (1 when
+   * e_K <= 0), K = min(nprobe_init, nprobe[q]). Then, in FP32,
+   * g = max(p - p0, 0) * (p + p1) and
+   *   nprobe_q  = min(nprobe[q], n_min + floor((nprobe[q] - n_min) * g)),
+   *               n_min = clamp(nprobe_min, 1, nprobe[q]);
+   *   reorder_q = min(rerank,   r_min + floor((rerank - r_min) * g)),
+   *               r_min = clamp(reorder_min, k, rerank).
+   * The candidate pool still keeps the rerank best keys; the re-rank uses
+   * the reorder_q best of them (the set a pool of that size would hold). */
+  int32_t adaptive;    /* 0 or 1                                              */
+  int32_t nprobe_init; /* K >= 1                                              */
+  int32_t nprobe_min;  /* >= 1                                                */
+  int32_t reorder_min; /* >= 1                                                */
+  float p0, p1;        /* finite                                              */
 } ivf_search_opts;
 
 /* Defaults: EXACT coarse, widen 2, PLAIN form, no graph, auto pool and grid. */
@@ -172,12 +190,24 @@ ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries,
                                   float* out_dist, void* stream);
 
 /* Step 1 only: out_probes [nq,max_nprobe] int32 list indices ordered by
- * (canonical score, list index); entries past nprobe[q] are -1. */
+ * (canonical score, list index); entries past the query's probe count
+ * (nprobe[q], or the adaptive choice with opts->adaptive) are -1. */
 ivf_status ivf_debug_probes(const ivf_index* idx, const float* queries,
                             int32_t nq, const int32_t* nprobe,
                             int32_t max_nprobe, const ivf_search_opts* opts,
                             void* workspace, size_t workspace_bytes,
                             int32_t* out_probes, void* stream);
+
+/* Adaptive choice only (opts->adaptive = 1, section 4.2): per query the
+ * probe count and re-rank size ivf_search would use with these arguments,
+ * out_nprobe [nq] and out_reorder [nq] int32 (device); -1 for an invalid
+ * nprobe[q]. The workspace is sized by ivf_search_workspace_bytes for the
+ * same (nq, max_nprobe, k, rerank, opts). */
+ivf_status ivf_debug_adaptive(const ivf_index* idx, const float* queries, int32_t nq,
+                              const int32_t* nprobe, int32_t max_nprobe, int32_t k,
+                              int32_t rerank, const ivf_search_opts* opts, void* workspace,
+                              size_t workspace_bytes, int32_t* out_nprobe,
+                              int32_t* out_reorder, void* stream);
 
 /* The approximate coarse score matrix of an MFMA form (opts->coarse != EXACT):
  * out_scores [nq,L] FP32, |c_l|^2 - 2<q,c_l> (L2) or -<q,c_l> (IP) computed

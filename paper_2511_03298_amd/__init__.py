@@ -27,7 +27,7 @@ EXPORTED = [
     "ivf_search", "ivf_search_with_probes", "ivf_debug_probes", "ivf_debug_luts",
     "ivf_debug_candidates", "ivf_get_table_layout", "ivf_get_device_error", "ivf_destroy",
     "ivf_last_error", "ivf_profile_enable", "ivf_profile_read", "ivf_debug_coarse_scores",
-    "ivf_assign_workspace_bytes", "ivf_assign", "ivf_encode",
+    "ivf_assign_workspace_bytes", "ivf_assign", "ivf_encode", "ivf_debug_adaptive",
 ]
 STAGES = ("coarse", "select", "prep", "scan", "merge", "rerank")
 
@@ -51,7 +51,10 @@ class SearchOpts(ctypes.Structure):
     _fields_ = [("coarse", ctypes.c_int32), ("widen", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("pool_cap", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("rounds", ctypes.c_int32), ("spill_cap", ctypes.c_int32)]
+                ("rounds", ctypes.c_int32), ("spill_cap", ctypes.c_int32),
+                ("adaptive", ctypes.c_int32), ("nprobe_init", ctypes.c_int32),
+                ("nprobe_min", ctypes.c_int32), ("reorder_min", ctypes.c_int32),
+                ("p0", ctypes.c_float), ("p1", ctypes.c_float)]
 
 
 class TableLayout(ctypes.Structure):
@@ -88,6 +91,7 @@ def _declare(lib):
         "ivf_assign_workspace_bytes": (SZ, [I32, I32, I32, I32]),
         "ivf_assign": (I32, [P, I32, I32, I32, P, I64, I32, I32, I32, P, SZ, P, P]),
         "ivf_encode": (I32, [P, I64, I32, P, P, P, I32, P, P]),
+        "ivf_debug_adaptive": (I32, [P, P, I32, P, I32, I32, I32, P, P, SZ, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -120,21 +124,35 @@ def check(status: int):
 
 def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
               use_graph: bool = False, pool_cap: int = 0, grid: int = 0,
-              rounds: int = 0, spill_cap: int = 0) -> SearchOpts:
+              rounds: int = 0, spill_cap: int = 0,
+              adaptive: Optional[dict] = None) -> SearchOpts:
+    """adaptive: dict(nprobe_init, nprobe_min, reorder_min, p0, p1) turns on
+    the per-query probe count and re-rank size of Eq. 2 (nprobe[q] and
+    rerank are the maxima)."""
     o = SearchOpts()
     lib().ivf_default_opts(ctypes.byref(o))
     o.coarse, o.widen, o.form = COARSE[coarse], int(widen), FORM[form]
     o.use_graph, o.pool_cap, o.grid = int(bool(use_graph)), int(pool_cap), int(grid)
     o.rounds, o.spill_cap = int(rounds), int(spill_cap)
+    if adaptive:
+        o.adaptive = 1
+        o.nprobe_init = int(adaptive["nprobe_init"])
+        o.nprobe_min = int(adaptive["nprobe_min"])
+        o.reorder_min = int(adaptive["reorder_min"])
+        o.p0, o.p1 = float(adaptive["p0"]), float(adaptive["p1"])
     return o
 
 
 def opts_dict(o: SearchOpts) -> dict:
     inv_c = {v: k for k, v in COARSE.items()}
     inv_f = {v: k for k, v in FORM.items()}
-    return dict(coarse=inv_c[o.coarse], widen=o.widen, form=inv_f[o.form],
-                use_graph=bool(o.use_graph), pool_cap=o.pool_cap, grid=o.grid,
-                rounds=o.rounds, spill_cap=o.spill_cap)
+    d = dict(coarse=inv_c[o.coarse], widen=o.widen, form=inv_f[o.form],
+             use_graph=bool(o.use_graph), pool_cap=o.pool_cap, grid=o.grid,
+             rounds=o.rounds, spill_cap=o.spill_cap)
+    if o.adaptive:
+        d["adaptive"] = dict(nprobe_init=o.nprobe_init, nprobe_min=o.nprobe_min,
+                             reorder_min=o.reorder_min, p0=o.p0, p1=o.p1)
+    return d
 
 
 def _ptr(t) -> Optional[int]:
@@ -282,6 +300,22 @@ class GpuIndex:
                                            k, rerank, ctypes.byref(opts), ws.data_ptr(),
                                            ws.numel(), _ptr(ids), _ptr(dist), _stream()))
         return ids, dist
+
+    def debug_adaptive(self, queries, nprobe, k: int, rerank: int, max_nprobe=None, opts=None):
+        """Per-query (nprobe, reorder) the adaptive search would use."""
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npb = self._nprobe(nprobe, nq)
+        if max_nprobe is None:
+            max_nprobe = max(1, min(int(npb.max().item()), self.L))
+        ws = self.workspace(nq, max_nprobe, k, rerank, opts)
+        out_n = torch.empty(nq, dtype=torch.int32, device=self.device)
+        out_r = torch.empty(nq, dtype=torch.int32, device=self.device)
+        check(lib().ivf_debug_adaptive(self._h, _ptr(q), nq, _ptr(npb), max_nprobe, k, rerank,
+                                       ctypes.byref(opts), ws.data_ptr(), ws.numel(),
+                                       _ptr(out_n), _ptr(out_r), _stream()))
+        return out_n, out_r
 
     def debug_probes(self, queries, nprobe, max_nprobe=None, opts=None):
         import torch

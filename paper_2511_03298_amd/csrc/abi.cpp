@@ -2,6 +2,7 @@
 // workspace layout, and the order in which the kernels are enqueued.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -140,6 +141,12 @@ ivf_status check_device() {
   return IVF_OK;
 }
 
+uint32_t f32_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
 ivf_status check_opts(const ivf_search_opts& o) {
   if (o.coarse < IVF_COARSE_EXACT || o.coarse > IVF_COARSE_FP8)
     return fail(IVF_ERR_INVALID_ARG, "opts.coarse out of range");
@@ -154,6 +161,14 @@ ivf_status check_opts(const ivf_search_opts& o) {
   if (o.rounds < 0 || o.rounds > 8) return fail(IVF_ERR_INVALID_ARG, "opts.rounds must be in 0..8");
   if (o.spill_cap != 0 && (o.spill_cap < 256 || o.spill_cap > 16384 - 256))
     return fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be 0 or in 256..16128");
+  if (o.adaptive != 0 && o.adaptive != 1)
+    return fail(IVF_ERR_INVALID_ARG, "opts.adaptive must be 0 or 1");
+  if (o.adaptive) {
+    if (o.nprobe_init < 1 || o.nprobe_min < 1 || o.reorder_min < 1)
+      return fail(IVF_ERR_INVALID_ARG, "opts.nprobe_init, nprobe_min, reorder_min must be >= 1");
+    if (!std::isfinite(o.p0) || !std::isfinite(o.p1))
+      return fail(IVF_ERR_INVALID_ARG, "opts.p0 and opts.p1 must be finite");
+  }
   return IVF_OK;
 }
 
@@ -195,6 +210,7 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   w.scores = (float*)take(nqs * t.L * 4);
   w.probes = (int32_t*)take(nqs * max_nprobe * 4);
   w.nprobe_eff = (int32_t*)take(nqs * 4);
+  w.reorder_eff = (int32_t*)take(nqs * 4);
   w.bias = (float*)take(nqs * max_nprobe * 4);
   w.cand = (uint64_t*)take(nqs * rerank * 8);
   if (o.coarse != IVF_COARSE_EXACT) {
@@ -242,6 +258,12 @@ void ivf_default_opts(ivf_search_opts* o) {
   o->grid = 0;
   o->rounds = 0;
   o->spill_cap = 0;
+  o->adaptive = 0;
+  o->nprobe_init = 8;
+  o->nprobe_min = 1;
+  o->reorder_min = 1;
+  o->p0 = 0.0f;
+  o->p1 = 0.0f;
 }
 
 const char* ivf_last_error(void) { return g_last_error.c_str(); }
@@ -493,24 +515,28 @@ ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, int32_t nq,
     IVF_HIP(launch_scan_plain(t, Q, nq, max_nprobe, rerank, w, s));
   }
   IVF_HIP(prof_mark(idx, s, IVF_STAGE_RERANK));
-  if (out_ids) IVF_HIP(launch_rerank(t, Q, nq, k, rerank, w, out_ids, out_dist, s));
+  if (out_ids)
+    IVF_HIP(launch_rerank(t, Q, nq, k, rerank, o.adaptive ? w.reorder_eff : nullptr, w, out_ids,
+                          out_dist, s));
   IVF_HIP(prof_mark(idx, s, IVF_NSTAGES));
   return IVF_OK;
 }
 
 ivf_status run_coarse(const ivf_index* idx, const float* Q, int32_t nq, const int32_t* nprobe,
-                      int32_t max_nprobe, const ivf_search_opts& o, const Workspace& w,
-                      hipStream_t s) {
+                      int32_t max_nprobe, int32_t k, int32_t rerank, const ivf_search_opts& o,
+                      const Workspace& w, hipStream_t s) {
   const Tables& t = idx->t;
+  const AdaptiveArgs ad{o.adaptive, o.nprobe_init, o.nprobe_min, o.reorder_min, k, rerank,
+                        o.p0, o.p1};
   IVF_HIP(prof_mark(idx, s, IVF_STAGE_COARSE));
   if (o.coarse == IVF_COARSE_EXACT) {
     IVF_HIP(launch_coarse_exact(t, Q, nq, w.scores, s));
     IVF_HIP(prof_mark(idx, s, IVF_STAGE_SELECT));
-    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, 1, false, w, s));
+    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, 1, false, w, s, ad));
   } else {
     IVF_HIP(launch_coarse_mfma(t, Q, nq, o.coarse, w, s));
     IVF_HIP(prof_mark(idx, s, IVF_STAGE_SELECT));
-    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, o.widen, true, w, s));
+    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, o.widen, true, w, s, ad));
   }
   return IVF_OK;
 }
@@ -538,6 +564,9 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
                                  (uint64_t)rerank, (uint64_t)o.coarse, (uint64_t)o.widen,
                                  (uint64_t)o.form, (uint64_t)o.pool_cap, (uint64_t)o.grid,
                                  (uint64_t)o.rounds, (uint64_t)o.spill_cap,
+                                 (uint64_t)o.adaptive, (uint64_t)o.nprobe_init,
+                                 (uint64_t)o.nprobe_min, (uint64_t)o.reorder_min,
+                                 (uint64_t)f32_bits(o.p0), (uint64_t)f32_bits(o.p1),
                                  (uint64_t)(uintptr_t)queries,
                                  (uint64_t)(uintptr_t)nprobe, (uint64_t)(uintptr_t)workspace,
                                  (uint64_t)(uintptr_t)out_ids, (uint64_t)(uintptr_t)out_dist};
@@ -558,7 +587,7 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
     IVF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     ivf_status cst = IVF_OK;
     if (launch_fill_u32((uint32_t*)w.err, 0u, 4, s) != hipSuccess) cst = IVF_ERR_DEVICE;
-    if (cst == IVF_OK) cst = run_coarse(idx, queries, nq, nprobe, max_nprobe, o, w, s);
+    if (cst == IVF_OK) cst = run_coarse(idx, queries, nq, nprobe, max_nprobe, k, rerank, o, w, s);
     if (cst == IVF_OK)
       cst = run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);
     hipGraph_t g = nullptr;
@@ -585,7 +614,7 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
   }
   IVF_HIP(prof_begin(idx));
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
-  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, o, w, s);
+  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, k, rerank, o, w, s);
   if (st != IVF_OK) return st;
   return run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);
 }
@@ -601,6 +630,8 @@ ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries, in
   ivf_status st = begin_search(idx, nq, max_nprobe, k, rerank, opts, workspace, workspace_bytes,
                                &o, &w);
   if (st != IVF_OK) return st;
+  if (o.adaptive)
+    return fail(IVF_ERR_INVALID_ARG, "opts.adaptive needs the coarse step (use ivf_search)");
   if (nq == 0) return IVF_OK;
   if (!queries || !probes || !nprobe || !out_ids || !out_dist)
     return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
@@ -623,10 +654,33 @@ ivf_status ivf_debug_probes(const ivf_index* idx, const float* queries, int32_t 
   if (!queries || !nprobe || !out_probes) return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
-  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, o, w, s);
+  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, 1, 1, o, w, s);
   if (st != IVF_OK) return st;
   IVF_HIP(hipMemcpyAsync(out_probes, w.probes, (size_t)nq * max_nprobe * 4,
                          hipMemcpyDeviceToDevice, s));
+  return IVF_OK;
+}
+
+ivf_status ivf_debug_adaptive(const ivf_index* idx, const float* queries, int32_t nq,
+                              const int32_t* nprobe, int32_t max_nprobe, int32_t k,
+                              int32_t rerank, const ivf_search_opts* opts, void* workspace,
+                              size_t workspace_bytes, int32_t* out_nprobe,
+                              int32_t* out_reorder, void* stream) {
+  ivf_search_opts o;
+  Workspace w;
+  ivf_status st = begin_search(idx, nq, max_nprobe, k, rerank, opts, workspace, workspace_bytes,
+                               &o, &w);
+  if (st != IVF_OK) return st;
+  if (!o.adaptive) return fail(IVF_ERR_INVALID_ARG, "opts.adaptive must be 1");
+  if (nq == 0) return IVF_OK;
+  if (!queries || !nprobe || !out_nprobe || !out_reorder)
+    return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
+  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, k, rerank, o, w, s);
+  if (st != IVF_OK) return st;
+  IVF_HIP(hipMemcpyAsync(out_nprobe, w.nprobe_eff, (size_t)nq * 4, hipMemcpyDeviceToDevice, s));
+  IVF_HIP(hipMemcpyAsync(out_reorder, w.reorder_eff, (size_t)nq * 4, hipMemcpyDeviceToDevice, s));
   return IVF_OK;
 }
 
@@ -672,6 +726,8 @@ ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries, int3
   ivf_status st = begin_search(idx, nq, max_nprobe, 1, rerank, opts, workspace, workspace_bytes,
                                &o, &w);
   if (st != IVF_OK) return st;
+  if (o.adaptive)
+    return fail(IVF_ERR_INVALID_ARG, "opts.adaptive needs the coarse step (use ivf_search)");
   if (nq == 0) return IVF_OK;
   if (!queries || !probes || !nprobe || !out_keys)
     return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");

@@ -121,6 +121,19 @@ __device__ __forceinline__ float canonical_score(const Tables& t, const float* q
   return ip ? plus_zero(-acc) : acc;
 }
 
+// Eq. 2 (section 4.2) in FP32, in the order written: the adaptive count
+// between v_min (clamped to [1, v_max]) and v_max for hardness p.
+__device__ __forceinline__ int32_t eq2_count(float p, int32_t vmin, int32_t vmax, float p0,
+                                             float p1) {
+  vmin = vmin < 1 ? 1 : (vmin > vmax ? vmax : vmin);
+  const float relu = fmaxf(p - p0, 0.0f);
+  const float g = relu * (p + p1);
+  const float span = (float)(vmax - vmin);
+  const float x = fminf(span * g, span + 1.0f);  // caps the conversion only
+  const int32_t v = vmin + (int32_t)floorf(x);
+  return v < vmax ? v : vmax;
+}
+
 // One workgroup per query. Keys (ord(score) << 32 | list) live in LDS; the
 // wanted count is selected by radix selection and sorted. With `rescore`,
 // the first selection keeps widen*nprobe lists by the (approximate) score
@@ -131,7 +144,9 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
                                                      int32_t rescore, const float* __restrict__ S,
                                                      int32_t* __restrict__ probes,
                                                      int32_t* __restrict__ nprobe_eff,
-                                                     int32_t* __restrict__ err) {
+                                                     int32_t* __restrict__ err,
+                                                     AdaptiveArgs ad,
+                                                     int32_t* __restrict__ reorder_eff) {
   extern __shared__ uint64_t keys[];  // [pow2_ceil(L)]
   __shared__ SelectScratch sc;
   __shared__ float qv[1024];
@@ -142,6 +157,7 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
   if (np < 1 || np > max_nprobe) {
     if (tid == 0) {
       nprobe_eff[q] = -1;
+      if (reorder_eff) reorder_eff[q] = -1;
       atomicOr(err, 1);
     }
     for (int p = tid; p < max_nprobe; p += blockDim.x) probes[(size_t)q * max_nprobe + p] = -1;
@@ -188,18 +204,44 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
     for (uint32_t i = n + tid; i < n2; i += blockDim.x) keys[i] = KEY_NONE;
     block_bitonic_sort(keys, n2);
   }
+  // Adaptive probe count and re-rank size from the sorted canonical scores.
+  __shared__ int32_t np_used;
+  if (tid == 0) {
+    int32_t npu = np, reo = ad.R;
+    if (ad.on) {
+      const int K = ad.nprobe_init < 1 ? 1 : (ad.nprobe_init > np ? np : ad.nprobe_init);
+      const bool ip = t.metric == IVF_METRIC_IP;
+      const float s1 = ord2f((uint32_t)(sorted[0] >> 32));
+      const float sK = ord2f((uint32_t)(sorted[K - 1] >> 32));
+      const float e1 = ip ? 1.0f + s1 : s1;
+      const float eK = ip ? 1.0f + sK : sK;
+      float p = eK > 0.0f ? e1 / eK : 1.0f;
+      if (!(p >= 0.0f)) p = p < 0.0f ? 0.0f : 1.0f;
+      p = fminf(p, 1.0f);
+      npu = eq2_count(p, ad.nprobe_min, np, ad.p0, ad.p1);
+      const int32_t rmin = ad.reorder_min < ad.k ? ad.k
+                                                 : (ad.reorder_min > ad.R ? ad.R : ad.reorder_min);
+      reo = eq2_count(p, rmin, ad.R, ad.p0, ad.p1);
+    }
+    np_used = npu;
+    nprobe_eff[q] = npu;
+    if (reorder_eff) reorder_eff[q] = reo;
+  }
+  __syncthreads();
+  const int npu = np_used;
   for (int p = tid; p < max_nprobe; p += blockDim.x)
-    probes[(size_t)q * max_nprobe + p] = p < np ? (int32_t)(uint32_t)sorted[p] : -1;
-  if (tid == 0) nprobe_eff[q] = np;
+    probes[(size_t)q * max_nprobe + p] = p < npu ? (int32_t)(uint32_t)sorted[p] : -1;
 }
 
 hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
                                 const int32_t* nprobe, int32_t max_nprobe, int32_t widen,
-                                bool rescore, const Workspace& w, hipStream_t s) {
+                                bool rescore, const Workspace& w, hipStream_t s,
+                                const AdaptiveArgs& ad) {
   if (nq == 0) return hipSuccess;
   size_t lds = (size_t)pow2_ceil((uint32_t)t.L) * sizeof(uint64_t);
   hipLaunchKernelGGL(select_kernel, dim3(nq), dim3(256), lds, s, t, Q, nq, nprobe, max_nprobe,
-                     widen, rescore ? 1 : 0, w.scores, w.probes, w.nprobe_eff, w.err);
+                     widen, rescore ? 1 : 0, w.scores, w.probes, w.nprobe_eff, w.err, ad,
+                     w.reorder_eff);
   return hipGetLastError();
 }
 

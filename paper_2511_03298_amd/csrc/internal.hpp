@@ -64,6 +64,7 @@ struct Workspace {
   float* scores;        // [nq][L] coarse scores (exact or approximate)
   int32_t* probes;      // [nq][max_nprobe]
   int32_t* nprobe_eff;  // [nq]; -1 marks an invalid request
+  int32_t* reorder_eff; // [nq] re-rank size (adaptive form; else rerank)
   float* bias;          // [nq][max_nprobe] per-(q,list) constant (IP), else unused
   uint64_t* cand;       // [nq][rerank]
   int32_t* err;         // [4] device error word
@@ -107,10 +108,16 @@ hipError_t launch_coarse_mfma(const Tables& t, const float* Q, int32_t nq, int c
                               const Workspace& w, hipStream_t s);
 // Select per query the nprobe[q]*widen best lists of `scores` and, when
 // widen > 1 or the scores are approximate, re-score them canonically and
-// keep the nprobe[q] best. Writes probes / nprobe_eff.
+// keep the nprobe[q] best. Writes probes / nprobe_eff; with `ad.on`, the
+// adaptive probe count and re-rank size of Eq. 2 (reorder_eff).
+struct AdaptiveArgs {
+  int32_t on, nprobe_init, nprobe_min, reorder_min, k, R;
+  float p0, p1;
+};
 hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
                                 const int32_t* nprobe, int32_t max_nprobe, int32_t widen,
-                                bool rescore, const Workspace& w, hipStream_t s);
+                                bool rescore, const Workspace& w, hipStream_t s,
+                                const AdaptiveArgs& ad = AdaptiveArgs{});
 hipError_t launch_copy_probes(const int32_t* probes, const int32_t* nprobe, int32_t nq,
                               int32_t max_nprobe, int32_t L, const Workspace& w,
                               hipStream_t s);
@@ -135,7 +142,9 @@ hipError_t launch_batched_redo(const Tables& t, const float* Q, int32_t nq, int3
 hipError_t launch_debug_luts(const Tables& t, const float* Q, int32_t nq, const int32_t* probes,
                              const int32_t* nprobe, int32_t max_nprobe, uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
                              hipStream_t s);
+// reorder: per-query re-rank sizes (<= rerank) or nullptr for all of them.
 hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k, int32_t rerank,
+                         const int32_t* reorder,
                          const Workspace& w, int64_t* out_ids, float* out_dist, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_sort_rows(uint64_t* cand, int32_t nq, int32_t R, hipStream_t s);

@@ -59,6 +59,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
                                                      int32_t k, int32_t R,
                                                      const int32_t* __restrict__ nprobe_eff,
                                                      const uint64_t* __restrict__ cand,
+                                                     const int32_t* __restrict__ reorder,
                                                      int64_t* __restrict__ out_ids,
                                                      float* __restrict__ out_dist) {
   extern __shared__ __align__(16) unsigned char dyn[];
@@ -76,7 +77,19 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
     return;
   }
   for (int i = tid; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
+  // The pool into LDS; with a per-query re-rank size, its `reorder` smallest
+  // keys only (the set a pool of that size would hold). Keys are unique apart
+  // from the empty-slot value, which sorts last.
+  __shared__ SelectScratch sc;
+  __shared__ uint32_t cnt;
+  for (int i = tid; i < R; i += blockDim.x) keys[i] = cand[(size_t)q * R + i];
   __syncthreads();
+  int32_t nc = R;
+  if (reorder && reorder[q] < R) {
+    KeyUnion u{keys, (uint32_t)R, nullptr, 0};
+    const uint64_t thr = block_kth(u, (uint32_t)reorder[q], &sc);
+    nc = (int32_t)block_compact_le(keys, (uint32_t)R, thr, &cnt);
+  }
   constexpr int G = 8;
   constexpr int GROUPS = IVF_BLOCK / G;
   const int g = tid / G, gl = tid % G;
@@ -85,13 +98,13 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   const bool vec = row_bytes % 16 == 0;
   const int nvec = t.d / per_vec;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(t.base);
-  for (int c0 = 0; c0 < R; c0 += GROUPS * U) {
+  for (int c0 = 0; c0 < nc; c0 += GROUPS * U) {
     uint64_t key[U];
     float acc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = c0 + u * GROUPS + g;
-      key[u] = c < R ? cand[(size_t)q * R + c] : KEY_NONE;
+      key[u] = c < nc ? keys[c] : KEY_NONE;
       acc[u] = 0.0f;
     }
     if (vec) {
@@ -127,7 +140,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
     for (int u = 0; u < U; ++u) {
       for (int s = 1; s < G; s <<= 1) acc[u] = acc[u] + __shfl_xor(acc[u], s, G);
       const int c = c0 + u * GROUPS + g;
-      if (gl == 0 && c < R) {
+      if (gl == 0 && c < nc) {
         if (key[u] == KEY_NONE) {
           keys[c] = KEY_NONE;
         } else {
@@ -141,9 +154,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   }
   __syncthreads();
   // Top k: select the k smallest keys, then sort only those.
-  __shared__ SelectScratch sc;
-  __shared__ uint32_t cnt;
-  uint32_t n = (uint32_t)R;
+  uint32_t n = (uint32_t)nc;
   if ((uint32_t)k < n) {
     KeyUnion u{keys, n, nullptr, 0};
     const uint64_t thr = block_kth(u, (uint32_t)k, &sc);
@@ -152,7 +163,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   // Ascending order of the (at most k) kept keys: by rank into the free space
   // behind them when there is room, else bitonic.
   const uint64_t* sorted = keys;
-  if (n <= 512 && 2 * n <= pow2_ceil((uint32_t)R)) {
+  if (n <= 512 && n + n <= pow2_ceil((uint32_t)R)) {
     __syncthreads();
     block_rank_sort(keys, n, keys + n);
     sorted = keys + n;
@@ -162,7 +173,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
     block_bitonic_sort(keys, n2);
   }
   for (int i = tid; i < k; i += blockDim.x) {
-    const uint64_t kk = (uint32_t)i < n ? sorted[i] : KEY_NONE;
+    const uint64_t kk = (uint32_t)i < n ? sorted[i] : KEY_NONE;  // n may be < k
     if (kk == KEY_NONE) {
       out_ids[(size_t)q * k + i] = -1;
       out_dist[(size_t)q * k + i] = ip ? -INFINITY : INFINITY;
@@ -175,11 +186,12 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
 }
 
 hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k, int32_t rerank,
-                         const Workspace& w, int64_t* out_ids, float* out_dist, hipStream_t s) {
+                         const int32_t* reorder, const Workspace& w, int64_t* out_ids,
+                         float* out_dist, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   size_t lds = (size_t)pow2_ceil((uint32_t)rerank) * 8 + (size_t)t.d * 4;
   hipLaunchKernelGGL(rerank_kernel<4>, dim3(nq), dim3(256), lds, s, t, Q, k, rerank, w.nprobe_eff,
-                     w.cand, out_ids, out_dist);
+                     w.cand, reorder, out_ids, out_dist);
   return hipGetLastError();
 }
 

@@ -113,12 +113,33 @@ def test_search_argument_validation_without_index():
     assert lib.ivf_get_device_error(None, None, None) == -1
 
 
+def test_every_export_has_a_prototype():
+    # Without argtypes ctypes would pass device pointers as 32-bit ints.
+    ivf, lib = _lib()
+    for name in ivf.EXPORTED:
+        assert getattr(lib, name).argtypes is not None, name
+
+
 def test_default_opts():
     ivf, lib = _lib()
     o = ivf.SearchOpts()
     lib.ivf_default_opts(ctypes.byref(o))
     assert (o.coarse, o.widen, o.form, o.use_graph, o.pool_cap, o.grid, o.rounds) == \
         (0, 2, 0, 0, 0, 0, 0)
+    assert (o.spill_cap, o.adaptive) == (0, 0)
+
+
+def test_adaptive_opts_validated():
+    ivf, lib = _lib()
+    ok = ivf.make_opts(adaptive=dict(nprobe_init=4, nprobe_min=2, reorder_min=10, p0=0.2, p1=0.5))
+    assert ivf.opts_dict(ok)["adaptive"]["nprobe_min"] == 2
+    for field, value in (("adaptive", 2), ("nprobe_init", 0), ("nprobe_min", 0),
+                         ("reorder_min", 0), ("p0", float("nan")), ("p1", float("inf"))):
+        o = ivf.make_opts(adaptive=dict(nprobe_init=4, nprobe_min=2, reorder_min=10,
+                                        p0=0.2, p1=0.5))
+        setattr(o, field, value)
+        assert lib.ivf_search_workspace_bytes(None, 1, 1, 1, 1, ctypes.byref(o)) == 0
+        assert "opts." in ivf.last_error()
 
 
 @pytest.mark.parametrize("field,value", [("pool_cap", 100), ("pool_cap", 20000), ("grid", 9),

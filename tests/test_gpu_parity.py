@@ -440,6 +440,64 @@ def test_stage_profile_sums_rounds():
 
 
 # ---------------------------------------------------------------------------
+# Adaptive probing depth and re-rank size (section 4.2, Eq. 2).
+# ---------------------------------------------------------------------------
+
+ADAPT = dict(nprobe_init=3, nprobe_min=2, reorder_min=1, p0=0.3, p1=0.5)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adaptive_choice_and_search(name):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    ad = dict(ADAPT, reorder_min=max(cfg.k, cfg.R // 4))
+    # Per-query choice: integers decided in FP32 from canonical scores.
+    n_used, r_used = g.debug_adaptive(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(adaptive=ad))
+    n_used, r_used = n_used.cpu().numpy(), r_used.cpu().numpy()
+    want_n, want_r = [], []
+    for qi in range(len(Q)):
+        s = oracle.coarse_scores(np.asarray(Q[qi], np.float32), index["cp"], cfg.metric)
+        npq, reo, _ = oracle.adaptive_params(s, int(nprobe[qi]), cfg.metric, ad["nprobe_init"],
+                                             ad["nprobe_min"], ad["reorder_min"], cfg.R, cfg.k,
+                                             ad["p0"], ad["p1"])
+        want_n.append(npq)
+        want_r.append(reo)
+    assert np.array_equal(n_used, want_n) and np.array_equal(r_used, want_r)
+    # Probe export: the chosen count, then -1.
+    P = g.debug_probes(Q, nprobe, opts=ivf.make_opts(adaptive=ad)).cpu().numpy()
+    for qi in range(len(Q)):
+        assert (P[qi, want_n[qi]:] == -1).all()
+    # Search: plain and batched identical; the oracle's adaptive search.
+    ip, dp = g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(form="plain", adaptive=ad))
+    ib, db = g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(form="batched", adaptive=ad))
+    assert torch.equal(ip, ib) and torch.equal(dp.view(torch.int32), db.view(torch.int32))
+    ores = oracle.search(index, X, Q, nprobe, cfg.k, cfg.R, adaptive=ad)
+    assert np.array_equal(ores["nprobe_used"], want_n)
+    check_final(ib.cpu().numpy(), db.cpu().numpy(), ores, X, Q, cfg.metric,
+                exact_ids=(cfg.dist == "int255"))
+    assert g.device_error() == 0
+
+
+def test_adaptive_limits_and_rejections():
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case("c3s")
+    # p0 above every hardness: the minima; the pools are the static ones at
+    # nprobe_min and the re-rank uses reorder_min of them.
+    ad = dict(ADAPT, p0=2.0, reorder_min=cfg.k)
+    n_used, r_used = g.debug_adaptive(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(adaptive=ad))
+    assert (n_used.cpu() == ADAPT["nprobe_min"]).all() and (r_used.cpu() == cfg.k).all()
+    ia, da = g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(adaptive=ad))
+    ores = oracle.search(index, X, Q, np.full(len(Q), ADAPT["nprobe_min"]), cfg.k, cfg.R)
+    for qi in range(len(Q)):
+        ids, _ = oracle.rerank(Q[qi], X, ores["cand_id"][qi][:cfg.k], cfg.k, cfg.metric)
+        assert set(ia[qi].cpu().numpy().tolist()) == set(ids.tolist())
+    # Caller-given probes have no coarse scores: rejected.
+    with pytest.raises(ivf.IvfError):
+        g.search_with_probes(Q, probes_tensor(res, nprobe), nprobe, cfg.k, cfg.R,
+                             opts=ivf.make_opts(adaptive=ad))
+
+
+# ---------------------------------------------------------------------------
 # Index construction on the GPU (Alg. 1): assignment and encoding.
 # ---------------------------------------------------------------------------
 
