@@ -19,6 +19,7 @@ by hand-worked values and its limits, the choice of p is a reading.
 from .ivfpq import (  # noqa: F401
     adaptive_params,
     assign_lists,
+    component_filter,
     eq2,
     hardness,
     brute_force_knn,

@@ -236,6 +236,31 @@ def rerank(q: np.ndarray, X: np.ndarray, cand_ids: np.ndarray, k: int,
 
 
 # --------------------------------------------------------------------------
+# Component filtration (section 4.3; Alg. 1 FilterComponents, Alg. 2).
+# --------------------------------------------------------------------------
+
+def component_filter(X: np.ndarray, threshold: float):
+    """Dimensions kept by the statistical filtration of section 4.3.
+
+    For every dimension t over all rows: mean mu_t and standard deviation
+    sigma_t (population, FP64), and the share of components that are zero or
+    lie within one standard deviation of the mean, |x_t - mu_t| <= sigma_t.
+    A dimension whose share exceeds `threshold` is dropped. Returns the kept
+    dimension indices (ascending) and the shares."""
+    X64 = np.asarray(X, dtype=np.float64)
+    n, d = X64.shape
+    share = np.empty(d, dtype=np.float64)
+    for t in range(d):
+        col = X64[:, t]
+        mu = col.sum() / n
+        sigma = np.sqrt(((col - mu) ** 2).sum() / n)
+        quiet = (col == 0.0) | (np.abs(col - mu) <= sigma)
+        share[t] = quiet.sum() / n
+    keep = np.nonzero(share <= threshold)[0].astype(np.int64)
+    return keep, share
+
+
+# --------------------------------------------------------------------------
 # Adaptive probing depth and re-rank size (section 4.2, Eq. 2).
 # --------------------------------------------------------------------------
 
@@ -302,6 +327,9 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
     array. Returns dict with ids [nq,k] int64, dist [nq,k] f64, cand_a
     [nq,R] f32 (+inf padded), cand_id [nq,R] int64 (-1 padded) and, when
     want_stages, probes (list of arrays) and luts {(qi, list): (q8, lo, delta, B)}.
+    index["dims"] (optional): kept dimensions of component filtration; the
+    index lives in that subspace, stages 1-5 use q[dims] and the re-rank the
+    full query against the full rows X (Alg. 2).
     adaptive: dict(nprobe_init, nprobe_min, reorder_min, p0, p1) -- per query,
     nprobe[qi] is nprob_max and R is reorder_max of Eq. 2; the pool keeps the
     R best as always and the re-rank takes its reorder best (the same set a
@@ -321,8 +349,10 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
     probes, luts = [], {}
     np_used = np.zeros(nq, dtype=np.int64)
     reo_used = np.full(nq, R, dtype=np.int64)
+    dims = index.get("dims")
     for qi in range(nq):
-        q = np.asarray(Q[qi], dtype=F32)
+        q_init = np.asarray(Q[qi], dtype=F32)
+        q = q_init[np.asarray(dims)] if dims is not None else q_init
         s = coarse_scores(q, cp, metric)
         npq = int(nprobe[qi])
         if adaptive is not None:
@@ -349,7 +379,7 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
         ca, cid = top_r(a, ids, R)
         cand_a[qi, :len(ca)] = ca
         cand_id[qi, :len(cid)] = cid
-        out_ids[qi], out_d[qi] = rerank(q, X, cid[:reo_used[qi]], k, metric)
+        out_ids[qi], out_d[qi] = rerank(q_init, X, cid[:reo_used[qi]], k, metric)
     res = dict(ids=out_ids, dist=out_d, cand_a=cand_a, cand_id=cand_id)
     if adaptive is not None:
         res["nprobe_used"] = np_used

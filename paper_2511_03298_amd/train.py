@@ -51,6 +51,29 @@ def _host_kmeans(X, k, iters, rng):
     return C.astype(np.float32)
 
 
+def component_filter(X: np.ndarray, threshold: float, chunk: int = 1 << 18) -> np.ndarray:
+    """Statistical component filtration (section 4.3, Alg. 1 FilterComponents):
+    per dimension the mean and (population) standard deviation over all rows,
+    then the share of components equal to 0 or within one standard deviation
+    of the mean; dimensions whose share exceeds `threshold` are dropped.
+    Host FP64 in row chunks (a build step, like the k-means means). Returns
+    the kept dimensions, ascending."""
+    n, d = X.shape
+    s1 = np.zeros(d, dtype=np.float64)
+    for r in range(0, n, chunk):
+        s1 += X[r:r + chunk].astype(np.float64).sum(axis=0)
+    mu = s1 / n
+    s2 = np.zeros(d, dtype=np.float64)
+    for r in range(0, n, chunk):
+        s2 += ((X[r:r + chunk].astype(np.float64) - mu) ** 2).sum(axis=0)
+    sd = np.sqrt(s2 / n)
+    quiet = np.zeros(d, dtype=np.int64)
+    for r in range(0, n, chunk):
+        x = X[r:r + chunk].astype(np.float64)
+        quiet += ((x == 0.0) | (np.abs(x - mu) <= sd)).sum(axis=0)
+    return np.nonzero(quiet / n <= threshold)[0].astype(np.int64)
+
+
 def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
                     iters: int = 10, pq_iters: int = 12, train_per_list: int = 64,
                     pq_train: int = 65536, coarse: str = "bf16", widen: int = 4,

@@ -7,6 +7,7 @@ which the 8-bit table is exact, error bounds, plain-Python sorts, and a
 hand-worked example.
 """
 
+import dataclasses
 import json
 import math
 import os
@@ -405,3 +406,58 @@ def test_adaptive_search_is_static_search_at_chosen_parameters(name):
     full = oracle.search(index, X, Q, npmax, cfg.k, 60)
     assert (hi["nprobe_used"] == 12).all() and (hi["reorder_used"] == 60).all()
     assert np.array_equal(hi["ids"], full["ids"])
+
+
+# ---------------------------------------------------------------------------
+# Component filtration (section 4.3).
+# ---------------------------------------------------------------------------
+
+def test_component_filter_hand_example():
+    X = np.array([[0, 1, 5, 2], [0, 2, 5, 0], [0, 3, 5, 4], [1, 4, 5, 6]], np.float32)
+    # col 0: mu 0.25, sigma 0.433, three zeros, |1-mu| > sigma -> 3/4
+    # col 1: mu 2.5, sigma 1.118, 2 and 3 within -> 2/4
+    # col 2: constant, sigma 0 -> every component within -> 4/4
+    # col 3: mu 3, sigma 2.236, one zero, 2 and 4 within, 6 outside -> 3/4
+    keep, share = oracle.component_filter(X, 0.75)
+    assert np.allclose(share, [0.75, 0.5, 1.0, 0.75])
+    assert keep.tolist() == [0, 1, 3]
+    assert oracle.component_filter(X, 0.7)[0].tolist() == [1]
+
+
+def test_component_filter_distributions_and_product_agree():
+    from paper_2511_03298_amd.train import component_filter as product_filter
+    rng = make_rng(7)
+    n = 200_000
+    X = np.stack([rng.standard_normal(n),                      # Gaussian: ~68.3 % within 1 sigma
+                  rng.uniform(-1, 1, n),                       # uniform: 1/sqrt(3) ~ 57.7 %
+                  np.full(n, 3.0),                             # constant: 100 %
+                  np.where(rng.random(n) < 0.96, 0.0, 5.0),    # 96 % zeros
+                  ], axis=1).astype(np.float32)
+    keep, share = oracle.component_filter(X, 0.9)
+    assert abs(share[0] - 0.6827) < 0.005 and abs(share[1] - 1 / np.sqrt(3)) < 0.005
+    assert share[2] == 1.0 and share[3] >= 0.95
+    assert keep.tolist() == [0, 1]
+    assert product_filter(X, 0.9).tolist() == keep.tolist()
+    from workloads import make_workload, scaled
+    cfg = scaled("c6", 8000, 4, L=16, ncomp=16)
+    Xw, _, _ = make_workload(cfg)
+    kw = oracle.component_filter(Xw, 0.9)[0]
+    assert kw.tolist() == list(range(cfg.d - cfg.background))
+    assert product_filter(Xw, 0.9).tolist() == kw.tolist()
+
+
+def test_filtered_search_all_lists_equals_brute_force_on_full_rows():
+    # Dropped dimensions that are exactly 0 carry no distance: with every
+    # list probed and a full re-rank against the full rows, the filtered
+    # search is exact k-NN on the full data.
+    from workloads import train_index
+    cfg, X, Q, _, _ = cached_workload("c1", 2500, 8, L=12, ncomp=10)
+    Xz = np.concatenate([X, np.zeros((len(X), 8), np.float32)], axis=1)
+    Qz = np.concatenate([Q, np.zeros((len(Q), 8), np.float32)], axis=1)
+    keep, _ = oracle.component_filter(Xz, 0.9)
+    assert keep.tolist() == list(range(X.shape[1]))
+    idx = train_index(Xz, dataclasses.replace(cfg, d=Xz.shape[1], m=cfg.m * Xz.shape[1] // cfg.d),
+                      dims=keep)
+    res = oracle.search(idx, Xz, Qz, cfg.L, cfg.k, len(Xz))
+    bf_ids, bf_d = oracle.brute_force_knn(Xz, Qz, cfg.k, cfg.metric)
+    assert np.array_equal(res["ids"], bf_ids)

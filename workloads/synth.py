@@ -46,6 +46,7 @@ class WorkloadConfig:
     base_dtype: str = "f32"   # "f32" or "bf16" (rows stored as bfloat16)
     sigma: float = 0.1
     zipf: float = 0.0     # >0: component weights proportional to rank^-zipf
+    background: int = 0   # last dims that are almost always 0 (image-background-like)
 
     @property
     def dsub(self) -> int:
@@ -69,6 +70,11 @@ CONFIGS = {
     "c5": WorkloadConfig("c5", 5, 10_000_000, 768, "ip", "aniso", 8192, 4096,
                          8192, 192, (4, 256), 10, 256, base_dtype="bf16",
                          sigma=0.5),
+    # Redundant dimensions (component filtration, section 4.3): the c2-like
+    # mixture in 128 dims plus 128 background dims that are 0 in ~96 % of
+    # rows (FASHION-MNIST-like uniform backgrounds).
+    "c6": WorkloadConfig("c6", 6, 1_000_000, 256, "l2", "int255", 1000, 10_000,
+                         1024, 128, (32, 32), 10, 200, sigma=16.0, background=128),
 }
 
 
@@ -107,15 +113,16 @@ def _weights(cfg: WorkloadConfig, rng: np.random.Generator) -> np.ndarray:
 
 def _means(cfg: WorkloadConfig):
     rng = rng_for(cfg, STREAM_MEANS)
+    d = cfg.d - cfg.background
     if cfg.dist == "gauss":
-        mu = rng.uniform(-1.0, 1.0, size=(cfg.ncomp, cfg.d))
+        mu = rng.uniform(-1.0, 1.0, size=(cfg.ncomp, d))
     elif cfg.dist == "int255":
-        mu = rng.uniform(0.0, 128.0, size=(cfg.ncomp, cfg.d))
+        mu = rng.uniform(0.0, 128.0, size=(cfg.ncomp, d))
     elif cfg.dist == "sphere":
-        mu = _normalize(rng.standard_normal((cfg.ncomp, cfg.d))).astype(np.float64)
+        mu = _normalize(rng.standard_normal((cfg.ncomp, d))).astype(np.float64)
     elif cfg.dist == "aniso":
-        lam = (1.0 + np.arange(cfg.d)) ** -0.5
-        mu = lam[None, :] * rng.standard_normal((cfg.ncomp, cfg.d))
+        lam = (1.0 + np.arange(d)) ** -0.5
+        mu = lam[None, :] * rng.standard_normal((cfg.ncomp, d))
     else:
         raise ValueError(cfg.dist)
     w = _weights(cfg, rng)
@@ -124,26 +131,41 @@ def _means(cfg: WorkloadConfig):
 
 def _rotation(cfg: WorkloadConfig) -> np.ndarray:
     rng = rng_for(cfg, STREAM_ROT)
-    g = rng.standard_normal((cfg.d, cfg.d))
+    d = cfg.d - cfg.background
+    g = rng.standard_normal((d, d))
     qm, r = np.linalg.qr(g)
     return qm * np.sign(np.diag(r))[None, :]
 
 
 def _draw(cfg: WorkloadConfig, mu, w, rot, count: int,
           rng: np.random.Generator) -> np.ndarray:
+    x = _draw_informative(cfg, mu, w, rot, count, rng)
+    if cfg.background:
+        # 0 with probability 0.96, else a small value of the data's kind.
+        on = rng.random((count, cfg.background)) < 0.04
+        val = rng.integers(1, 33, size=(count, cfg.background)).astype(np.float32)
+        if cfg.dist != "int255":
+            val *= np.float32(cfg.sigma / 32.0)
+        x = np.concatenate([x, np.where(on, val, np.float32(0.0))], axis=1)
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+def _draw_informative(cfg: WorkloadConfig, mu, w, rot, count: int,
+                      rng: np.random.Generator) -> np.ndarray:
+    d = cfg.d - cfg.background
     comp = rng.choice(cfg.ncomp, size=count, p=w)
-    noise = rng.standard_normal((count, cfg.d),
+    noise = rng.standard_normal((count, d),
                                 dtype=np.float32 if cfg.dist == "aniso" else np.float64)
     if cfg.dist == "gauss":
         x = mu[comp] + cfg.sigma * noise
     elif cfg.dist == "int255":
         x = np.clip(np.rint(mu[comp] + cfg.sigma * noise), 0.0, 255.0)
     elif cfg.dist == "sphere":
-        x = mu[comp] + cfg.sigma * noise / np.sqrt(cfg.d)
+        x = mu[comp] + cfg.sigma * noise / np.sqrt(d)
         x = _normalize(x)
     elif cfg.dist == "aniso":
         # FP32 arithmetic (the rows are rounded to BF16 afterwards anyway).
-        lam = ((1.0 + np.arange(cfg.d)) ** -0.5).astype(np.float32)
+        lam = ((1.0 + np.arange(d)) ** -0.5).astype(np.float32)
         x = (mu[comp].astype(np.float32) + np.float32(cfg.sigma) * lam[None, :]
              * noise.astype(np.float32)) @ rot.T.astype(np.float32)
         x = x / np.sqrt(np.einsum("ij,ij->i", x, x))[:, None]

@@ -15,6 +15,8 @@ is shared data, and do not affect parity between the GPU path and the oracle.
 
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 
 from .synth import STREAM_KMEANS, STREAM_PQ, WorkloadConfig, rng_for
@@ -66,7 +68,7 @@ def _kmeans(X: np.ndarray, k: int, iters: int, rng, ip: bool) -> np.ndarray:
 
 def train_index(X: np.ndarray, cfg: WorkloadConfig, iters: int = 10,
                 pq_iters: int = 12, train_per_list: int = 64,
-                pq_train: int = 65536):
+                pq_train: int = 65536, dims=None):
     """Build an IVF-PQ index over X (float32 [n, d]).
 
     Returns a dict of numpy arrays:
@@ -74,7 +76,19 @@ def train_index(X: np.ndarray, cfg: WorkloadConfig, iters: int = 10,
       cp [L,d] f32 probe centroids (= cm for L2, cm/|cm| for IP),
       codebooks [m,16,d'] f32, codes [n,m] u8 (0..15),
       list_offsets [L+1] i64, list_ids [n] i32 (ascending within a list).
+    dims: kept dimensions of a component filtration (computed by the caller);
+    the index is then built over X[:, dims] with m scaled to keep d', and
+    the dict carries "dims" and "d_base" (the full row width).
     """
+    if dims is not None:
+        dims = np.asarray(dims, dtype=np.int64)
+        d_base = X.shape[1]
+        m = cfg.m * len(dims) // d_base
+        sub = dataclasses.replace(cfg, d=len(dims), m=m, background=0)
+        index = train_index(np.ascontiguousarray(X[:, dims]), sub, iters, pq_iters,
+                            train_per_list, pq_train)
+        index.update(dims=dims, d_base=d_base)
+        return index
     n, d = X.shape
     L, m = cfg.L, cfg.m
     assert d % m == 0
