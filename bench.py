@@ -15,6 +15,7 @@ from the same mixture, 1024 lists, PQ with 64 subspaces x 16 codewords
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -214,6 +215,11 @@ def main():
                     help="skip the autotuned schedule (paper_2511_03298_amd.tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-queries", type=int, default=1000)
+    ap.add_argument("--filter", type=float, default=None, metavar="THRESHOLD",
+                    help="component filtration (section 4.3): drop dimensions whose share of "
+                         "components that are 0 or within one standard deviation of the mean "
+                         "exceeds THRESHOLD; the index is built over the kept dims (m scaled to "
+                         "keep d'), the re-rank uses the full rows")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure static nprobe values and adaptive (Eq. 2) settings with "
                          "the batched BF16 form; adds a 'sweep' list to the JSON line")
@@ -234,13 +240,20 @@ def main():
     log(f"generated in {time.time() - t0:.1f}s; training IVF-PQ (L={cfg.L}, m={cfg.m})")
     t0 = time.time()
     gpu_trained = cfg.n > 2_000_000
+    dims = None
+    if args.filter is not None:
+        from paper_2511_03298_amd.train import component_filter
+        dims = component_filter(X, args.filter)
+        log(f"component filtration at {args.filter}: {len(dims)} of {cfg.d} dims kept")
     if gpu_trained:
         # 10M-point shapes: assignment and encoding on the GPU (ivf_assign /
         # ivf_encode); the host trainer would take many minutes.
         from paper_2511_03298_amd.train import train_index_gpu
-        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index, log=log)
+        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index, log=log, dims=dims)
     else:
-        index = train_index(X, cfg)
+        index = train_index(X, cfg, dims=dims)
+    if dims is not None:
+        cfg = dataclasses.replace(cfg, m=int(index["codebooks"].shape[0]))
     lens = np.diff(index["list_offsets"])
     log(f"trained in {time.time() - t0:.1f}s ({'GPU' if gpu_trained else 'host'}); "
         f"list length mean {lens.mean():.0f} max {lens.max()}")
@@ -356,6 +369,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT.get(args.config, args.config), "n": cfg.n,
                    "d": cfg.d, "nq": cfg.nq, "L": cfg.L, "m": cfg.m, "nprobe": list(cfg.nprobe),
                    "k": cfg.k, "rerank": cfg.R, "form": best["form"], "coarse": best["coarse"],
+                   "filter": args.filter, "dims_kept": None if dims is None else int(len(dims)),
                    "schedule": best["opts"]},
         "recall_at_10": round(best["recall_at_10"], 4),
         "forms": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()

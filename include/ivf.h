@@ -79,6 +79,16 @@ typedef struct {
   const int32_t* list_ids;        /* [list_offsets[L]] point ids (rows of base,
                                      each at most once) grouped by list, ascending
                                      within a list. Consumed.                     */
+  int32_t d_base;                 /* row width of `base` and of the queries the
+                                     searches take: d, or 0 (= d) when dims is
+                                     NULL; >= d otherwise                          */
+  const int32_t* dims;            /* HOST [d] or NULL. Component filtration
+                                     (section 4.3, Alg. 1/2): the index (centroids,
+                                     codebooks, codes) lives in the base columns
+                                     dims[0..d), strictly ascending, < d_base.
+                                     Steps 1-4 use those components of each query,
+                                     the re-rank the full d_base-wide query and
+                                     rows. Copied.                                 */
 } ivf_index_desc;
 
 /* Coarse-scoring precision (step 1). IVF_COARSE_EXACT scores every list with
@@ -244,10 +254,11 @@ ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries,
  * codes: uint32 [blocks][words][64], word w of a point holds the 4-bit codes
  * of subspaces 8w..8w+7 in bits 4s..4s+3 (padding subspaces are 0);
  * slot_ids: int32 [blocks][64] point id per slot, -1 for padding;
- * block_offsets: int32 [L+1] first block of each list. */
+ * block_offsets: int32 [L+1] first block of each list; dims: int32 [d] kept
+ * base columns of a filtered index (an empty section without filtration). */
 typedef struct {
   size_t codes, slot_ids, block_offsets, list_len, centroids, probe_centroids,
-      codebooks, probe_norms, probe_f32, probe_bf16, probe_fp8, probe_fp8_scale, total;
+      codebooks, probe_norms, probe_f32, probe_bf16, probe_fp8, probe_fp8_scale, dims, total;
   int32_t words_per_point, m_padded, blocks, L_padded, d_padded, reserved;
 } ivf_table_layout;
 

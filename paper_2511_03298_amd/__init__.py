@@ -44,7 +44,8 @@ class IndexDesc(ctypes.Structure):
                 ("base_dtype", ctypes.c_int32), ("base", ctypes.c_void_p),
                 ("centroids", ctypes.c_void_p), ("probe_centroids", ctypes.c_void_p),
                 ("codebooks", ctypes.c_void_p), ("codes", ctypes.c_void_p),
-                ("list_offsets", ctypes.c_void_p), ("list_ids", ctypes.c_void_p)]
+                ("list_offsets", ctypes.c_void_p), ("list_ids", ctypes.c_void_p),
+                ("d_base", ctypes.c_int32), ("dims", ctypes.c_void_p)]
 
 
 class SearchOpts(ctypes.Structure):
@@ -61,7 +62,7 @@ class TableLayout(ctypes.Structure):
     _fields_ = [(name, ctypes.c_size_t) for name in (
         "codes", "slot_ids", "block_offsets", "list_len", "centroids", "probe_centroids",
         "codebooks", "probe_norms", "probe_f32", "probe_bf16", "probe_fp8", "probe_fp8_scale",
-        "total")] + \
+        "dims", "total")] + \
         [(name, ctypes.c_int32) for name in (
             "words_per_point", "m_padded", "blocks", "L_padded", "d_padded", "reserved")]
 
@@ -173,7 +174,7 @@ class GpuIndex:
 
     def __init__(self, base, centroids, codebooks, codes, list_offsets, list_ids,
                  metric: str, probe_centroids=None, base_dtype: str = "f32",
-                 device: str = "cuda"):
+                 device: str = "cuda", dims=None):
         import numpy as np
         import torch
         L = lib()
@@ -192,16 +193,21 @@ class GpuIndex:
         codes_t = dev(codes, torch.uint8)
         ids_t = dev(list_ids, torch.int32)
         offs = np.ascontiguousarray(np.asarray(list_offsets, dtype=np.int64))
-        n, d = self.base.shape
-        Lc = self.centroids.shape[0]
+        n, d_base = self.base.shape
+        Lc, d = self.centroids.shape
         m = self.codebooks.shape[0]
+        # Component filtration: the index lives in the kept base columns.
+        self.dims = None if dims is None else np.ascontiguousarray(np.asarray(dims, np.int32))
         self.n, self.d, self.L, self.m, self.metric = n, d, Lc, m, metric
+        self.d_base = d_base
         desc = IndexDesc(n=n, d=d, L=Lc, m=m, metric=METRIC[metric],
                          base_dtype=DTYPE[base_dtype], base=_ptr(self.base),
                          centroids=_ptr(self.centroids),
                          probe_centroids=_ptr(self.probe_centroids),
                          codebooks=_ptr(self.codebooks), codes=_ptr(codes_t),
-                         list_offsets=offs.ctypes.data, list_ids=_ptr(ids_t))
+                         list_offsets=offs.ctypes.data, list_ids=_ptr(ids_t),
+                         d_base=d_base if self.dims is not None else 0,
+                         dims=None if self.dims is None else self.dims.ctypes.data)
         nbytes = L.ivf_tables_bytes(ctypes.byref(desc))
         if nbytes == 0:
             raise IvfError(IVF_ERR_INVALID_ARG, last_error())
@@ -217,7 +223,7 @@ class GpuIndex:
     def from_index(cls, index: dict, X, base_dtype: str = "f32", device: str = "cuda"):
         return cls(X, index["cm"], index["codebooks"], index["codes"], index["list_offsets"],
                    index["list_ids"], index["metric"], probe_centroids=index["cp"],
-                   base_dtype=base_dtype, device=device)
+                   base_dtype=base_dtype, device=device, dims=index.get("dims"))
 
     def __del__(self):
         h = getattr(self, "_h", None)

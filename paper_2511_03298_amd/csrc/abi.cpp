@@ -90,6 +90,15 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
     if (len > mx) mx = len;
   }
   if (off[d->L] > d->n) return "list_offsets[L] must be <= n";
+  if (d->dims) {
+    if (d->d_base < d->d) return "d_base must be >= d with dims";
+    for (int j = 0; j < d->d; ++j) {
+      if (d->dims[j] < 0 || d->dims[j] >= d->d_base) return "dims entries must be in [0, d_base)";
+      if (j > 0 && d->dims[j] <= d->dims[j - 1]) return "dims must be strictly ascending";
+    }
+  } else if (d->d_base != 0 && d->d_base != d->d) {
+    return "d_base must be 0 or d without dims";
+  }
   std::memset(lay, 0, sizeof(*lay));
   const int32_t words = (d->m + 7) / 8;
   lay->words_per_point = words;
@@ -116,6 +125,7 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
   lay->probe_bf16 = take((size_t)lay->L_padded * lay->d_padded * 2);
   lay->probe_fp8 = take((size_t)lay->L_padded * lay->d_padded);
   lay->probe_fp8_scale = take((size_t)lay->L_padded * 4);
+  lay->dims = take(d->dims ? (size_t)d->d * 4 : 0);
   // Build-time copy of the CSR offsets (int64), then the end.
   take((size_t)(d->L + 1) * 8);
   lay->total = o;
@@ -211,6 +221,7 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   w.probes = (int32_t*)take(nqs * max_nprobe * 4);
   w.nprobe_eff = (int32_t*)take(nqs * 4);
   w.reorder_eff = (int32_t*)take(nqs * 4);
+  if (t.dims) w.qf = (float*)take(nqs * t.d * 4);
   w.bias = (float*)take(nqs * max_nprobe * 4);
   w.cand = (uint64_t*)take(nqs * rerank * 8);
   if (o.coarse != IVF_COARSE_EXACT) {
@@ -309,6 +320,8 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
   t.L_pad = lay.L_padded;
   t.d_pad = lay.d_padded;
   t.max_list_len = max_len;
+  t.d_base = desc->dims ? desc->d_base : desc->d;
+  t.dims = desc->dims ? (const int32_t*)(base + lay.dims) : nullptr;
   t.base = desc->base;
   t.codes = (const uint32_t*)(base + lay.codes);
   t.slot_ids = (const int32_t*)(base + lay.slot_ids);
@@ -334,6 +347,8 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
   const size_t cb_bytes = (size_t)desc->m * KSUB * t.dsub * 4;
   const size_t cb_pad_bytes = (size_t)t.m_pad * KSUB * t.dsub * 4;
   IVF_HIP(hipMemcpyAsync((void*)t.block_off, boff.data(), boff.size() * 4, hipMemcpyHostToDevice, s));
+  if (t.dims)
+    IVF_HIP(hipMemcpyAsync((void*)t.dims, desc->dims, (size_t)desc->d * 4, hipMemcpyHostToDevice, s));
   IVF_HIP(hipMemcpyAsync((void*)t.list_len, llen.data(), llen.size() * 4, hipMemcpyHostToDevice, s));
   IVF_HIP(hipMemcpyAsync(list_off_dev, desc->list_offsets, (size_t)(desc->L + 1) * 8,
                          hipMemcpyHostToDevice, s));
@@ -485,7 +500,7 @@ ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, in
   return IVF_OK;
 }
 
-ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, int32_t nq,
+ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, const float* Qr, int32_t nq,
                                int32_t max_nprobe, int32_t k, int32_t rerank,
                                const ivf_search_opts& o, const Workspace& w, int64_t* out_ids,
                                float* out_dist, hipStream_t s) {
@@ -516,9 +531,20 @@ ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, int32_t nq,
   }
   IVF_HIP(prof_mark(idx, s, IVF_STAGE_RERANK));
   if (out_ids)
-    IVF_HIP(launch_rerank(t, Q, nq, k, rerank, o.adaptive ? w.reorder_eff : nullptr, w, out_ids,
+    IVF_HIP(launch_rerank(t, Qr, nq, k, rerank, o.adaptive ? w.reorder_eff : nullptr, w, out_ids,
                           out_dist, s));
   IVF_HIP(prof_mark(idx, s, IVF_NSTAGES));
+  return IVF_OK;
+}
+
+// The queries of the search steps: the kept components of a filtered index
+// (gathered into the workspace), else the caller's queries.
+ivf_status search_queries(const ivf_index* idx, const float* queries, int32_t nq,
+                          const Workspace& w, hipStream_t s, const float** out) {
+  *out = queries;
+  if (!idx->t.dims) return IVF_OK;
+  IVF_HIP(launch_gather_queries(idx->t, queries, nq, w.qf, s));
+  *out = w.qf;
   return IVF_OK;
 }
 
@@ -586,10 +612,13 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
     e.key = key;
     IVF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     ivf_status cst = IVF_OK;
+    const float* Qs = queries;
     if (launch_fill_u32((uint32_t*)w.err, 0u, 4, s) != hipSuccess) cst = IVF_ERR_DEVICE;
-    if (cst == IVF_OK) cst = run_coarse(idx, queries, nq, nprobe, max_nprobe, k, rerank, o, w, s);
+    if (cst == IVF_OK) cst = search_queries(idx, queries, nq, w, s, &Qs);
+    if (cst == IVF_OK) cst = run_coarse(idx, Qs, nq, nprobe, max_nprobe, k, rerank, o, w, s);
     if (cst == IVF_OK)
-      cst = run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);
+      cst = run_scan_and_rerank(idx, Qs, queries, nq, max_nprobe, k, rerank, o, w, out_ids,
+                                out_dist, s);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(s, &g);
     if (cst != IVF_OK) {
@@ -614,9 +643,13 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
   }
   IVF_HIP(prof_begin(idx));
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
-  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, k, rerank, o, w, s);
+  const float* Qs = queries;
+  st = search_queries(idx, queries, nq, w, s, &Qs);
   if (st != IVF_OK) return st;
-  return run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);
+  st = run_coarse(idx, Qs, nq, nprobe, max_nprobe, k, rerank, o, w, s);
+  if (st != IVF_OK) return st;
+  return run_scan_and_rerank(idx, Qs, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist,
+                             s);
 }
 
 ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries, int32_t nq,
@@ -639,7 +672,11 @@ ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries, in
   IVF_HIP(prof_begin(idx));
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
   IVF_HIP(launch_copy_probes(probes, nprobe, nq, max_nprobe, idx->t.L, w, s));
-  return run_scan_and_rerank(idx, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist, s);
+  const float* Qs = queries;
+  st = search_queries(idx, queries, nq, w, s, &Qs);
+  if (st != IVF_OK) return st;
+  return run_scan_and_rerank(idx, Qs, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist,
+                             s);
 }
 
 ivf_status ivf_debug_probes(const ivf_index* idx, const float* queries, int32_t nq,
@@ -654,7 +691,10 @@ ivf_status ivf_debug_probes(const ivf_index* idx, const float* queries, int32_t 
   if (!queries || !nprobe || !out_probes) return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
-  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, 1, 1, o, w, s);
+  const float* Qs = queries;
+  st = search_queries(idx, queries, nq, w, s, &Qs);
+  if (st != IVF_OK) return st;
+  st = run_coarse(idx, Qs, nq, nprobe, max_nprobe, 1, 1, o, w, s);
   if (st != IVF_OK) return st;
   IVF_HIP(hipMemcpyAsync(out_probes, w.probes, (size_t)nq * max_nprobe * 4,
                          hipMemcpyDeviceToDevice, s));
@@ -677,7 +717,10 @@ ivf_status ivf_debug_adaptive(const ivf_index* idx, const float* queries, int32_
     return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
-  st = run_coarse(idx, queries, nq, nprobe, max_nprobe, k, rerank, o, w, s);
+  const float* Qs = queries;
+  st = search_queries(idx, queries, nq, w, s, &Qs);
+  if (st != IVF_OK) return st;
+  st = run_coarse(idx, Qs, nq, nprobe, max_nprobe, k, rerank, o, w, s);
   if (st != IVF_OK) return st;
   IVF_HIP(hipMemcpyAsync(out_nprobe, w.nprobe_eff, (size_t)nq * 4, hipMemcpyDeviceToDevice, s));
   IVF_HIP(hipMemcpyAsync(out_reorder, w.reorder_eff, (size_t)nq * 4, hipMemcpyDeviceToDevice, s));
@@ -695,7 +738,10 @@ ivf_status ivf_debug_coarse_scores(const ivf_index* idx, const float* queries, i
   if (nq == 0) return IVF_OK;
   if (!queries || !out_scores) return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   hipStream_t s = (hipStream_t)stream;
-  IVF_HIP(launch_coarse_mfma(idx->t, queries, nq, o.coarse, w, s));
+  const float* Qs = queries;
+  st = search_queries(idx, queries, nq, w, s, &Qs);
+  if (st != IVF_OK) return st;
+  IVF_HIP(launch_coarse_mfma(idx->t, Qs, nq, o.coarse, w, s));
   IVF_HIP(hipMemcpyAsync(out_scores, w.scores, (size_t)nq * idx->t.L * 4, hipMemcpyDeviceToDevice, s));
   return IVF_OK;
 }
@@ -734,7 +780,10 @@ ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries, int3
   hipStream_t s = (hipStream_t)stream;
   IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
   IVF_HIP(launch_copy_probes(probes, nprobe, nq, max_nprobe, idx->t.L, w, s));
-  st = run_scan_and_rerank(idx, queries, nq, max_nprobe, 1, rerank, o, w, nullptr, nullptr, s);
+  const float* Qs = queries;
+  st = search_queries(idx, queries, nq, w, s, &Qs);
+  if (st != IVF_OK) return st;
+  st = run_scan_and_rerank(idx, Qs, queries, nq, max_nprobe, 1, rerank, o, w, nullptr, nullptr, s);
   if (st != IVF_OK) return st;
   IVF_HIP(launch_sort_rows(w.cand, nq, rerank, s));
   IVF_HIP(hipMemcpyAsync(out_keys, w.cand, (size_t)nq * rerank * 8, hipMemcpyDeviceToDevice, s));
@@ -765,6 +814,7 @@ AssignPlan plan_assign(int32_t L, int32_t d, int32_t metric, int32_t chunk, int3
   };
   Tables& t = a.t;
   t.d = d;
+  t.d_base = d;
   t.L = L;
   t.m = 1;
   t.dsub = d;

@@ -321,4 +321,25 @@ hipError_t launch_bias(const Tables& t, const float* Q, int32_t nq, int32_t max_
   return hipGetLastError();
 }
 
+// Component filtration (section 4.3): the kept components of each query,
+// qf[q][j] = Q[q][dims[j]], for the search steps.
+__global__ void gather_queries_kernel(const float* __restrict__ Q, int64_t total, int32_t d,
+                                      int32_t d_base, const int32_t* __restrict__ dims,
+                                      float* __restrict__ qf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t q = i / d;
+  const int j = (int)(i % d);
+  qf[i] = Q[q * d_base + dims[j]];
+}
+
+hipError_t launch_gather_queries(const Tables& t, const float* Q, int32_t nq, float* qf,
+                                 hipStream_t s) {
+  const int64_t total = (int64_t)nq * t.d;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_queries_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     Q, total, t.d, t.d_base, t.dims, qf);
+  return hipGetLastError();
+}
+
 }  // namespace ivf

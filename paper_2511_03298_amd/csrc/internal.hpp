@@ -29,6 +29,8 @@ struct Tables {
   int32_t blocks;     // total 64-point blocks
   int32_t L_pad, d_pad;
   int32_t max_list_len;
+  int32_t d_base;               // row width of base / queries (>= d)
+  const int32_t* dims;          // [d] kept base columns, or nullptr
   const void* base;
   const uint32_t* codes;        // [blocks][words][64]
   const int32_t* slot_ids;      // [blocks][64]
@@ -65,6 +67,7 @@ struct Workspace {
   int32_t* probes;      // [nq][max_nprobe]
   int32_t* nprobe_eff;  // [nq]; -1 marks an invalid request
   int32_t* reorder_eff; // [nq] re-rank size (adaptive form; else rerank)
+  float* qf;            // [nq][d] kept query components (filtered index only)
   float* bias;          // [nq][max_nprobe] per-(q,list) constant (IP), else unused
   uint64_t* cand;       // [nq][rerank]
   int32_t* err;         // [4] device error word
@@ -121,6 +124,8 @@ hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
 hipError_t launch_copy_probes(const int32_t* probes, const int32_t* nprobe, int32_t nq,
                               int32_t max_nprobe, int32_t L, const Workspace& w,
                               hipStream_t s);
+hipError_t launch_gather_queries(const Tables& t, const float* Q, int32_t nq, float* qf,
+                                 hipStream_t s);
 hipError_t launch_bias(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
                        const Workspace& w, hipStream_t s);
 hipError_t launch_scan_plain(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,

@@ -11,9 +11,9 @@ namespace ivf {
 __device__ __forceinline__ float load_base(const Tables& t, int64_t row, int c) {
   if (t.base_dtype == IVF_DTYPE_BF16) {
     const uint16_t* b = reinterpret_cast<const uint16_t*>(t.base);
-    return __uint_as_float((uint32_t)b[row * t.d + c] << 16);
+    return __uint_as_float((uint32_t)b[row * t.d_base + c] << 16);
   }
-  return reinterpret_cast<const float*>(t.base)[row * t.d + c];
+  return reinterpret_cast<const float*>(t.base)[row * t.d_base + c];
 }
 
 // Sum over one 16-byte vector of the row: 4 FP32 values, or 8 BF16 values
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
     }
     return;
   }
-  for (int i = tid; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
+  for (int i = tid; i < t.d_base; i += blockDim.x) qv[i] = Q[(size_t)q * t.d_base + i];
   // The pool into LDS; with a per-query re-rank size, its `reorder` smallest
   // keys only (the set a pool of that size would hold). Keys are unique apart
   // from the empty-slot value, which sorts last.
@@ -94,9 +94,9 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   constexpr int GROUPS = IVF_BLOCK / G;
   const int g = tid / G, gl = tid % G;
   const int per_vec = bf16 ? 8 : 4;                       // elements per 16 bytes
-  const size_t row_bytes = (size_t)t.d * (bf16 ? 2 : 4);
+  const size_t row_bytes = (size_t)t.d_base * (bf16 ? 2 : 4);
   const bool vec = row_bytes % 16 == 0;
-  const int nvec = t.d / per_vec;
+  const int nvec = t.d_base / per_vec;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(t.base);
   for (int c0 = 0; c0 < nc; c0 += GROUPS * U) {
     uint64_t key[U];
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
           if (key[u] != KEY_NONE) acc[u] = acc[u] + vec_term(qv, x[u], v0 * per_vec, ip, bf16);
       }
     } else {
-      for (int i = gl; i < t.d; i += G) {
+      for (int i = gl; i < t.d_base; i += G) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (key[u] == KEY_NONE) continue;
@@ -189,7 +189,7 @@ hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k,
                          const int32_t* reorder, const Workspace& w, int64_t* out_ids,
                          float* out_dist, hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  size_t lds = (size_t)pow2_ceil((uint32_t)rerank) * 8 + (size_t)t.d * 4;
+  size_t lds = (size_t)pow2_ceil((uint32_t)rerank) * 8 + (size_t)t.d_base * 4;
   hipLaunchKernelGGL(rerank_kernel<4>, dim3(nq), dim3(256), lds, s, t, Q, k, rerank, w.nprobe_eff,
                      w.cand, reorder, out_ids, out_dist);
   return hipGetLastError();

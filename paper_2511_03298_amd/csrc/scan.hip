@@ -346,7 +346,9 @@ __global__ void __launch_bounds__(256) debug_lut_kernel(Tables t, const float* _
   if (p >= nprobe[q] || probes[qp] < 0 || probes[qp] >= t.L) return;
   float* Tf = reinterpret_cast<float*>(dyn);
   float* qv = Tf + t.m_pad * KSUB;
-  for (int i = threadIdx.x; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
+  // Filtered index: the kept components of the d_base-wide query.
+  for (int i = threadIdx.x; i < t.d; i += blockDim.x)
+    qv[i] = Q[(size_t)q * t.d_base + (t.dims ? t.dims[i] : i)];
   __syncthreads();
   const int l = probes[qp];
   lut_float(t, qv, l, Tf);

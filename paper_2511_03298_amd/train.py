@@ -77,11 +77,20 @@ def component_filter(X: np.ndarray, threshold: float, chunk: int = 1 << 18) -> n
 def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
                     iters: int = 10, pq_iters: int = 12, train_per_list: int = 64,
                     pq_train: int = 65536, coarse: str = "bf16", widen: int = 4,
-                    device: str = "cuda", log=None):
+                    device: str = "cuda", log=None, dims=None):
     """Train an IVF-PQ index over X (float32 [n, d], host). Returns the same
     dict layout as the host trainer; `codes` and `list_ids` stay on the GPU
-    (torch tensors), everything else is numpy."""
+    (torch tensors), everything else is numpy. dims: kept columns of a
+    component filtration; the index is built over X[:, dims] with m scaled
+    to keep d', and carries "dims" and "d_base"."""
     import torch
+    if dims is not None:
+        dims = np.asarray(dims, dtype=np.int64)
+        mf = m * len(dims) // X.shape[1]
+        index = train_index_gpu(np.ascontiguousarray(X[:, dims]), L, mf, metric, seed, iters,
+                                pq_iters, train_per_list, pq_train, coarse, widen, device, log)
+        index.update(dims=dims, d_base=X.shape[1])
+        return index
 
     n, d = X.shape
     assert d % m == 0

@@ -72,6 +72,27 @@ def test_invalid_descriptors_rejected(field, value):
     assert not h.value
 
 
+def test_filtration_dims_validated():
+    ivf, lib = _lib()
+    desc, offs = _desc(ivf, d=32, m=16)
+    good = np.arange(0, 64, 2, dtype=np.int32)  # 32 kept columns of 64
+    desc.d_base, desc.dims = 64, good.ctypes.data
+    with_dims = lib.ivf_tables_bytes(ctypes.byref(desc))
+    assert with_dims > 0
+    desc.dims, desc.d_base = None, 0
+    assert lib.ivf_tables_bytes(ctypes.byref(desc)) == with_dims - 256  # the dims section
+    bad = [(64, np.arange(32, 0, -1, dtype=np.int32)),           # not ascending
+           (40, np.arange(0, 64, 2, dtype=np.int32)),           # column >= d_base
+           (16, np.arange(0, 32, dtype=np.int32)),              # d_base < d
+           ]
+    for d_base, dims in bad:
+        desc.d_base, desc.dims = d_base, dims.ctypes.data
+        assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
+        assert "d" in ivf.last_error()
+    desc.dims, desc.d_base = None, 40  # d_base without dims must be 0 or d
+    assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
+
+
 def test_bad_offsets_rejected():
     ivf, lib = _lib()
     offs = np.array([0, 10, 5, 1000] + [1000] * 5, dtype=np.int64)

@@ -498,6 +498,52 @@ def test_adaptive_limits_and_rejections():
 
 
 # ---------------------------------------------------------------------------
+# Component filtration (section 4.3): the index over the kept columns.
+# ---------------------------------------------------------------------------
+
+def _filtered_case():
+    if "c6s" not in _STATE:
+        ivf = _gpu()
+        from workloads import make_workload, scaled, train_index
+        cfg = scaled("c6", 20_000, 30, L=32, ncomp=32, nprobe=(6, 6))
+        X, Q, nprobe = make_workload(cfg)
+        keep, _ = oracle.component_filter(X, 0.9)
+        index = train_index(X, cfg, dims=keep)
+        print(f"[case c6s] n={cfg.n} d_base={cfg.d} kept={len(keep)} m={index['codebooks'].shape[0]}",
+              flush=True)
+        g = ivf.GpuIndex.from_index(index, X)
+        res = oracle_stages(index, X, Q, nprobe, cfg.k, cfg.R)
+        _STATE["c6s"] = (cfg, X, Q, nprobe, index, g, res)
+    return _STATE["c6s"]
+
+
+def test_filtered_index_parity():
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = _filtered_case()
+    assert g.d == len(index["dims"]) < g.d_base == X.shape[1]
+    # Steps 1-4 on the kept components: probes, tables and pools bit-exact.
+    P = g.debug_probes(Q, nprobe).cpu().numpy()
+    for qi, p in enumerate(res["probes"]):
+        assert np.array_equal(P[qi, :len(p)], p), qi
+    Pt = probes_tensor(res, nprobe)
+    lut, lo, delta, B = g.debug_luts(Q, Pt, nprobe)
+    qi, p = 3, 2
+    q8, lo_o, d_o, B_o = res["luts"][(qi, int(res["probes"][qi][p]))]
+    assert np.array_equal(lut[qi, p].cpu().numpy(), q8)
+    assert np.float32(delta[qi, p].item()) == d_o and np.float32(B[qi, p].item()) == B_o
+    for form in ("plain", "batched"):
+        keys = g.debug_candidates(Q, Pt, nprobe, cfg.R, opts=ivf.make_opts(form=form)).cpu().numpy()
+        a, ids = ivf.decode_keys(keys)
+        assert np.array_equal(ids, res["cand_id"]), form
+        assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32)), form
+    # The re-rank against the full rows and queries (Alg. 2).
+    for form, coarse in (("plain", "exact"), ("batched", "bf16")):
+        ids, dist = g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(form=form, coarse=coarse))
+        check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q, cfg.metric, exact_ids=True)
+    assert g.device_error() == 0
+
+
+# ---------------------------------------------------------------------------
 # Index construction on the GPU (Alg. 1): assignment and encoding.
 # ---------------------------------------------------------------------------
 
