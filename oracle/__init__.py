@@ -14,6 +14,9 @@ no value printed by the paper pins it: parity unpinned for the scheme itself.
 The adaptive nprobe/reorder stand-in (hardness, eq2) follows Eq. 2 with a
 closed-form p in place of the paper's trained model; Eq. 2 itself is pinned
 by hand-worked values and its limits, the choice of p is a reading.
+The spilled assignment (spill_assign, SOAR) and the per-point pool of a
+spilled index (top_r_unique) are pinned by a hand-worked case, the lam = 0
+limit, an independent projection-matrix form and brute force.
 """
 
 from .ivfpq import (  # noqa: F401
@@ -31,8 +34,10 @@ from .ivfpq import (  # noqa: F401
     scan_list,
     search,
     select_probes,
+    spill_assign,
     seq_sum,
     tree_sum,
     top_r,
+    top_r_unique,
     rerank,
 )

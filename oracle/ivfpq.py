@@ -35,6 +35,10 @@ Readings where the paper is silent (all also listed in the design notes):
     is replaced by a closed form of its "centroid distances" feature,
     p = e_1 / e_K (see hardness); Eq. 2 is read as
     min(v_max, v_min + floor(D * ReLU(p - p0) * (p + p1))).
+  * Spilled assignment (section 4.6.2 integrates SOAR): each point also
+    goes to one spill list chosen by SOAR's loss with weight lam; in the
+    search a point scanned in several probed lists enters the pool once, at
+    the smallest of its approximate distances.
 """
 
 from __future__ import annotations
@@ -204,6 +208,20 @@ def top_r(a: np.ndarray, ids: np.ndarray, R: int):
     return a[order], ids[order]
 
 
+def top_r_unique(a: np.ndarray, ids: np.ndarray, R: int):
+    """Pool over a spilled index, where one point may be scanned in several
+    probed lists (section 4.6.2): a point's approximate distance is the
+    smallest of its copies, and the pool is the min(R, #points) smallest
+    (distance, id) pairs over distinct points."""
+    best = {}
+    for v, i in zip(a.tolist(), ids.tolist()):
+        if i not in best or v < best[i]:
+            best[i] = v
+    pairs = sorted((v, i) for i, v in best.items())[:R]
+    return (np.array([v for v, _ in pairs], dtype=F32),
+            np.array([i for _, i in pairs], dtype=np.int64))
+
+
 # --------------------------------------------------------------------------
 # Stage 6: exact re-rank (Alg. 2, final step) -- float64.
 # --------------------------------------------------------------------------
@@ -327,6 +345,10 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
     array. Returns dict with ids [nq,k] int64, dist [nq,k] f64, cand_a
     [nq,R] f32 (+inf padded), cand_id [nq,R] int64 (-1 padded) and, when
     want_stages, probes (list of arrays) and luts {(qi, list): (q8, lo, delta, B)}.
+    index["copies"] (optional, default 1): a spilled index (section 4.6.2),
+    where a point lies in up to `copies` lists; codes are then per list entry
+    ([list_offsets[L], m], aligned with list_ids) and the pool keeps each
+    point once, at its best copy (top_r_unique).
     index["dims"] (optional): kept dimensions of component filtration; the
     index lives in that subspace, stages 1-5 use q[dims] and the re-rank the
     full query against the full rows X (Alg. 2).
@@ -350,6 +372,7 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
     np_used = np.zeros(nq, dtype=np.int64)
     reo_used = np.full(nq, R, dtype=np.int64)
     dims = index.get("dims")
+    spilled = int(index.get("copies", 1)) > 1
     for qi in range(nq):
         q_init = np.asarray(Q[qi], dtype=F32)
         q = q_init[np.asarray(dims)] if dims is not None else q_init
@@ -371,12 +394,13 @@ def search(index: dict, X: np.ndarray, Q: np.ndarray, nprobe, k: int, R: int,
             if want_stages:
                 luts[(qi, int(l))] = (q8, lo, delta, B)
             ids = np.asarray(lid[off[l]:off[l + 1]], dtype=np.int64)
-            _, a = scan_list(q8, delta, B, codes[ids])
+            rows = codes[off[l]:off[l + 1]] if spilled else codes[ids]
+            _, a = scan_list(q8, delta, B, rows)
             all_a.append(a)
             all_id.append(ids)
         a = np.concatenate(all_a) if all_a else np.zeros(0, F32)
         ids = np.concatenate(all_id) if all_id else np.zeros(0, np.int64)
-        ca, cid = top_r(a, ids, R)
+        ca, cid = top_r_unique(a, ids, R) if spilled else top_r(a, ids, R)
         cand_a[qi, :len(ca)] = ca
         cand_id[qi, :len(cid)] = cid
         out_ids[qi], out_d[qi] = rerank(q_init, X, cid[:reo_used[qi]], k, metric)
@@ -415,6 +439,36 @@ def encode(X: np.ndarray, cm: np.ndarray, lists: np.ndarray, codebooks: np.ndarr
     diff = r.reshape(len(X), m, 1, dsub) - cb[None]
     dist = seq_sum(diff * diff)                      # [n, m, K]
     return np.argmin(dist, axis=2).astype(np.uint8)  # first minimum
+
+
+def spill_assign(X: np.ndarray, cm: np.ndarray, primary: np.ndarray, lam: float) -> np.ndarray:
+    """Spilled (secondary) list of every row, SOAR (section 4.6.2 integrates
+    it for points near list boundaries; the loss is the one SOAR defines).
+
+    With r = x - c_p the residual to the row's primary list p (mean
+    centroids, the residual origin) and r' = x - c_l for a candidate list
+    l != p, the spill list minimises
+        loss(l) = ||r'||^2 + lam * <r', r>^2 / ||r||^2,
+    the squared residual plus lam times the squared length of its projection
+    on r, so that the second residual is pushed towards being orthogonal to
+    the first (a query badly served by one list is then better served by
+    the other). A row equal to its centroid (r = 0) takes the nearest other
+    list. Ties go to the smaller list index. float64."""
+    X64 = np.asarray(X, dtype=np.float64)
+    C64 = np.asarray(cm, dtype=np.float64)
+    out = np.empty(len(X64), dtype=np.int64)
+    for i, x in enumerate(X64):
+        p = int(primary[i])
+        r = x - C64[p]
+        rr = float(r @ r)
+        dev = x[None, :] - C64
+        loss = (dev * dev).sum(axis=1)
+        if rr > 0.0:
+            proj = dev @ r
+            loss = loss + lam * proj * proj / rr
+        loss[p] = np.inf
+        out[i] = int(np.argmin(loss))  # first minimum
+    return out
 
 
 def brute_force_knn(X: np.ndarray, Q: np.ndarray, k: int, metric: str):

@@ -461,3 +461,128 @@ def test_filtered_search_all_lists_equals_brute_force_on_full_rows():
     res = oracle.search(idx, Xz, Qz, cfg.L, cfg.k, len(Xz))
     bf_ids, bf_d = oracle.brute_force_knn(Xz, Qz, cfg.k, cfg.metric)
     assert np.array_equal(res["ids"], bf_ids)
+
+
+# ---------------------------------- spilled assignment (section 4.6.2, SOAR)
+
+def test_spill_assign_hand_example():
+    # x = (1, 0) in list 0 (c = origin), so r = (1, 0). List 1 at (2, 0) leaves
+    # r' = (-1, 0), parallel to r: loss 1 + lam * 1. List 2 at (1, 1.5) leaves
+    # r' = (0, -1.5), orthogonal to r: loss 2.25. lam = 0 takes the nearer
+    # list 1; lam = 1.5 (loss 2.5) or more takes the orthogonal list 2.
+    X = np.array([[1.0, 0.0]], np.float32)
+    cm = np.array([[0.0, 0.0], [2.0, 0.0], [1.0, 1.5]], np.float32)
+    prim = np.array([0])
+    assert oracle.spill_assign(X, cm, prim, 0.0).tolist() == [1]
+    assert oracle.spill_assign(X, cm, prim, 1.0).tolist() == [1]
+    assert oracle.spill_assign(X, cm, prim, 1.5).tolist() == [2]
+    assert oracle.spill_assign(X, cm, prim, 4.0).tolist() == [2]
+    # Exact tie (mirror-image lists): the smaller list index.
+    X = np.array([[0.0, 1.0]], np.float32)
+    cm = np.array([[0.0, 0.0], [1.0, 1.0], [-1.0, 1.0]], np.float32)
+    assert oracle.spill_assign(X, cm, prim, 1.0).tolist() == [1]
+    # A row on its centroid (r = 0): the nearest other list.
+    X = np.array([[0.0, 0.0]], np.float32)
+    cm = np.array([[0.0, 0.0], [3.0, 0.0], [0.0, 2.0]], np.float32)
+    assert oracle.spill_assign(X, cm, prim, 1.0).tolist() == [2]
+
+
+def test_spill_assign_brute_force_projection_form():
+    rng = make_rng(8)
+    X = rng.standard_normal((40, 6))
+    cm = rng.standard_normal((9, 6))
+    prim = rng.integers(0, 9, size=40)
+    for lam in (0.0, 0.7, 1.0, 3.0):
+        got = oracle.spill_assign(X, cm, prim, lam)
+        for i in range(len(X)):
+            r = X[i] - cm[prim[i]]
+            P = np.outer(r, r) / float(r @ r)      # projection onto r
+            losses = []
+            for l in range(len(cm)):
+                if l == prim[i]:
+                    continue
+                rp = X[i] - cm[l]
+                pr = P @ rp
+                losses.append((float(rp @ rp) + lam * float(pr @ pr), l))
+            assert got[i] == min(losses)[1]
+        if lam == 0.0:
+            # lam = 0: the second-nearest list (the nearest other than p).
+            d = ((X[:, None, :] - cm[None]) ** 2).sum(axis=2)
+            d[np.arange(len(X)), prim] = np.inf
+            assert got.tolist() == np.argmin(d, axis=1).tolist()
+    # Larger lam: the chosen second residuals are less aligned with r.
+    cos0, cos3 = [], []
+    for lam, acc in ((0.0, cos0), (3.0, cos3)):
+        sp = oracle.spill_assign(X, cm, prim, lam)
+        for i in range(len(X)):
+            r, rp = X[i] - cm[prim[i]], X[i] - cm[sp[i]]
+            acc.append(abs(r @ rp) / np.linalg.norm(r) / np.linalg.norm(rp))
+    assert np.mean(cos3) < np.mean(cos0)
+
+
+def test_spill_lists_of_the_trainer_agree_with_oracle():
+    from workloads.train import _spill_lists
+    cfg, X, Q, _, index = cached_workload("c1", 3000, 4, L=16, ncomp=12)
+    off = index["list_offsets"]
+    prim = np.empty(len(X), np.int64)
+    prim[index["list_ids"]] = np.repeat(np.arange(cfg.L), np.diff(off))
+    ref = oracle.spill_assign(X, index["cm"], prim, 1.0)
+    got = _spill_lists(X, index["cm"], prim, 1.0)
+    assert (got == ref).mean() >= 0.99
+    assert (got != prim).all()
+
+
+def test_unique_pool_against_greedy_selection():
+    # Repeated ids with different and equal values; the pool keeps each id
+    # once at its smallest value. Greedy reference: take the smallest
+    # remaining (a, id) pair, then drop every entry of that id.
+    rng = make_rng(9)
+    a = rng.integers(0, 30, size=400).astype(np.float32)
+    ids = rng.integers(0, 150, size=400).astype(np.int64)
+    for R in (1, 5, 60, 150, 400):
+        ra, rid = oracle.top_r_unique(a, ids, R)
+        rest = sorted(zip(a.tolist(), ids.tolist()))
+        ref = []
+        while rest and len(ref) < R:
+            v, i = rest[0]
+            ref.append((v, i))
+            rest = [(w, j) for w, j in rest if j != i]
+        assert list(zip(ra.tolist(), rid.tolist())) == ref
+        assert len(set(rid.tolist())) == len(rid)
+
+
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_spilled_search_all_lists_equals_brute_force(name):
+    from workloads import spill_index
+    cfg, X, Q, _, index = cached_workload(name, 2500, 8, L=12, ncomp=10)
+    sp = spill_index(X, index, 1.0)
+    assert len(sp["list_ids"]) == 2 * len(X) and sp["codes"].shape[0] == 2 * len(X)
+    res = oracle.search(sp, X, Q, cfg.L, cfg.k, len(X))
+    ids, dist = oracle.brute_force_knn(X, Q, cfg.k, cfg.metric)
+    assert np.array_equal(res["ids"], ids)
+    for qi in range(len(Q)):
+        assert sorted(res["cand_id"][qi].tolist()) == list(range(len(X)))
+
+
+def test_spilled_pool_is_best_copy_of_each_point():
+    # Every pooled point's value is the smaller of its copies' values in the
+    # probed lists, recomputed from the stage tables and the entry codes;
+    # points in no probed list are absent, and nothing better is left out.
+    from workloads import spill_index
+    cfg, X, Q, _, index = cached_workload("c1", 3000, 6, L=16, ncomp=12)
+    sp = spill_index(X, index, 1.0)
+    off, lid, codes = sp["list_offsets"], sp["list_ids"], sp["codes"]
+    R = 150
+    res = oracle.search(sp, X, Q, 4, cfg.k, R, want_stages=True)
+    for qi in range(len(Q)):
+        best = {}
+        for l in res["probes"][qi]:
+            q8, lo, delta, B = res["luts"][(qi, int(l))]
+            for e in range(off[l], off[l + 1]):
+                s = sum(int(q8[j][codes[e][j]]) for j in range(codes.shape[1]))
+                v = np.float32(B + np.float32(delta * np.float32(s)))
+                i = int(lid[e])
+                best[i] = min(best.get(i, np.float32(np.inf)), v)
+        ref = sorted((v, i) for i, v in best.items())[:R]
+        got = list(zip(res["cand_a"][qi].tolist(), res["cand_id"][qi].tolist()))
+        assert got[:len(ref)] == [(float(v), i) for v, i in ref]

@@ -8,5 +8,5 @@ oracle consume what it produces; neither shares code with the other.
 """
 
 from .synth import CONFIGS, WorkloadConfig, make_workload, scaled  # noqa: F401
-from .train import train_index  # noqa: F401
+from .train import spill_index, train_index  # noqa: F401
 from .truth import exact_knn, recall_at_k  # noqa: F401

@@ -66,6 +66,59 @@ def _kmeans(X: np.ndarray, k: int, iters: int, rng, ip: bool) -> np.ndarray:
     return C
 
 
+def _spill_lists(X: np.ndarray, cm: np.ndarray, primary: np.ndarray, lam: float,
+                 chunk: int = 16384) -> np.ndarray:
+    """SOAR spill list of every row (float32 BLAS, chunked): the list l != p
+    minimising ||x - c_l||^2 + lam * <x - c_l, r>^2 / ||r||^2, r = x - c_p."""
+    out = np.empty(len(X), dtype=np.int64)
+    C = np.asarray(cm, dtype=np.float32)
+    Ct = np.ascontiguousarray(C.T)
+    cn = (C.astype(np.float64) ** 2).sum(axis=1).astype(np.float32)
+    for s in range(0, len(X), chunk):
+        x = np.asarray(X[s:s + chunk], dtype=np.float32)
+        p = primary[s:s + chunk]
+        r = x - C[p]
+        rr = (r * r).sum(axis=1)
+        xc = x @ Ct
+        dist = (x * x).sum(axis=1)[:, None] - 2.0 * xc + cn[None, :]
+        proj = (r * x).sum(axis=1)[:, None] - r @ Ct
+        loss = dist + lam * proj * proj / np.where(rr > 0, rr, 1.0)[:, None]
+        loss[np.arange(len(x)), p] = np.inf
+        out[s:s + chunk] = np.argmin(loss, axis=1)
+    return out
+
+
+def spill_index(X: np.ndarray, index: dict, lam: float, spill=None) -> dict:
+    """A copy of `index` where every point also lies in its SOAR spill list
+    (section 4.6.2): list_ids then holds 2 entries per point (ascending ids
+    within a list), codes are per entry ([entries, m], the residual to that
+    entry's list) and "copies" is 2. `spill` overrides the spill lists."""
+    assert "dims" not in index, "spill the sub-index before filtration"
+    off, lid = index["list_offsets"], np.asarray(index["list_ids"], dtype=np.int64)
+    L = len(off) - 1
+    assert L >= 2, "a spill list needs a second list"
+    primary = np.full(len(X), -1, dtype=np.int64)
+    primary[lid] = np.repeat(np.arange(L), np.diff(off))
+    assert (primary >= 0).all(), "every row must be in a list"
+    if spill is None:
+        spill = _spill_lists(X, index["cm"], primary, lam)
+    ent_list = np.concatenate([primary, spill])
+    ent_id = np.concatenate([np.arange(len(X)), np.arange(len(X))])
+    order = np.lexsort((ent_id, ent_list))
+    ent_list, ent_id = ent_list[order], ent_id[order]
+    codes = np.empty((len(ent_id), index["codebooks"].shape[0]), dtype=np.uint8)
+    step = 262144
+    for s in range(0, len(ent_id), step):
+        ids, ls = ent_id[s:s + step], ent_list[s:s + step]
+        codes[s:s + step] = encode(X[ids] - index["cm"][ls], index["codebooks"])
+    out = dict(index)
+    offsets = np.zeros(L + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(np.bincount(ent_list, minlength=L))
+    out.update(codes=codes, list_offsets=offsets, list_ids=ent_id.astype(np.int32),
+               copies=2, spill=spill, soar_lambda=float(lam))
+    return out
+
+
 def train_index(X: np.ndarray, cfg: WorkloadConfig, iters: int = 10,
                 pq_iters: int = 12, train_per_list: int = 64,
                 pq_train: int = 65536, dims=None):
