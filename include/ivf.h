@@ -70,15 +70,18 @@ typedef struct {
                                      centroids (section 4.6.1). Copied.           */
   const float* codebooks;         /* [m,16,d'] PQ codewords of the residuals.
                                      Copied.                                      */
-  const uint8_t* codes;           /* [n,m] one 4-bit code (0..15) per byte, row =
-                                     point id. Consumed: packed into the tables.  */
+  const uint8_t* codes;           /* one 4-bit code (0..15) per byte: [n,m], row =
+                                     point id; with copies >= 2 [list_offsets[L],m],
+                                     row = list entry (the residual to that entry's
+                                     list). Consumed: packed into the tables.     */
   const int64_t* list_offsets;    /* HOST [L+1] CSR offsets into list_ids,
                                      non-decreasing, list_offsets[0] == 0 and
-                                     list_offsets[L] <= n (rows in no list are
-                                     never returned).                             */
-  const int32_t* list_ids;        /* [list_offsets[L]] point ids (rows of base,
-                                     each at most once) grouped by list, ascending
-                                     within a list. Consumed.                     */
+                                     list_offsets[L] <= n * copies (rows in no
+                                     list are never returned).                    */
+  const int32_t* list_ids;        /* [list_offsets[L]] point ids (rows of base)
+                                     grouped by list, ascending within a list; a
+                                     point lies in at most `copies` lists.
+                                     Consumed.                                    */
   int32_t d_base;                 /* row width of `base` and of the queries the
                                      searches take: d, or 0 (= d) when dims is
                                      NULL; >= d otherwise                          */
@@ -89,6 +92,15 @@ typedef struct {
                                      Steps 1-4 use those components of each query,
                                      the re-rank the full d_base-wide query and
                                      rows. Copied.                                 */
+  int32_t copies;                 /* Spilled assignment (section 4.6.2, SOAR): the
+                                     most lists one point lies in, 1..4 (0 = 1).
+                                     With copies >= 2 a point scanned in several
+                                     probed lists enters the candidate pool once,
+                                     at the smallest of its approximate distances;
+                                     n * copies < 2^31 and rerank * copies <= 2048.
+                                     ivf_build_tables fails with
+                                     IVF_ERR_INVALID_ARG when a point lies in more
+                                     lists.                                       */
 } ivf_index_desc;
 
 /* Coarse-scoring precision (step 1). IVF_COARSE_EXACT scores every list with
@@ -173,7 +185,10 @@ size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq,
                                   int32_t max_nprobe, int32_t k,
                                   int32_t rerank, const ivf_search_opts* opts);
 
-/* Search nq queries (Alg. 2 with static parameters).
+/* Search nq queries (Alg. 2 with static parameters). On a spilled index
+ * (copies >= 2) the scan keeps the rerank * copies best (distance, copy)
+ * keys, which hold the rerank best distinct points, and the pool keeps each
+ * of those once at its best copy before the re-rank.
  *   queries  [nq,d] FP32 row-major.
  *   nprobe   [nq] int32, each in 1..max_nprobe (max_nprobe <= L). A value out
  *            of range sets the device error word (ivf_get_device_error) and
@@ -242,7 +257,8 @@ ivf_status ivf_debug_luts(const ivf_index* idx, const float* queries,
 /* Steps 2-4 on caller-given probes: out_keys [nq,rerank] uint64 candidate
  * keys in ascending order, key = (ord(a) << 32) | id, where a is the FP32
  * ADC value and ord maps float order onto unsigned order (sign bit set:
- * all bits inverted; else sign bit set). Padding is UINT64_MAX. */
+ * all bits inverted; else sign bit set). Padding is UINT64_MAX. On a
+ * spilled index each point appears once, at its smallest a. */
 ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries,
                                 int32_t nq, const int32_t* probes,
                                 const int32_t* nprobe, int32_t max_nprobe,
@@ -253,7 +269,8 @@ ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries,
 /* Byte offsets of the table sections inside table_mem (for inspection):
  * codes: uint32 [blocks][words][64], word w of a point holds the 4-bit codes
  * of subspaces 8w..8w+7 in bits 4s..4s+3 (padding subspaces are 0);
- * slot_ids: int32 [blocks][64] point id per slot, -1 for padding;
+ * slot_ids: int32 [blocks][64] point id per slot, -1 for padding (spilled
+ * index: id * copies + c, c numbering one point's entries in slot order);
  * block_offsets: int32 [L+1] first block of each list; dims: int32 [d] kept
  * base columns of a filtered index (an empty section without filtration). */
 typedef struct {
@@ -314,6 +331,25 @@ ivf_status ivf_encode(const float* X, int64_t n, int32_t d,
                       const float* centroids, const int32_t* lists,
                       const float* codebooks, int32_t m, uint8_t* out_codes,
                       void* stream);
+
+/* Spill lists of SOAR (section 4.6.2 integrates it; the loss is SOAR's):
+ * for every row x of X [n,d] with primary list p = primary[x] and residual
+ * r = x - c_p, out_list[x] = the list l != p with the smallest
+ *   loss(l) = sum_t (x_t - c_lt)^2 + lam * (sum_t r_t (x_t - c_lt))^2 / sum_t r_t^2
+ * (the second term is dropped when r = 0), ties to the smaller l. Canonical
+ * FP32: every component difference rounded once, the three sums sequential
+ * in t, no fused multiply-add, then pp = proj * proj, loss = dist +
+ * lam * (pp / rr). All arrays device: centroids [L,d] (the mean centroids,
+ * the residual origin), primary [n] int32 in [0, L) (a row whose primary is
+ * out of range gets out_list -1), out_list [n] int32.
+ * L >= 2, lam finite and >= 0. Rows are processed `chunk` at a time
+ * (workspace: ivf_assign_spill_workspace_bytes). */
+size_t ivf_assign_spill_workspace_bytes(int32_t L, int32_t d, int32_t chunk);
+ivf_status ivf_assign_spill(const float* centroids, int32_t L, int32_t d,
+                            const float* X, int64_t n, const int32_t* primary,
+                            float lam, int32_t chunk, void* workspace,
+                            size_t workspace_bytes, int32_t* out_list,
+                            void* stream);
 
 /* Frees the host handle only; table_mem stays the caller's. */
 void ivf_destroy(ivf_index* idx);

@@ -28,6 +28,7 @@ EXPORTED = [
     "ivf_debug_candidates", "ivf_get_table_layout", "ivf_get_device_error", "ivf_destroy",
     "ivf_last_error", "ivf_profile_enable", "ivf_profile_read", "ivf_debug_coarse_scores",
     "ivf_assign_workspace_bytes", "ivf_assign", "ivf_encode", "ivf_debug_adaptive",
+    "ivf_assign_spill_workspace_bytes", "ivf_assign_spill",
 ]
 STAGES = ("coarse", "select", "prep", "scan", "merge", "rerank")
 
@@ -45,7 +46,8 @@ class IndexDesc(ctypes.Structure):
                 ("centroids", ctypes.c_void_p), ("probe_centroids", ctypes.c_void_p),
                 ("codebooks", ctypes.c_void_p), ("codes", ctypes.c_void_p),
                 ("list_offsets", ctypes.c_void_p), ("list_ids", ctypes.c_void_p),
-                ("d_base", ctypes.c_int32), ("dims", ctypes.c_void_p)]
+                ("d_base", ctypes.c_int32), ("dims", ctypes.c_void_p),
+                ("copies", ctypes.c_int32)]
 
 
 class SearchOpts(ctypes.Structure):
@@ -92,6 +94,8 @@ def _declare(lib):
         "ivf_assign_workspace_bytes": (SZ, [I32, I32, I32, I32]),
         "ivf_assign": (I32, [P, I32, I32, I32, P, I64, I32, I32, I32, P, SZ, P, P]),
         "ivf_encode": (I32, [P, I64, I32, P, P, P, I32, P, P]),
+        "ivf_assign_spill_workspace_bytes": (SZ, [I32, I32, I32]),
+        "ivf_assign_spill": (I32, [P, I32, I32, P, I64, P, ctypes.c_float, I32, P, SZ, P, P]),
         "ivf_debug_adaptive": (I32, [P, P, I32, P, I32, I32, I32, P, P, SZ, P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -174,7 +178,7 @@ class GpuIndex:
 
     def __init__(self, base, centroids, codebooks, codes, list_offsets, list_ids,
                  metric: str, probe_centroids=None, base_dtype: str = "f32",
-                 device: str = "cuda", dims=None):
+                 device: str = "cuda", dims=None, copies: int = 1):
         import numpy as np
         import torch
         L = lib()
@@ -200,6 +204,8 @@ class GpuIndex:
         self.dims = None if dims is None else np.ascontiguousarray(np.asarray(dims, np.int32))
         self.n, self.d, self.L, self.m, self.metric = n, d, Lc, m, metric
         self.d_base = d_base
+        # Spilled index (section 4.6.2): codes are per list entry.
+        self.copies = int(copies)
         desc = IndexDesc(n=n, d=d, L=Lc, m=m, metric=METRIC[metric],
                          base_dtype=DTYPE[base_dtype], base=_ptr(self.base),
                          centroids=_ptr(self.centroids),
@@ -207,7 +213,8 @@ class GpuIndex:
                          codebooks=_ptr(self.codebooks), codes=_ptr(codes_t),
                          list_offsets=offs.ctypes.data, list_ids=_ptr(ids_t),
                          d_base=d_base if self.dims is not None else 0,
-                         dims=None if self.dims is None else self.dims.ctypes.data)
+                         dims=None if self.dims is None else self.dims.ctypes.data,
+                         copies=self.copies)
         nbytes = L.ivf_tables_bytes(ctypes.byref(desc))
         if nbytes == 0:
             raise IvfError(IVF_ERR_INVALID_ARG, last_error())
@@ -223,7 +230,8 @@ class GpuIndex:
     def from_index(cls, index: dict, X, base_dtype: str = "f32", device: str = "cuda"):
         return cls(X, index["cm"], index["codebooks"], index["codes"], index["list_offsets"],
                    index["list_ids"], index["metric"], probe_centroids=index["cp"],
-                   base_dtype=base_dtype, device=device, dims=index.get("dims"))
+                   base_dtype=base_dtype, device=device, dims=index.get("dims"),
+                   copies=int(index.get("copies", 1)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -410,6 +418,25 @@ def assign_lists(centroids, X, metric: str, coarse: str = "bf16", widen: int = 4
     out = torch.empty(n, dtype=torch.int32, device=X.device)
     check(lib().ivf_assign(_ptr(centroids), L, d, METRIC[metric], _ptr(X), n, chunk,
                            COARSE[coarse], widen, ws.data_ptr(), nb, _ptr(out), _stream()))
+    return out
+
+
+def assign_spill(centroids, X, primary, lam: float = 1.0, chunk: int = 65536):
+    """SOAR spill list per row of X (device tensors) via ivf_assign_spill: the
+    list l != primary minimising ||x - c_l||^2 + lam <x - c_l, r>^2 / ||r||^2
+    with r = x - c_primary (section 4.6.2); int32 tensor."""
+    import torch
+    L, d = centroids.shape
+    n = X.shape[0]
+    chunk = max(1, min(chunk, n))
+    nb = lib().ivf_assign_spill_workspace_bytes(L, d, chunk)
+    if nb == 0:
+        raise IvfError(IVF_ERR_INVALID_ARG, last_error())
+    ws = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    out = torch.empty(n, dtype=torch.int32, device=X.device)
+    prim = primary.to(dtype=torch.int32).contiguous()
+    check(lib().ivf_assign_spill(_ptr(centroids), L, d, _ptr(X), n, _ptr(prim), float(lam),
+                                 chunk, ws.data_ptr(), nb, _ptr(out), _stream()))
     return out
 
 

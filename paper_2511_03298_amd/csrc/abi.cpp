@@ -89,7 +89,12 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
     blocks += (len + BLOCK_PTS - 1) / BLOCK_PTS;
     if (len > mx) mx = len;
   }
-  if (off[d->L] > d->n) return "list_offsets[L] must be <= n";
+  if (d->copies < 0 || d->copies > 4) return "copies must be in 0..4";
+  const int64_t copies = d->copies > 1 ? d->copies : 1;
+  if (copies > 1 && d->n * copies >= ((int64_t)1 << 31) - 1) return "n * copies must be < 2^31 - 1";
+  if (off[d->L] > d->n * copies) return copies > 1 ? "list_offsets[L] must be <= n * copies"
+                                                   : "list_offsets[L] must be <= n";
+  if (blocks * BLOCK_PTS >= ((int64_t)1 << 31)) return "too many list entries (blocks * 64 >= 2^31)";
   if (d->dims) {
     if (d->d_base < d->d) return "d_base must be >= d with dims";
     for (int j = 0; j < d->d; ++j) {
@@ -126,7 +131,9 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
   lay->probe_fp8 = take((size_t)lay->L_padded * lay->d_padded);
   lay->probe_fp8_scale = take((size_t)lay->L_padded * 4);
   lay->dims = take(d->dims ? (size_t)d->d * 4 : 0);
-  // Build-time copy of the CSR offsets (int64), then the end.
+  // Build-time scratch: a spilled index's per-point numbering array and flag,
+  // then the copy of the CSR offsets (int64), then the end.
+  take(copies > 1 ? (size_t)(d->n + 64) * 4 : 0);
   take((size_t)(d->L + 1) * 8);
   lay->total = o;
   if (max_len) *max_len = (int32_t)mx;
@@ -135,6 +142,11 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
 
 size_t list_off_section(const ivf_index_desc* d, const ivf_table_layout& lay) {
   return lay.total - align_up((size_t)(d->L + 1) * 8);
+}
+
+// Numbering scratch of a spilled index: [n] int32, then the flag word.
+size_t copies_section(const ivf_index_desc* d, const ivf_table_layout& lay) {
+  return list_off_section(d, lay) - align_up((size_t)(d->n + 64) * 4);
 }
 
 ivf_status check_device() {
@@ -191,6 +203,8 @@ ivf_status check_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, in
   if (rerank < 1 || rerank > MAX_RERANK)
     return fail(IVF_ERR_INVALID_ARG, "rerank must be in [1, 2048]");
   if (k < 1 || k > rerank) return fail(IVF_ERR_INVALID_ARG, "k must be in [1, rerank]");
+  if ((int64_t)rerank * idx->t.copies > MAX_RERANK)
+    return fail(IVF_ERR_INVALID_ARG, "rerank * copies must be <= 2048 on a spilled index");
   return IVF_OK;
 }
 
@@ -209,6 +223,7 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   (void)k;
   Workspace w;
   std::memset(&w, 0, sizeof(w));
+  const int32_t pool = rerank * t.copies;  // scan pool: keys of list entries
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -223,7 +238,8 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   w.reorder_eff = (int32_t*)take(nqs * 4);
   if (t.dims) w.qf = (float*)take(nqs * t.d * 4);
   w.bias = (float*)take(nqs * max_nprobe * 4);
-  w.cand = (uint64_t*)take(nqs * rerank * 8);
+  w.cand = (uint64_t*)take(nqs * pool * 8);
+  if (t.copies > 1) w.cand_u = (uint64_t*)take(nqs * rerank * 8);
   if (o.coarse != IVF_COARSE_EXACT) {
     const size_t nq_pad = (size_t)round_up_i((int64_t)nqs, TILE_L);
     w.q_lowp = (void*)take(nq_pad * t.d_pad * 4);
@@ -232,7 +248,7 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   w.pool_cap = o.pool_cap;
   w.grid = o.grid;
   if (o.form == IVF_FORM_BATCHED) {
-    w.spill_cap = o.spill_cap > 0 ? o.spill_cap : batched_spill_cap(rerank, nq);
+    w.spill_cap = o.spill_cap > 0 ? o.spill_cap : batched_spill_cap(pool, nq);
     w.p1 = (int32_t*)take(nqs * 4);
     w.thr = (uint64_t*)take(nqs * 8);
     w.list_cnt = (int32_t*)take((size_t)t.L * 4);
@@ -321,6 +337,7 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
   t.d_pad = lay.d_padded;
   t.max_list_len = max_len;
   t.d_base = desc->dims ? desc->d_base : desc->d;
+  t.copies = desc->copies > 1 ? desc->copies : 1;
   t.dims = desc->dims ? (const int32_t*)(base + lay.dims) : nullptr;
   t.base = desc->base;
   t.codes = (const uint32_t*)(base + lay.codes);
@@ -360,6 +377,17 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
   IVF_HIP(hipMemcpyAsync((void*)t.codebooks, desc->codebooks, cb_bytes, hipMemcpyDeviceToDevice, s));
   IVF_HIP(launch_pack(t, desc->codes, list_off_dev, desc->list_ids, s));
   IVF_HIP(launch_aux_tables(t, s));
+  if (t.copies > 1) {
+    int32_t* first = (int32_t*)(base + copies_section(desc, lay));
+    int32_t* flag = first + desc->n;
+    IVF_HIP(launch_number_copies(t, first, flag, s));
+    int32_t too_many = 0;
+    IVF_HIP(hipMemcpyAsync(&too_many, flag, 4, hipMemcpyDeviceToHost, s));
+    IVF_HIP(hipStreamSynchronize(s));
+    if (too_many)
+      return fail(IVF_ERR_INVALID_ARG,
+                  "a list entry names a point outside [0, n) or one in more than copies lists");
+  }
   IVF_HIP(hipStreamSynchronize(s));
 
   ivf_index* idx = new (std::nothrow) ivf_index;
@@ -436,8 +464,8 @@ size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq, int32_t max_
   if (opts) o = *opts;
   if (check_opts(o) != IVF_OK) return 0;
   if (check_search(idx, nq, max_nprobe, k, rerank) != IVF_OK) return 0;
-  if (o.spill_cap > 16384 - rerank) {
-    (void)fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be at most 16384 - rerank");
+  if (o.spill_cap > 16384 - rerank * idx->t.copies) {
+    (void)fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be at most 16384 - rerank * copies");
     return 0;
   }
   return plan_workspace(idx->t, nq, max_nprobe, k, rerank, o, nullptr).total;
@@ -488,8 +516,8 @@ ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, in
   if (opts) *o = *opts;
   st = check_opts(*o);
   if (st != IVF_OK) return st;
-  if (o->spill_cap > 16384 - rerank)
-    return fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be at most 16384 - rerank");
+  if (o->spill_cap > 16384 - rerank * idx->t.copies)
+    return fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be at most 16384 - rerank * copies");
   st = check_form(idx, *o);
   if (st != IVF_OK) return st;
   Workspace need = plan_workspace(idx->t, nq, max_nprobe, k, rerank, *o, nullptr);
@@ -505,34 +533,41 @@ ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, const float
                                const ivf_search_opts& o, const Workspace& w, int64_t* out_ids,
                                float* out_dist, hipStream_t s) {
   const Tables& t = idx->t;
+  // The scan keeps `pool` keys of list entries; on a spilled index they are
+  // reduced to `rerank` distinct points before the re-rank.
+  const int32_t pool = rerank * t.copies;
   IVF_HIP(prof_mark(idx, s, IVF_STAGE_PREP));
   IVF_HIP(launch_bias(t, Q, nq, max_nprobe, w, s));
   if (o.form == IVF_FORM_BATCHED) {
     // Rounds over probe ranks [b_r, b_{r+1}) with b = 0, 4, 16, 64, ...:
     // each round's merge publishes a tighter threshold for the next.
     const int rounds = o.rounds > 0 ? o.rounds : 1;
-    IVF_HIP(launch_batched_first(t, Q, nq, max_nprobe, rerank, w, s));
+    IVF_HIP(launch_batched_first(t, Q, nq, max_nprobe, pool, w, s));
     int lo = 0;
     for (int r = 0; r < rounds; ++r) {
       const int hi = r + 1 == rounds ? max_nprobe : (lo == 0 ? 4 : lo * 4);
       if (r > 0) IVF_HIP(prof_mark(idx, s, IVF_STAGE_PREP));
       IVF_HIP(launch_batched_pairs(t, nq, max_nprobe, lo, hi, w, s));
       IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
-      IVF_HIP(launch_batched_main(t, Q, nq, max_nprobe, rerank, w, s));
+      IVF_HIP(launch_batched_main(t, Q, nq, max_nprobe, pool, w, s));
       IVF_HIP(prof_mark(idx, s, IVF_STAGE_MERGE));
-      IVF_HIP(launch_batched_merge(t, nq, rerank, w, s));
+      IVF_HIP(launch_batched_merge(t, nq, pool, w, s));
       lo = hi;
       if (lo >= max_nprobe) break;
     }
-    IVF_HIP(launch_batched_redo(t, Q, nq, max_nprobe, rerank, w, s));
+    IVF_HIP(launch_batched_redo(t, Q, nq, max_nprobe, pool, w, s));
   } else {
     IVF_HIP(prof_mark(idx, s, IVF_STAGE_SCAN));
-    IVF_HIP(launch_scan_plain(t, Q, nq, max_nprobe, rerank, w, s));
+    IVF_HIP(launch_scan_plain(t, Q, nq, max_nprobe, pool, w, s));
+  }
+  if (t.copies > 1) {
+    IVF_HIP(prof_mark(idx, s, IVF_STAGE_MERGE));
+    IVF_HIP(launch_dedup_pool(t, nq, rerank, w, s));
   }
   IVF_HIP(prof_mark(idx, s, IVF_STAGE_RERANK));
   if (out_ids)
-    IVF_HIP(launch_rerank(t, Qr, nq, k, rerank, o.adaptive ? w.reorder_eff : nullptr, w, out_ids,
-                          out_dist, s));
+    IVF_HIP(launch_rerank(t, Qr, nq, k, rerank, t.copies > 1 ? w.cand_u : w.cand,
+                          o.adaptive ? w.reorder_eff : nullptr, w, out_ids, out_dist, s));
   IVF_HIP(prof_mark(idx, s, IVF_NSTAGES));
   return IVF_OK;
 }
@@ -785,8 +820,9 @@ ivf_status ivf_debug_candidates(const ivf_index* idx, const float* queries, int3
   if (st != IVF_OK) return st;
   st = run_scan_and_rerank(idx, Qs, queries, nq, max_nprobe, 1, rerank, o, w, nullptr, nullptr, s);
   if (st != IVF_OK) return st;
-  IVF_HIP(launch_sort_rows(w.cand, nq, rerank, s));
-  IVF_HIP(hipMemcpyAsync(out_keys, w.cand, (size_t)nq * rerank * 8, hipMemcpyDeviceToDevice, s));
+  uint64_t* pool = idx->t.copies > 1 ? w.cand_u : w.cand;
+  IVF_HIP(launch_sort_rows(pool, nq, rerank, s));
+  IVF_HIP(hipMemcpyAsync(out_keys, pool, (size_t)nq * rerank * 8, hipMemcpyDeviceToDevice, s));
   return IVF_OK;
 }
 
@@ -815,6 +851,7 @@ AssignPlan plan_assign(int32_t L, int32_t d, int32_t metric, int32_t chunk, int3
   Tables& t = a.t;
   t.d = d;
   t.d_base = d;
+  t.copies = 1;
   t.L = L;
   t.m = 1;
   t.dsub = d;
@@ -886,6 +923,46 @@ ivf_status ivf_assign(const float* centroids, int32_t L, int32_t d, int32_t metr
       IVF_HIP(launch_coarse_mfma(a.t, Xc, rows, coarse, w, s));
       IVF_HIP(launch_select_probes(a.t, Xc, rows, a.ones, 1, widen, true, w, s));
     }
+  }
+  return IVF_OK;
+}
+
+size_t ivf_assign_spill_workspace_bytes(int32_t L, int32_t d, int32_t chunk) {
+  if (L < 2 || L > 16384 || d < 1 || chunk < 1 || chunk > (1 << 20)) {
+    g_last_error = "invalid spill-assign sizes";
+    return 0;
+  }
+  return plan_assign(L, d, IVF_METRIC_L2, chunk, IVF_COARSE_EXACT, nullptr, nullptr).total;
+}
+
+ivf_status ivf_assign_spill(const float* centroids, int32_t L, int32_t d, const float* X,
+                            int64_t n, const int32_t* primary, float lam, int32_t chunk,
+                            void* workspace, size_t workspace_bytes, int32_t* out_list,
+                            void* stream) {
+  if (L < 2 || L > 16384 || d < 1 || n < 0 || chunk < 1 || chunk > (1 << 20))
+    return fail(IVF_ERR_INVALID_ARG, "invalid spill-assign sizes");
+  if (!std::isfinite(lam) || lam < 0.0f) return fail(IVF_ERR_INVALID_ARG, "lam must be finite and >= 0");
+  if (n == 0) return IVF_OK;
+  if (!centroids || !X || !primary || !out_list || !workspace)
+    return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  if ((uintptr_t)workspace % ALIGN) return fail(IVF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  // The exact-coarse assign layout: scores [chunk][L] hold the losses, the
+  // top-1 selection over them picks the spill list.
+  AssignPlan a = plan_assign(L, d, IVF_METRIC_L2, chunk, IVF_COARSE_EXACT, centroids,
+                             (char*)workspace);
+  if (workspace_bytes < a.total) return fail(IVF_ERR_WORKSPACE, "workspace too small");
+  ivf_status st = check_device();
+  if (st != IVF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_fill_u32((uint32_t*)a.ones, 1u, (size_t)chunk, s));
+  IVF_HIP(launch_fill_u32((uint32_t*)a.w.err, 0u, 4, s));
+  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+    const int32_t rows = (int32_t)((n - r0) < chunk ? (n - r0) : chunk);
+    Workspace w = a.w;
+    w.probes = out_list + r0;
+    IVF_HIP(launch_spill_loss(X + r0 * d, rows, d, centroids, L, primary + r0, lam, w.scores, s));
+    IVF_HIP(launch_select_probes(a.t, X + r0 * d, rows, a.ones, 1, 1, false, w, s));
+    IVF_HIP(launch_spill_fix(primary + r0, rows, L, out_list + r0, s));
   }
   return IVF_OK;
 }

@@ -30,6 +30,7 @@ struct Tables {
   int32_t L_pad, d_pad;
   int32_t max_list_len;
   int32_t d_base;               // row width of base / queries (>= d)
+  int32_t copies;               // most lists one point lies in (spilled index: >= 2)
   const int32_t* dims;          // [d] kept base columns, or nullptr
   const void* base;
   const uint32_t* codes;        // [blocks][words][64]
@@ -69,7 +70,8 @@ struct Workspace {
   int32_t* reorder_eff; // [nq] re-rank size (adaptive form; else rerank)
   float* qf;            // [nq][d] kept query components (filtered index only)
   float* bias;          // [nq][max_nprobe] per-(q,list) constant (IP), else unused
-  uint64_t* cand;       // [nq][rerank]
+  uint64_t* cand;       // [nq][rerank * copies] scan pool (keys of list entries)
+  uint64_t* cand_u;     // [nq][rerank] one key per point (spilled index only)
   int32_t* err;         // [4] device error word
   // batched form
   int32_t* p1;          // [nq] first probe slot of phase 2
@@ -103,6 +105,9 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
 // ---- launchers (each enqueues on `s`, returns hipSuccess or an error) ----
 hipError_t launch_pack(const Tables& t, const uint8_t* codes, const int64_t* list_off_dev,
                        const int32_t* list_ids, hipStream_t s);
+// Spilled index: slot values id * copies + c (see tables.hip); first [n] and
+// flag [1] are scratch, flag[0] = 1 when a point lies in too many lists.
+hipError_t launch_number_copies(const Tables& t, int32_t* first, int32_t* flag, hipStream_t s);
 hipError_t launch_aux_tables(const Tables& t, hipStream_t s);
 
 hipError_t launch_coarse_exact(const Tables& t, const float* Q, int32_t nq, float* scores,
@@ -147,10 +152,21 @@ hipError_t launch_batched_redo(const Tables& t, const float* Q, int32_t nq, int3
 hipError_t launch_debug_luts(const Tables& t, const float* Q, int32_t nq, const int32_t* probes,
                              const int32_t* nprobe, int32_t max_nprobe, uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
                              hipStream_t s);
-// reorder: per-query re-rank sizes (<= rerank) or nullptr for all of them.
+// pool: [nq][rerank] keys with point ids in their low 32 bits; reorder:
+// per-query re-rank sizes (<= rerank) or nullptr for all of them.
 hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k, int32_t rerank,
-                         const int32_t* reorder,
+                         const uint64_t* pool, const int32_t* reorder,
                          const Workspace& w, int64_t* out_ids, float* out_dist, hipStream_t s);
+// Spilled index: from the [nq][rerank * copies] entry keys of w.cand, each
+// point once at its smallest key, the rerank smallest into w.cand_u.
+hipError_t launch_dedup_pool(const Tables& t, int32_t nq, int32_t rerank, const Workspace& w,
+                             hipStream_t s);
+// SOAR spill loss of rows X [rows][d] against every list (canonical FP32;
+// +inf for the row's primary list) into loss [rows][L].
+hipError_t launch_spill_loss(const float* X, int32_t rows, int32_t d, const float* C, int32_t L,
+                             const int32_t* primary, float lam, float* loss, hipStream_t s);
+hipError_t launch_spill_fix(const int32_t* primary, int32_t rows, int32_t L, int32_t* out,
+                            hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_sort_rows(uint64_t* cand, int32_t nq, int32_t R, hipStream_t s);
 hipError_t launch_encode(const float* X, int64_t n, int32_t d, int32_t m, const float* cm,

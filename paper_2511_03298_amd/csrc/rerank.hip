@@ -186,12 +186,77 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
 }
 
 hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k, int32_t rerank,
-                         const int32_t* reorder, const Workspace& w, int64_t* out_ids,
-                         float* out_dist, hipStream_t s) {
+                         const uint64_t* pool, const int32_t* reorder, const Workspace& w,
+                         int64_t* out_ids, float* out_dist, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   size_t lds = (size_t)pow2_ceil((uint32_t)rerank) * 8 + (size_t)t.d_base * 4;
   hipLaunchKernelGGL(rerank_kernel<4>, dim3(nq), dim3(256), lds, s, t, Q, k, rerank, w.nprobe_eff,
-                     w.cand, reorder, out_ids, out_dist);
+                     pool, reorder, out_ids, out_dist);
+  return hipGetLastError();
+}
+
+// Pool of a spilled index (section 4.6.2). The scan keeps the P = R * copies
+// smallest keys (ord(a) << 32 | id * copies + c); since keys order by
+// (a, id) first and one point has at most `copies` of them, those hold every
+// key a point needs to be among the R best distinct points. One workgroup
+// per query: re-key as (id << 32 | ord(a)) and sort, so that each point's
+// copies are adjacent with its best first; keep the first of every run as
+// (ord(a) << 32 | id); then the R smallest of those.
+__global__ void __launch_bounds__(256) dedup_kernel(const uint64_t* __restrict__ in, int32_t P,
+                                                    int32_t copies, int32_t R,
+                                                    uint64_t* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);  // [pow2(P)]
+  __shared__ SelectScratch sc;
+  __shared__ uint32_t cnt;
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const uint32_t n2 = pow2_ceil((uint32_t)P);
+  for (uint32_t i = tid; i < n2; i += blockDim.x) {
+    const uint64_t v = i < (uint32_t)P ? in[(size_t)q * P + i] : KEY_NONE;
+    keys[i] = v == KEY_NONE ? KEY_NONE
+                            : ((uint64_t)((uint32_t)v / (uint32_t)copies) << 32) | (v >> 32);
+  }
+  block_bitonic_sort(keys, n2);
+  // First key of each point's run, back in (ord << 32 | id) form; the rest
+  // and the padding become KEY_NONE. All reads happen before any write.
+  constexpr int PER = 8;  // n2 <= 2048 = 8 * 256
+  uint64_t nv[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t i = tid + r * blockDim.x;
+    nv[r] = KEY_NONE;
+    if (i < n2) {
+      const uint64_t v = keys[i];
+      const bool first = v != KEY_NONE && (i == 0 || (keys[i - 1] >> 32) != (v >> 32));
+      if (first) nv[r] = ((v & 0xffffffffull) << 32) | (v >> 32);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const uint32_t i = tid + r * blockDim.x;
+    if (i < n2) keys[i] = nv[r];
+  }
+  __syncthreads();
+  uint32_t n = block_compact_le(keys, n2, KEY_NONE - 1, &cnt);
+  if (n > (uint32_t)R) {
+    KeyUnion u{keys, n, nullptr, 0};
+    const uint64_t thr = block_kth(u, (uint32_t)R, &sc);  // keys are unique now
+    n = block_compact_le(keys, n, thr, &cnt);
+  }
+  for (int i = tid; i < R; i += blockDim.x)
+    out[(size_t)q * R + i] = (uint32_t)i < n ? keys[i] : KEY_NONE;
+}
+
+hipError_t launch_dedup_pool(const Tables& t, int32_t nq, int32_t rerank, const Workspace& w,
+                             hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  const int32_t P = rerank * t.copies;
+  if (pow2_ceil((uint32_t)P) > 2048u) return hipErrorInvalidValue;
+  const size_t lds = (size_t)pow2_ceil((uint32_t)P) * 8;
+  hipLaunchKernelGGL(dedup_kernel, dim3(nq), dim3(256), lds, s, w.cand, P, t.copies, rerank,
+                     w.cand_u);
   return hipGetLastError();
 }
 

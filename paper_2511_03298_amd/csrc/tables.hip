@@ -28,12 +28,14 @@ __global__ void __launch_bounds__(256) pack_kernel(Tables t, const uint8_t* __re
   const int64_t p = (int64_t)(blk - t.block_off[l]) * BLOCK_PTS + lane;
   const bool valid = p < t.list_len[l];
   const int32_t id = valid ? list_ids[list_off[l] + p] : -1;
+  // Code row: the point's (one copy per point) or the list entry's (spilled).
+  const int64_t row = t.copies > 1 ? list_off[l] + p : (int64_t)id;
   for (int w = 0; w < t.words; ++w) {
     uint32_t word = 0;
     if (valid) {
       for (int s = 0; s < 8; ++s) {
         int j = 8 * w + s;
-        if (j < t.m) word |= (uint32_t)(codes[(int64_t)id * t.m + j] & 15) << (4 * s);
+        if (j < t.m) word |= (uint32_t)(codes[row * t.m + j] & 15) << (4 * s);
       }
     }
     out_codes[((size_t)blk * t.words + w) * BLOCK_PTS + lane] = word;
@@ -93,6 +95,60 @@ __global__ void __launch_bounds__(256) aux_kernel(Tables t) {
 
 hipError_t launch_aux_tables(const Tables& t, hipStream_t s) {
   hipLaunchKernelGGL(aux_kernel, dim3(t.L_pad), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+
+// Spilled index (section 4.6.2): the slots of one point get distinct values
+// id * copies + c, c = 0, 1, ... in slot order, so that every search key
+// (ord(a) << 32 | slot value) is unique and id = value / copies. Round r
+// finds, per point, the first slot not numbered yet (atomicMin into first[]),
+// numbers it r and marks it with the top bit (values stay below 2^31 - 1, so
+// a marked slot never reads as the -1 padding). A slot still unmarked after
+// `copies` rounds belongs to a point in more lists than allowed (or is not a
+// row of base): flag[0] = 1.
+__global__ void copies_min_kernel(const int32_t* __restrict__ slot_ids, int64_t slots, int64_t n,
+                                  int32_t* __restrict__ first) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= slots) return;
+  const int32_t v = slot_ids[sl];
+  if (v >= 0 && v < n) atomicMin(&first[v], (int32_t)sl);
+}
+
+__global__ void copies_mark_kernel(int32_t* __restrict__ slot_ids, int64_t slots, int64_t n,
+                                   const int32_t* __restrict__ first, int32_t copies, int32_t r) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= slots) return;
+  const int32_t v = slot_ids[sl];
+  if (v >= 0 && v < n && first[v] == (int32_t)sl)
+    slot_ids[sl] = (int32_t)(0x80000000u | (uint32_t)(v * copies + r));
+}
+
+__global__ void copies_final_kernel(int32_t* __restrict__ slot_ids, int64_t slots,
+                                    int32_t* __restrict__ flag) {
+  const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= slots) return;
+  const int32_t v = slot_ids[sl];
+  if (v == -1) return;
+  if (v >= 0)
+    flag[0] = 1;
+  else
+    slot_ids[sl] = (int32_t)((uint32_t)v & 0x7fffffffu);
+}
+
+hipError_t launch_number_copies(const Tables& t, int32_t* first, int32_t* flag, hipStream_t s) {
+  const int64_t slots = (int64_t)t.blocks * BLOCK_PTS;
+  hipError_t e = launch_fill_u32((uint32_t*)flag, 0u, 1, s);
+  if (e != hipSuccess || slots == 0) return e;
+  const unsigned grid = (unsigned)((slots + 255) / 256);
+  int32_t* ids = const_cast<int32_t*>(t.slot_ids);
+  for (int r = 0; r < t.copies; ++r) {
+    e = launch_fill_u32((uint32_t*)first, 0x7fffffffu, (size_t)t.n, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(copies_min_kernel, dim3(grid), dim3(256), 0, s, ids, slots, t.n, first);
+    hipLaunchKernelGGL(copies_mark_kernel, dim3(grid), dim3(256), 0, s, ids, slots, t.n, first,
+                       t.copies, r);
+  }
+  hipLaunchKernelGGL(copies_final_kernel, dim3(grid), dim3(256), 0, s, ids, slots, flag);
   return hipGetLastError();
 }
 

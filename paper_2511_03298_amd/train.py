@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import assign_lists, encode_codes
+from . import assign_lists, assign_spill, encode_codes
 
 KSUB = 16
 
@@ -77,18 +77,21 @@ def component_filter(X: np.ndarray, threshold: float, chunk: int = 1 << 18) -> n
 def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
                     iters: int = 10, pq_iters: int = 12, train_per_list: int = 64,
                     pq_train: int = 65536, coarse: str = "bf16", widen: int = 4,
-                    device: str = "cuda", log=None, dims=None):
+                    device: str = "cuda", log=None, dims=None, soar=None):
     """Train an IVF-PQ index over X (float32 [n, d], host). Returns the same
     dict layout as the host trainer; `codes` and `list_ids` stay on the GPU
     (torch tensors), everything else is numpy. dims: kept columns of a
     component filtration; the index is built over X[:, dims] with m scaled
-    to keep d', and carries "dims" and "d_base"."""
+    to keep d', and carries "dims" and "d_base". soar: weight lam of a SOAR
+    spilled assignment (section 4.6.2): every row also goes to its spill list
+    (ivf_assign_spill), codes are per list entry and "copies" is 2."""
     import torch
     if dims is not None:
         dims = np.asarray(dims, dtype=np.int64)
         mf = m * len(dims) // X.shape[1]
         index = train_index_gpu(np.ascontiguousarray(X[:, dims]), L, mf, metric, seed, iters,
-                                pq_iters, train_per_list, pq_train, coarse, widen, device, log)
+                                pq_iters, train_per_list, pq_train, coarse, widen, device, log,
+                                soar=soar)
         index.update(dims=dims, d_base=X.shape[1])
         return index
 
@@ -137,6 +140,25 @@ def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
     cmd = torch.from_numpy(cm).to(device)
     cbd = torch.from_numpy(codebooks).to(device)
     codes = encode_codes(Xd, cmd, assign_d, cbd)
+
+    if soar is not None:
+        if log:
+            log(f"SOAR spill lists (lambda {soar})")
+        spill_d = assign_spill(cmd, Xd, assign_d, soar)
+        codes_s = encode_codes(Xd, cmd, spill_d, cbd)
+        spill = spill_d.cpu().numpy().astype(np.int64)
+        ent_list = np.concatenate([assign, spill])
+        ent_id = np.concatenate([np.arange(n), np.arange(n)])
+        order = np.lexsort((ent_id, ent_list))
+        offsets = np.zeros(L + 1, dtype=np.int64)
+        offsets[1:] = np.cumsum(np.bincount(ent_list, minlength=L))
+        order_d = torch.from_numpy(order).to(device)
+        return dict(cm=cm, cp=cp, codebooks=codebooks,
+                    codes=torch.cat([codes, codes_s])[order_d].contiguous(),
+                    list_offsets=offsets,
+                    list_ids=torch.from_numpy(ent_id[order].astype(np.int32)).to(device),
+                    metric=metric, assign=assign, spill=spill, copies=2,
+                    soar_lambda=float(soar))
 
     order = np.argsort(assign, kind="stable")
     offsets = np.zeros(L + 1, dtype=np.int64)

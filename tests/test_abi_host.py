@@ -174,3 +174,36 @@ def test_invalid_opts_rejected(field, value):
     # Workspace sizing validates the options before the index handle.
     assert lib.ivf_search_workspace_bytes(None, 1, 1, 1, 1, ctypes.byref(o)) == 0
     assert "opts." in ivf.last_error()
+
+
+def test_spilled_descriptor_validated():
+    ivf, lib = _lib()
+    # Two copies per point: up to 2n entries, a numbering scratch section.
+    offs = np.linspace(0, 2000, 9).astype(np.int64)
+    desc, _ = _desc(ivf, n=1000, offsets=offs)
+    assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0       # 2n entries need copies = 2
+    desc.copies = 2
+    two = lib.ivf_tables_bytes(ctypes.byref(desc))
+    assert two > 0
+    one_desc, _ = _desc(ivf, n=1000, offsets=np.linspace(0, 1000, 9).astype(np.int64))
+    assert lib.ivf_tables_bytes(ctypes.byref(one_desc)) < two
+    for bad in (-1, 5):
+        desc.copies = bad
+        assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
+        assert "copies" in ivf.last_error()
+    desc, _ = _desc(ivf, n=1 << 30, offsets=np.linspace(0, 1000, 9).astype(np.int64))
+    desc.copies = 2                                              # n * copies >= 2^31 - 1
+    assert lib.ivf_tables_bytes(ctypes.byref(desc)) == 0
+
+
+def test_assign_spill_arguments_validated():
+    ivf, lib = _lib()
+    assert lib.ivf_assign_spill_workspace_bytes(1, 8, 100) == 0  # needs a second list
+    assert lib.ivf_assign_spill_workspace_bytes(16, 8, 0) == 0
+    assert lib.ivf_assign_spill_workspace_bytes(16, 8, 100) > 0
+    fake = 0x10000
+    for lam in (float("nan"), -1.0, float("inf")):
+        st = lib.ivf_assign_spill(fake, 16, 8, fake, 10, fake, lam, 10, fake, 1 << 20, fake, None)
+        assert st == ivf.IVF_ERR_INVALID_ARG and "lam" in ivf.last_error()
+    st = lib.ivf_assign_spill(fake, 16, 8, fake, 0, fake, 1.0, 10, fake, 1 << 20, fake, None)
+    assert st == ivf.IVF_OK                                      # nothing to do

@@ -604,3 +604,205 @@ def test_autotuner_picks_measured_schedule_and_caches(tmp_path):
     b = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
     if ivf.opts_dict(opts)["coarse"] == "exact":
         assert torch.equal(a[0], b[0])
+
+
+# ---------------------------------------------------------------------------
+# Spilled assignment (section 4.6.2, SOAR): two copies per point, the pool
+# keeps each point once at its best copy.
+# ---------------------------------------------------------------------------
+
+SPILL_BASE = {"c2x": "c2s", "c3x": "c3s"}
+
+
+def _spilled_case(name):
+    if name not in _STATE:
+        ivf = _gpu()
+        from workloads import spill_index
+        cfg, X, Q, nprobe, index, _, _ = case(SPILL_BASE[name])
+        sp = spill_index(X, index, 1.0)
+        print(f"[case {name}] spilled {SPILL_BASE[name]}: entries={len(sp['list_ids'])} "
+              f"n={len(X)} R={cfg.R} pool={2 * cfg.R}", flush=True)
+        g = ivf.GpuIndex.from_index(sp, X, base_dtype=cfg.base_dtype)
+        res = oracle_stages(sp, X, Q, nprobe, cfg.k, cfg.R)
+        _STATE[name] = (cfg, X, Q, nprobe, sp, g, res)
+    return _STATE[name]
+
+
+@pytest.mark.parametrize("name", list(SPILL_BASE))
+def test_spilled_tables(name):
+    cfg, X, Q, nprobe, sp, g, res = _spilled_case(name)
+    lay = g.layout()
+    tables = g.tables.cpu().numpy()
+    codes, slot, pad = unpack_tables(tables, lay, cfg.m)
+    boff = tables[lay.block_offsets:lay.block_offsets + (cfg.L + 1) * 4].view(np.int32)
+    off, lid = sp["list_offsets"], sp["list_ids"]
+    seen = {}
+    for l in range(cfg.L):
+        n_l = off[l + 1] - off[l]
+        s0 = boff[l] * 64
+        v = slot[s0:s0 + n_l]
+        assert np.array_equal(v // 2, lid[off[l]:off[l + 1]])
+        assert np.array_equal(codes[s0:s0 + n_l], sp["codes"][off[l]:off[l + 1]])
+        for sl, val in zip(range(s0, s0 + n_l), v.tolist()):
+            seen.setdefault(val // 2, []).append((sl, val % 2))
+    # Each point: two slots numbered 0 then 1 in slot order.
+    assert len(seen) == len(X)
+    for i, ent in seen.items():
+        assert [c for _, c in sorted(ent)] == [0, 1], i
+
+
+@pytest.mark.parametrize("form,rounds", [("plain", 0), ("batched", 1), ("batched", 3)])
+@pytest.mark.parametrize("name", list(SPILL_BASE))
+def test_spilled_candidates_bit_exact(name, form, rounds):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, sp, g, res = _spilled_case(name)
+    P = probes_tensor(res, nprobe)
+    keys = g.debug_candidates(Q, P, nprobe, cfg.R,
+                              opts=ivf.make_opts(form=form, rounds=rounds)).cpu().numpy()
+    a, ids = ivf.decode_keys(keys)
+    assert np.array_equal(ids, res["cand_id"])
+    assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+    for row in ids:
+        v = row[row >= 0]
+        assert len(np.unique(v)) == len(v)
+    assert g.device_error() == 0
+
+
+@pytest.mark.parametrize("name", list(SPILL_BASE))
+def test_spilled_search(name):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, sp, g, res = _spilled_case(name)
+    ip, dp = g.search(Q, nprobe, cfg.k, cfg.R)
+    check_final(ip.cpu().numpy(), dp.cpu().numpy(), res, X, Q, cfg.metric,
+                exact_ids=(cfg.dist == "int255"))
+    for opts in (ivf.make_opts(form="batched"), ivf.make_opts(form="batched", rounds=3),
+                 ivf.make_opts(form="plain", pool_cap=256)):
+        ib, db = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+        assert torch.equal(ib, ip) and torch.equal(db.view(torch.int32), dp.view(torch.int32))
+    # Adaptive re-rank size on the de-duplicated pool.
+    ad = dict(nprobe_init=4, nprobe_min=2, reorder_min=cfg.R // 2, p0=0.3, p1=0.5)
+    ra = oracle.search(sp, X, Q, nprobe, cfg.k, cfg.R, adaptive=ad)
+    ia, da = g.search(Q, nprobe, cfg.k, cfg.R,
+                      opts=ivf.make_opts(form="batched", coarse="exact", adaptive=ad))
+    check_final(ia.cpu().numpy(), da.cpu().numpy(), ra, X, Q, cfg.metric,
+                exact_ids=(cfg.dist == "int255"))
+    assert g.device_error() == 0
+
+
+def test_spilled_survivor_overflow_recomputes():
+    # Far list first: a loose first threshold, survivors overflow a 1024-key
+    # buffer and those queries are recomputed; pools equal the plain form's
+    # and the oracle's best-copy pool over the same lists.
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, sp, g, _ = _spilled_case("c2x")
+    nq = 6
+    rows = []
+    for q in Q[:nq]:
+        s = oracle.coarse_scores(q, sp["cp"], cfg.metric)
+        order = oracle.select_probes(s, cfg.L)
+        rows.append(np.concatenate(([order[-1]], order[:20])))
+    P = torch.from_numpy(np.stack(rows).astype(np.int32))
+    npb = np.full(nq, P.shape[1], dtype=np.int32)
+    kp = g.debug_candidates(Q[:nq], P, npb, cfg.R).cpu().numpy()
+    for rounds in (1, 3):
+        kb = g.debug_candidates(Q[:nq], P, npb, cfg.R,
+                                opts=ivf.make_opts(form="batched", rounds=rounds,
+                                                   spill_cap=1024)).cpu().numpy()
+        assert np.array_equal(kp, kb), rounds
+    off, lid = sp["list_offsets"], sp["list_ids"]
+    for qi, r in enumerate(rows):
+        all_a, all_i = [], []
+        for l in r:
+            T = oracle.lut_float(Q[qi], sp["cm"][l], sp["codebooks"], cfg.metric)
+            q8, lo, d, B = oracle.quantize_lut(T, oracle.list_bias(Q[qi], sp["cm"][l], cfg.metric))
+            all_a.append(oracle.scan_list(q8, d, B, sp["codes"][off[l]:off[l + 1]])[1])
+            all_i.append(lid[off[l]:off[l + 1]].astype(np.int64))
+        ca, ci = oracle.top_r_unique(np.concatenate(all_a), np.concatenate(all_i), cfg.R)
+        a, ids = ivf.decode_keys(kp[qi])
+        assert np.array_equal(ids[:len(ci)], ci)
+        assert np.array_equal(a[:len(ca)].view(np.uint32), ca.view(np.uint32))
+
+
+def test_spilled_index_rejections():
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, sp, g, _ = _spilled_case("c2x")
+    # rerank * copies above 2048.
+    with pytest.raises(ivf.IvfError):
+        g.search(Q[:2], 4, 10, 1500)
+    # A point in three lists with copies = 2, and an id outside [0, n).
+    off, lid = sp["list_offsets"], sp["list_ids"].copy()
+    for bad_id, what in ((int(lid[off[1]]), "three lists"), (len(X), "out of range")):
+        l = 0
+        ids0 = lid[off[l]:off[l + 1]]
+        if bad_id in ids0.tolist():
+            l = 2
+            ids0 = lid[off[l]:off[l + 1]]
+        new0 = np.sort(np.concatenate([ids0, [bad_id]])).astype(np.int32)
+        pos = int(np.searchsorted(new0, bad_id))
+        lid2 = np.concatenate([lid[:off[l]], new0, lid[off[l + 1]:]])
+        codes2 = np.insert(sp["codes"], off[l] + pos, sp["codes"][off[l]], axis=0)
+        off2 = off.copy()
+        off2[l + 1:] += 1
+        with pytest.raises(ivf.IvfError):
+            ivf.GpuIndex(X, sp["cm"], sp["codebooks"], codes2, off2, lid2, cfg.metric,
+                         probe_centroids=sp["cp"], copies=2)
+
+
+@pytest.mark.parametrize("name", ["c2s", "c3s"])
+def test_gpu_spill_assignment(name):
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    rows = X[:3000]
+    prim = np.empty(len(X), np.int64)
+    prim[index["list_ids"]] = np.repeat(np.arange(cfg.L), np.diff(index["list_offsets"]))
+    prim = prim[:3000]
+    Xd = torch.from_numpy(np.ascontiguousarray(rows)).cuda()
+    cmd = torch.from_numpy(index["cm"]).cuda()
+    pd = torch.from_numpy(prim.astype(np.int32)).cuda()
+    C64 = index["cm"].astype(np.float64)
+    for lam in (0.0, 1.0, 2.5):
+        want = oracle.spill_assign(rows, index["cm"], prim, lam)
+        got = ivf.assign_spill(cmd, Xd, pd, lam, chunk=1111).cpu().numpy()
+        assert (got != prim).all()
+        assert (got == want).mean() >= 0.99, lam
+        for i in np.nonzero(got != want)[0]:
+            x = rows[i].astype(np.float64)
+            r = x - C64[prim[i]]
+
+            def loss(l):
+                dv = x - C64[l]
+                return dv @ dv + lam * (dv @ r) ** 2 / (r @ r)
+            assert loss(got[i]) <= loss(want[i]) * (1 + 1e-5) + 1e-6, (lam, i)
+    bad = pd.clone()
+    bad[5] = cfg.L
+    bad[9] = -3
+    got = ivf.assign_spill(cmd, Xd, bad, 1.0).cpu().numpy()
+    assert got[5] == -1 and got[9] == -1 and (got[:5] >= 0).all()
+
+
+def test_gpu_trained_spilled_index():
+    import paper_2511_03298_amd as ivf
+    from paper_2511_03298_amd.train import train_index_gpu
+    from workloads import exact_knn, recall_at_k
+    cfg, X, Q, nprobe, index, _, _ = case("c3s")
+    tr = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=1)
+    sp = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=1, soar=1.0)
+    assert sp["copies"] == 2 and len(sp["list_ids"]) == 2 * len(X)
+    lid = sp["list_ids"].cpu().numpy()
+    assert np.array_equal(np.bincount(lid, minlength=len(X)), np.full(len(X), 2))
+    assert (sp["spill"] != sp["assign"]).all()
+    gt, _ = exact_knn(X, Q, cfg.k, cfg.metric)
+    g1 = ivf.GpuIndex.from_index(tr, X)
+    g2 = ivf.GpuIndex.from_index(sp, X)
+    r1 = recall_at_k(g1.search(Q, 4, cfg.k, cfg.R)[0].cpu().numpy(), gt, cfg.k)
+    r2 = recall_at_k(g2.search(Q, 4, cfg.k, cfg.R)[0].cpu().numpy(), gt, cfg.k)
+    print(f"[spilled] recall@{cfg.k} nprobe 4: one copy {r1:.3f}, two copies {r2:.3f}", flush=True)
+    assert r2 >= r1 - 0.02
+    # The GPU-trained spilled index against the oracle on a few queries.
+    spn = dict(sp, codes=sp["codes"].cpu().numpy(), list_ids=lid)
+    res = oracle_stages(spn, X, Q[:8], 6, cfg.k, cfg.R)
+    keys = g2.debug_candidates(Q[:8], probes_tensor(res, np.full(8, 6)), np.full(8, 6, np.int32),
+                               cfg.R).cpu().numpy()
+    a, ids = ivf.decode_keys(keys)
+    assert np.array_equal(ids, res["cand_id"])
+    assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
