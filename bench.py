@@ -26,7 +26,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from workloads import CONFIGS, exact_knn, make_workload, recall_at_k, train_index  # noqa: E402
+from workloads import (CONFIGS, exact_knn, make_workload, recall_at_k, spill_index,  # noqa: E402
+                       train_index)
 
 METRIC_NAME = "QPS at recall@10=0.90, 1 GPU: plain vs BF16+batched; ADC-scan HBM GB/s"
 HBM_PEAK_GBS = 8000.0
@@ -220,6 +221,10 @@ def main():
                          "components that are 0 or within one standard deviation of the mean "
                          "exceeds THRESHOLD; the index is built over the kept dims (m scaled to "
                          "keep d'), the re-rank uses the full rows")
+    ap.add_argument("--soar", type=float, default=None, metavar="LAMBDA",
+                    help="spilled assignment (section 4.6.2, SOAR): every point also goes to the "
+                         "list minimising SOAR's loss with weight LAMBDA; the pool keeps each "
+                         "point once")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure static nprobe values and adaptive (Eq. 2) settings with "
                          "the batched BF16 form; adds a 'sweep' list to the JSON line")
@@ -249,9 +254,16 @@ def main():
         # 10M-point shapes: assignment and encoding on the GPU (ivf_assign /
         # ivf_encode); the host trainer would take many minutes.
         from paper_2511_03298_amd.train import train_index_gpu
-        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index, log=log, dims=dims)
+        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index, log=log, dims=dims,
+                                soar=args.soar)
     else:
         index = train_index(X, cfg, dims=dims)
+        if args.soar is not None:
+            if dims is not None:
+                raise SystemExit("--soar with --filter needs the GPU trainer")
+            log(f"SOAR spill lists (lambda {args.soar})")
+            index = spill_index(X, index, args.soar)
+    copies = int(index.get("copies", 1))
     if dims is not None:
         cfg = dataclasses.replace(cfg, m=int(index["codebooks"].shape[0]))
     lens = np.diff(index["list_offsets"])
@@ -293,12 +305,12 @@ def main():
     scanned = int(lens[probes[probes >= 0]].sum())
     code_bytes = (cfg.m + 1) // 2
     # The batched scan kernel covers the lists after each query's first ones
-    # holding >= R points (those go through the first-list pass).
+    # holding >= R * copies entries (those go through the first-list pass).
     scanned_main = 0
     for row in probes:
         row = row[row >= 0]
         seen, p = 0, 0
-        while p < len(row) and seen < cfg.R:
+        while p < len(row) and seen < cfg.R * copies:
             seen += int(lens[row[p]])
             p += 1
         scanned_main += int(lens[row[p:]].sum())
@@ -370,6 +382,7 @@ def main():
                    "d": cfg.d, "nq": cfg.nq, "L": cfg.L, "m": cfg.m, "nprobe": list(cfg.nprobe),
                    "k": cfg.k, "rerank": cfg.R, "form": best["form"], "coarse": best["coarse"],
                    "filter": args.filter, "dims_kept": None if dims is None else int(len(dims)),
+                   "soar_lambda": args.soar, "copies": copies,
                    "schedule": best["opts"]},
         "recall_at_10": round(best["recall_at_10"], 4),
         "forms": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()

@@ -292,7 +292,7 @@ int32_t ivf_get_device_error(const ivf_index* idx, void* workspace,
  * (IVF_STAGE_*): coarse scoring, probe selection, scan preparation (IP
  * biases; batched form: first-list pass and each round's work-list build),
  * the scan kernel itself (batched: every round's), the merges (batched
- * form), the re-rank. ivf_profile_read waits for the last recorded event and
+ * form; a spilled index's per-point pool reduction), the re-rank. ivf_profile_read waits for the last recorded event and
  * returns, per stage, the summed milliseconds and the number of completed
  * searches since the previous read (then resets). At most 64 searches are
  * kept between reads (older ones are dropped). Graph replays
