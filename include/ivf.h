@@ -49,7 +49,9 @@ typedef enum {
 } ivf_status;
 
 typedef enum { IVF_METRIC_L2 = 0, IVF_METRIC_IP = 1 } ivf_metric;
-typedef enum { IVF_DTYPE_F32 = 0, IVF_DTYPE_BF16 = 1 } ivf_dtype;
+/* Raw-row storage for the re-rank. BF16 and U8 (byte vectors such as SIFT /
+ * BIGANN) are widened to FP32 exactly; the distances are then FP32 sums. */
+typedef enum { IVF_DTYPE_F32 = 0, IVF_DTYPE_BF16 = 1, IVF_DTYPE_U8 = 2 } ivf_dtype;
 
 /* A trained IVF + residual-PQ index (Alg. 1 outputs), K = 16 codewords per
  * subspace (4-bit codes). Sizes: 1 <= d, 1 <= m <= 256, d % m == 0,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG_DIR, "libivfpq.so")
 IVF_OK, IVF_ERR_INVALID_ARG, IVF_ERR_DEVICE, IVF_ERR_WORKSPACE = 0, 1, 2, 3
 IVF_ERR_UNSUPPORTED, IVF_ERR_INTERNAL = 4, 5
 METRIC = {"l2": 0, "ip": 1}
-DTYPE = {"f32": 0, "bf16": 1}
+DTYPE = {"f32": 0, "bf16": 1, "u8": 2}
 COARSE = {"exact": 0, "f32": 1, "bf16": 2, "fp8": 3}
 FORM = {"plain": 0, "batched": 1}
 
@@ -189,6 +189,14 @@ class GpuIndex:
 
         if base_dtype == "bf16":
             self.base = dev(base, torch.bfloat16)
+        elif base_dtype == "u8":
+            # Byte vectors: the rows must be integers in [0, 255] (stored exactly).
+            b = base if isinstance(base, torch.Tensor) else torch.from_numpy(np.asarray(base))
+            if b.dtype != torch.uint8:
+                bf = b.to(torch.float32)
+                if not bool(((bf >= 0) & (bf <= 255) & (bf == torch.round(bf))).all()):
+                    raise ValueError("base_dtype 'u8' needs integer components in [0, 255]")
+            self.base = dev(b, torch.uint8)
         else:
             self.base = dev(base, torch.float32)
         self.centroids = dev(centroids, torch.float32)

@@ -75,7 +75,8 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
   if (d->m < 1 || d->m > MAX_M) return "m must be in [1, 256]";
   if (d->d % d->m != 0) return "d must be a multiple of m";
   if (d->metric != IVF_METRIC_L2 && d->metric != IVF_METRIC_IP) return "unknown metric";
-  if (d->base_dtype != IVF_DTYPE_F32 && d->base_dtype != IVF_DTYPE_BF16)
+  if (d->base_dtype != IVF_DTYPE_F32 && d->base_dtype != IVF_DTYPE_BF16 &&
+      d->base_dtype != IVF_DTYPE_U8)
     return "unknown base dtype";
   if (!d->base || !d->centroids || !d->codebooks || !d->codes || !d->list_offsets ||
       !d->list_ids)

@@ -1,7 +1,7 @@
 // Step 5 of the search (Alg. 2, final step): exact distances between the
-// query and its candidate rows, FP32 accumulation (BF16 rows are widened
-// exactly), and the top k by (distance, id): ascending squared L2, or
-// descending inner product.
+// query and its candidate rows, FP32 accumulation (BF16 and U8 rows are
+// widened exactly), and the top k by (distance, id): ascending squared L2,
+// or descending inner product.
 #include "common.hpp"
 #include "internal.hpp"
 #include "rank_sort.hpp"
@@ -13,15 +13,29 @@ __device__ __forceinline__ float load_base(const Tables& t, int64_t row, int c) 
     const uint16_t* b = reinterpret_cast<const uint16_t*>(t.base);
     return __uint_as_float((uint32_t)b[row * t.d_base + c] << 16);
   }
+  if (t.base_dtype == IVF_DTYPE_U8)
+    return (float)reinterpret_cast<const uint8_t*>(t.base)[row * t.d_base + c];
   return reinterpret_cast<const float*>(t.base)[row * t.d_base + c];
 }
 
-// Sum over one 16-byte vector of the row: 4 FP32 values, or 8 BF16 values
-// widened exactly, in element order.
+// Sum over one 16-byte vector of the row: 4 FP32 values, or 8 BF16 / 16 U8
+// values widened exactly, in element order.
 __device__ __forceinline__ float vec_term(const float* qv, const uint4& x, int e0, bool ip,
-                                          bool bf16) {
+                                          int dtype) {
   float acc = 0.0f;
-  if (bf16) {
+  if (dtype == IVF_DTYPE_U8) {
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int h = 0; h < 16; ++h) {
+      const float v = (float)((w[h >> 2] >> (8 * (h & 3))) & 0xffu);
+      if (ip) {
+        acc = acc + qv[e0 + h] * v;
+      } else {
+        const float df = qv[e0 + h] - v;
+        acc = acc + df * df;
+      }
+    }
+  } else if (dtype == IVF_DTYPE_BF16) {
     const uint32_t w[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
     for (int h = 0; h < 8; ++h) {
@@ -68,7 +82,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   const int q = blockIdx.x;
   const int tid = threadIdx.x;
   const bool ip = t.metric == IVF_METRIC_IP;
-  const bool bf16 = t.base_dtype == IVF_DTYPE_BF16;
+  const int dtype = t.base_dtype;
   if (nprobe_eff[q] < 0) {  // invalid request row
     for (int i = tid; i < k; i += blockDim.x) {
       out_ids[(size_t)q * k + i] = -1;
@@ -93,8 +107,9 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
   constexpr int G = 8;
   constexpr int GROUPS = IVF_BLOCK / G;
   const int g = tid / G, gl = tid % G;
-  const int per_vec = bf16 ? 8 : 4;                       // elements per 16 bytes
-  const size_t row_bytes = (size_t)t.d_base * (bf16 ? 2 : 4);
+  const int esize = dtype == IVF_DTYPE_U8 ? 1 : dtype == IVF_DTYPE_BF16 ? 2 : 4;
+  const int per_vec = 16 / esize;                         // elements per 16 bytes
+  const size_t row_bytes = (size_t)t.d_base * esize;
   const bool vec = row_bytes % 16 == 0;
   const int nvec = t.d_base / per_vec;
   const unsigned char* base = reinterpret_cast<const unsigned char*>(t.base);
@@ -119,7 +134,7 @@ __global__ void __launch_bounds__(256) rerank_kernel(Tables t, const float* __re
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (key[u] != KEY_NONE) acc[u] = acc[u] + vec_term(qv, x[u], v0 * per_vec, ip, bf16);
+          if (key[u] != KEY_NONE) acc[u] = acc[u] + vec_term(qv, x[u], v0 * per_vec, ip, dtype);
       }
     } else {
       for (int i = gl; i < t.d_base; i += G) {

@@ -207,3 +207,13 @@ def test_assign_spill_arguments_validated():
         assert st == ivf.IVF_ERR_INVALID_ARG and "lam" in ivf.last_error()
     st = lib.ivf_assign_spill(fake, 16, 8, fake, 0, fake, 1.0, 10, fake, 1 << 20, fake, None)
     assert st == ivf.IVF_OK                                      # nothing to do
+
+
+def test_u8_rows_must_be_bytes():
+    ivf, lib = _lib()
+    X = np.array([[0.0, 1.0], [2.5, 3.0]], np.float32)
+    for bad in (X, X - 3.0, X * 200.0):
+        with pytest.raises(ValueError):
+            ivf.GpuIndex(bad, np.zeros((1, 2), np.float32), np.zeros((1, 16, 2), np.float32),
+                         np.zeros((2, 1), np.uint8), [0, 2], [0, 1], "l2", base_dtype="u8",
+                         device="cpu")

@@ -124,6 +124,20 @@ def test_search_end_to_end(name):
                 exact_ids=(cfg.dist == "int255"))
 
 
+def test_u8_and_f32_rows_rerank_identically():
+    # Byte-valued rows stored as u8 are widened exactly: the same search on
+    # FP32 rows gives bit-identical distances (integer sums stay below 2^24).
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case("c2s")
+    assert cfg.base_dtype == "u8"
+    g32 = ivf.GpuIndex.from_index(index, X, base_dtype="f32")
+    for opts in (ivf.make_opts(), ivf.make_opts(form="batched", coarse="bf16")):
+        i8, d8 = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+        i32, d32 = g32.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+        assert torch.equal(i8, i32) and torch.equal(d8.view(torch.int32), d32.view(torch.int32))
+    check_final(i8.cpu().numpy(), d8.cpu().numpy(), res, X, Q, cfg.metric, exact_ids=True)
+
+
 @pytest.mark.parametrize("name", ["c1", "c3s"])
 def test_repeat_runs_bit_identical(name):
     cfg, X, Q, nprobe, index, g, res = case(name)

@@ -43,7 +43,7 @@ class WorkloadConfig:
     nprobe: Tuple[int, int]  # per-query nprobe drawn uniformly from [lo, hi]
     k: int
     R: int                # re-rank candidates ("reorder")
-    base_dtype: str = "f32"   # "f32" or "bf16" (rows stored as bfloat16)
+    base_dtype: str = "f32"   # "f32", "bf16" (rows stored as bfloat16) or "u8" (byte vectors)
     sigma: float = 0.1
     zipf: float = 0.0     # >0: component weights proportional to rank^-zipf
     background: int = 0   # last dims that are almost always 0 (image-background-like)
@@ -59,7 +59,7 @@ CONFIGS = {
                          (8, 8), 10, 100, sigma=0.1),
     # SIFT/BIGANN-like: integer components in [0,255], 1000 components.
     "c2": WorkloadConfig("c2", 2, 1_000_000, 128, "l2", "int255", 1000, 10_000,
-                         1024, 64, (32, 32), 10, 200, sigma=16.0),
+                         1024, 64, (32, 32), 10, 200, base_dtype="u8", sigma=16.0),
     # GloVe-like angular data with Zipf(1.1) cluster sizes; per-query nprobe.
     "c3": WorkloadConfig("c3", 3, 1_200_000, 100, "ip", "sphere", 2000, 10_000,
                          2000, 50, (8, 128), 10, 200, sigma=0.6, zipf=1.1),
@@ -74,7 +74,8 @@ CONFIGS = {
     # mixture in 128 dims plus 128 background dims that are 0 in ~96 % of
     # rows (FASHION-MNIST-like uniform backgrounds).
     "c6": WorkloadConfig("c6", 6, 1_000_000, 256, "l2", "int255", 1000, 10_000,
-                         1024, 128, (32, 32), 10, 200, sigma=16.0, background=128),
+                         1024, 128, (32, 32), 10, 200, base_dtype="u8", sigma=16.0,
+                         background=128),
 }
 
 
