@@ -203,6 +203,45 @@ def sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args):
     return out
 
 
+def batch_sweep(g, cfg, Qd, npd, gt_ids, nrec, args):
+    """Query batches of 1 .. nq, each search captured once into a hipGraph and
+    replayed: milliseconds per batch, QPS and Recall@10 (on the batch's
+    queries that have ground truth), for the plain and batched forms."""
+    import torch
+
+    import paper_2511_03298_amd as ivf
+    out = []
+    stream = torch.cuda.Stream()
+    sizes = [b for b in (1, 16, 128, 1024, 4096) if b <= cfg.nq]
+    if cfg.nq not in sizes:
+        sizes.append(cfg.nq)
+    for form, coarse in (("plain", "bf16"), ("batched", "bf16")):
+        opts = ivf.make_opts(form=form, coarse=coarse, use_graph=True)
+        for b in sizes:
+            q, npb = Qd[:b], npd[:b]
+            max_np = int(npb.max())
+            ids = torch.empty((b, cfg.k), dtype=torch.int64, device="cuda")
+            dist = torch.empty((b, cfg.k), dtype=torch.float32, device="cuda")
+            reps = max(5, min(200, int(2e4 // max(b, 1))))
+            with torch.cuda.stream(stream):
+                for _ in range(3):
+                    g.search(q, npb, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
+                stream.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    g.search(q, npb, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
+                stream.synchronize()
+            ms = (time.perf_counter() - t0) * 1000.0 / reps
+            nr = min(b, nrec)
+            rec = recall_at_k(ids[:nr].cpu().numpy(), gt_ids[:nr], 10)
+            r = dict(form=form, coarse=coarse, batch=b, ms_per_batch=round(ms, 4),
+                     qps=round(b / (ms / 1e3), 1), recall_at_10=round(rec, 4))
+            log(f"batch {b} {form}/{coarse} (graph): {ms:.3f} ms, {r['qps']:.0f} q/s, "
+                f"recall@10 {rec:.4f}")
+            out.append(r)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,9 +264,15 @@ def main():
                     help="spilled assignment (section 4.6.2, SOAR): every point also goes to the "
                          "list minimising SOAR's loss with weight LAMBDA; the pool keeps each "
                          "point once")
+    ap.add_argument("--base-dtype", default=None, choices=("f32", "bf16", "u8"),
+                    help="storage of the raw rows for the exact re-rank (default: the "
+                         "workload's); u8 needs integer components in [0, 255]")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure static nprobe values and adaptive (Eq. 2) settings with "
                          "the batched BF16 form; adds a 'sweep' list to the JSON line")
+    ap.add_argument("--batch-sweep", action="store_true",
+                    help="also time graph-captured searches of query batches of 1 .. nq "
+                         "(plain and batched forms); adds a 'batches' list to the JSON line")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB before timing (a kernel of "
                          "known traffic for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -239,6 +284,8 @@ def main():
         sys.exit(2)
 
     cfg = CONFIGS[args.config]
+    if args.base_dtype:
+        cfg = dataclasses.replace(cfg, base_dtype=args.base_dtype)
     t0 = time.time()
     log(f"generating {args.config}: n={cfg.n} d={cfg.d} nq={cfg.nq}")
     X, Q, nprobe = make_workload(cfg, log=log)
@@ -382,7 +429,7 @@ def main():
                    "d": cfg.d, "nq": cfg.nq, "L": cfg.L, "m": cfg.m, "nprobe": list(cfg.nprobe),
                    "k": cfg.k, "rerank": cfg.R, "form": best["form"], "coarse": best["coarse"],
                    "filter": args.filter, "dims_kept": None if dims is None else int(len(dims)),
-                   "soar_lambda": args.soar, "copies": copies,
+                   "soar_lambda": args.soar, "copies": copies, "base_dtype": cfg.base_dtype,
                    "schedule": best["opts"]},
         "recall_at_10": round(best["recall_at_10"], 4),
         "forms": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()
@@ -395,6 +442,8 @@ def main():
     }
     if args.sweep:
         line["sweep"] = sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args)
+    if args.batch_sweep:
+        line["batches"] = batch_sweep(g, cfg, Qd, npd, gt_ids, nrec, args)
     print(json.dumps(line), flush=True)
 
 

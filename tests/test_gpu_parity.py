@@ -129,11 +129,11 @@ def test_u8_and_f32_rows_rerank_identically():
     # FP32 rows gives bit-identical distances (integer sums stay below 2^24).
     import paper_2511_03298_amd as ivf
     cfg, X, Q, nprobe, index, g, res = case("c2s")
-    assert cfg.base_dtype == "u8"
-    g32 = ivf.GpuIndex.from_index(index, X, base_dtype="f32")
+    assert cfg.dist == "int255" and cfg.base_dtype == "f32"
+    g8 = ivf.GpuIndex.from_index(index, X, base_dtype="u8")
     for opts in (ivf.make_opts(), ivf.make_opts(form="batched", coarse="bf16")):
-        i8, d8 = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
-        i32, d32 = g32.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+        i8, d8 = g8.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+        i32, d32 = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
         assert torch.equal(i8, i32) and torch.equal(d8.view(torch.int32), d32.view(torch.int32))
     check_final(i8.cpu().numpy(), d8.cpu().numpy(), res, X, Q, cfg.metric, exact_ids=True)
 

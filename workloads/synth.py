@@ -59,7 +59,7 @@ CONFIGS = {
                          (8, 8), 10, 100, sigma=0.1),
     # SIFT/BIGANN-like: integer components in [0,255], 1000 components.
     "c2": WorkloadConfig("c2", 2, 1_000_000, 128, "l2", "int255", 1000, 10_000,
-                         1024, 64, (32, 32), 10, 200, base_dtype="u8", sigma=16.0),
+                         1024, 64, (32, 32), 10, 200, sigma=16.0),
     # GloVe-like angular data with Zipf(1.1) cluster sizes; per-query nprobe.
     "c3": WorkloadConfig("c3", 3, 1_200_000, 100, "ip", "sphere", 2000, 10_000,
                          2000, 50, (8, 128), 10, 200, sigma=0.6, zipf=1.1),
