@@ -328,6 +328,77 @@ __device__ __forceinline__ void wave_build_lut_lanes(const Tables& t, const floa
   }
 }
 
+// The same build for 64 < m_pad <= 128 with two subspaces per lane (j and
+// j + 64) and the item's half count as a parameter. The pairwise sum of lo
+// is the canonical tree over 128 leaves: its top level adds the halves
+// 0..63 and 64..127, each the butterfly of one lane-resident value.
+template <int W, int HALVES>
+__device__ __forceinline__ void wave_build_lut_lanes2(const Tables& t, const float* qg,
+                                                      const float* cl, const float* cbT, int g,
+                                                      uint16_t* lut16, float* outB,
+                                                      float* outDelta) {
+  constexpr int MP = W * 8;
+  static_assert(MP > IVF_WAVE && MP <= 2 * IVF_WAVE, "two subspaces per lane");
+  const int ln = lane_id();
+  const int ds = t.dsub;
+  float T[2][KSUB];
+  float lo[2] = {0.0f, 0.0f};
+  float mx = 0.0f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = ln + IVF_WAVE * h;
+#pragma unroll
+    for (int k = 0; k < KSUB; ++k) T[h][k] = 0.0f;
+    if (j < t.m) {
+      for (int u = 0; u < ds; ++u) {
+        const float r = qg[j * ds + u] - cl[j * ds + u];
+#pragma unroll
+        for (int k = 0; k < KSUB; ++k) {
+          const int code = (k + j) & 15;
+          const float df = r - cbT[(code * ds + u) * MP + j];
+          T[h][k] = T[h][k] + df * df;
+        }
+      }
+      float v = T[h][0];
+#pragma unroll
+      for (int k = 1; k < KSUB; ++k) v = fminf(v, T[h][k]);
+      lo[h] = v;
+#pragma unroll
+      for (int k = 0; k < KSUB; ++k) {
+        T[h][k] = T[h][k] - v;  // entry minus its subspace minimum (rounded once)
+        mx = fmaxf(mx, T[h][k]);
+      }
+    }
+  }
+  for (int s = 1; s < IVF_WAVE; s <<= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
+  const float rng = mx;
+  const bool live = rng > 0.0f;
+  const float sc = live ? 255.0f / rng : 0.0f;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = ln + IVF_WAVE * h;
+    if (j < MP) {
+#pragma unroll
+      for (int k = 0; k < KSUB; ++k) {
+        const int code = (k + j) & 15;
+        uint32_t v = 0;
+        if (live && j < t.m) v = (uint32_t)fminf(rintf(T[h][k] * sc), 255.0f);
+        lut16[((j * HALVES + (g >> 3)) * 16 + code) * 8 + (g & 7)] = (uint16_t)v;
+      }
+    }
+  }
+  float x0 = lo[0], x1 = lo[1];
+  for (int s = 1; s < IVF_WAVE; s <<= 1) {
+    x0 = x0 + __shfl_xor(x0, s);
+    x1 = x1 + __shfl_xor(x1, s);
+  }
+  const float ls = __shfl(x0, 0) + __shfl(x1, 0);
+  if (ln == 0) {
+    *outB = ls + 0.0f;
+    *outDelta = live ? rng / 255.0f : 0.0f;
+  }
+}
+
 // Inner product: the table does not depend on the list (only the bias
 // does), so it is built once per query: one wave per query writes the u8
 // table, the pairwise sum of the subspace minima and delta.
@@ -367,9 +438,10 @@ struct BatchShared {
 // Codebooks are staged in LDS when they fit beside the tables.
 template <int W>
 constexpr bool cb_in_lds() { return W <= 16; }
-// L2 tables are built one lane per subspace when m_pad <= 64.
+// L2 tables are built with one lane per subspace (two when m_pad > 64) when
+// m_pad <= 128.
 template <int W>
-constexpr bool lane_build() { return W * 8 <= IVF_WAVE; }
+constexpr bool lane_build() { return W * 8 <= 2 * IVF_WAVE; }
 
 // PER_QUERY (inner product): the tables come from query_lut_kernel and are
 // only copied per item; otherwise (L2) each item builds its residual tables.
@@ -462,9 +534,11 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       if (g < nqi) {
         const float* qg = Q + (size_t)sh.qid[g] * t.d;
         const float* c = t.cm + (size_t)l * t.d;
-        if constexpr (lane_build<W>()) {
-          static_assert(BG == 16, "the lane builder writes 16-query items");
+        if constexpr (lane_build<W>() && W * 8 <= IVF_WAVE) {
+          static_assert(BG == 16, "the one-lane builder writes 16-query items");
           wave_build_lut_lanes<W>(t, qg, c, cbT, g, sh.lut16, &sh.B[g], &sh.delta[g]);
+        } else if constexpr (lane_build<W>()) {
+          wave_build_lut_lanes2<W, HALVES>(t, qg, c, cbT, g, sh.lut16, &sh.B[g], &sh.delta[g]);
         } else {
           for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
           wave_build_lut<W>(t, rq, cb, 0.0f, ItemStore{sh.lut16, g, HALVES}, sh.lo[wave],

@@ -35,6 +35,10 @@ CASES = {
     "c3s": ("c3", 30_000, 40, 80, 80, dict(nprobe=(8, 32))),
     "c4s": ("c4", 40_000, 20, 64, 64, dict(nprobe=(8, 8))),
     "c5s": ("c5", 12_000, 12, 32, 32, dict(nprobe=(4, 16))),
+    # L2 with 64 < m <= 128: two subspaces per lane in the batched table
+    # build, 8-query items (m = 128) and 16-query items (m = 96).
+    "c6u": ("c6", 20_000, 30, 32, 32, dict(nprobe=(6, 6))),
+    "c2w": ("c2", 20_000, 30, 32, 32, dict(nprobe=(6, 6), d=192, m=96)),
 }
 
 _STATE = {}
@@ -347,7 +351,7 @@ def test_batched_search_identical_to_plain(name):
 
 
 @pytest.mark.parametrize("rounds", [2, 3, 4])
-@pytest.mark.parametrize("name", ["c1", "c3s", "c4s", "c5s"])
+@pytest.mark.parametrize("name", ["c1", "c3s", "c4s", "c5s", "c6u", "c2w"])
 def test_batched_rounds_candidates_bit_exact(name, rounds):
     # Rounds over probe ranks [0,4), [4,16), [16,64), ... tighten the
     # threshold between them; the pool is still the exact R smallest keys.
