@@ -36,18 +36,19 @@ HBM_PEAK_GBS = 8000.0
 LOOKUP_PEAK_T = 256 * 64 * 2.4e9 * 2 / 1e12
 
 # HBM traffic of the dominant scan kernel, from rocprofv3 --pmc FETCH_SIZE
-# and --pmc WRITE_SIZE runs (KiB per dispatch, scaled by the factors a 1 GiB
-# device copy gave: 2.0 and 1.0). Valid only while the kernel source is the
-# one measured (sha256 of the listed files).
+# and --pmc WRITE_SIZE runs (KiB per dispatch, the mean of the timed
+# launches, scaled by the factors a 1 GiB device copy gave: 2.0 and 1.0).
+# Valid only while the kernel source is the one measured (sha256 of the
+# listed files).
 TRAFFIC = {
-    ("c2", "batched"): dict(files=("batched.hip", "common.hpp"), sha="f28d7a5d243fa4af",
-                            fetch_kib=109676.8, write_kib=1727.1),
-    ("c2", "plain"): dict(files=("scan.hip", "common.hpp"), sha="0d81da5cf7e0188b",
-                          fetch_kib=5188205.3, write_kib=15625.0),
-    ("c5", "plain"): dict(files=("scan.hip", "common.hpp"), sha="0d81da5cf7e0188b",
-                          fetch_kib=48323161.8, write_kib=8192.0),
-    ("c5", "batched"): dict(files=("batched.hip", "common.hpp"), sha="e0b5458056e63aa8",
-                            fetch_kib=3828540.5, write_kib=3191.5),
+    ("c2", "batched"): dict(files=("batched.hip", "common.hpp"), sha="e4f7fb9f060a9dcf",
+                            fetch_kib=109117.7, write_kib=1726.8),
+    ("c2", "plain"): dict(files=("scan.hip", "common.hpp"), sha="245a781fa59d5e7d",
+                          fetch_kib=5191013.5, write_kib=15625.0),
+    ("c5", "plain"): dict(files=("scan.hip", "common.hpp"), sha="245a781fa59d5e7d",
+                          fetch_kib=48323178.0, write_kib=8192.0),
+    ("c5", "batched"): dict(files=("batched.hip", "common.hpp"), sha="e4f7fb9f060a9dcf",
+                            fetch_kib=3834007.3, write_kib=3189.3),
 }
 
 

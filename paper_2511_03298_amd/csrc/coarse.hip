@@ -78,21 +78,24 @@ hipError_t launch_coarse_exact(const Tables& t, const float* Q, int32_t nq, floa
 }
 
 // Canonical score of one (query, list) pair, one thread, sequential over t.
-// Rows are fetched four floats at a time when d is a multiple of 4; the
-// accumulation order is the same in both paths.
+// Rows are fetched in 16-byte vectors when d is a multiple of 4, 16 vectors
+// (64 floats) requested before any is used, since the rows come from the
+// caches with long latency; the accumulation order is the same in both paths.
 __device__ __forceinline__ float canonical_score(const Tables& t, const float* q, int l) {
   const float* c = t.cp + (size_t)l * t.d;
   const bool ip = t.metric == IVF_METRIC_IP;
   float acc = 0.0f;
   int i = 0;
   if ((t.d & 3) == 0) {
+    constexpr int NV = 16;
     const float4* c4 = reinterpret_cast<const float4*>(c);
-    for (; i < t.d; i += 16) {
-      float4 v[4];
+    for (; i < t.d; i += 4 * NV) {
+      float4 v[NV];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = i + 4 * k < t.d ? c4[(i >> 2) + k] : make_float4(0, 0, 0, 0);
+      for (int k = 0; k < NV; ++k)
+        v[k] = i + 4 * k < t.d ? c4[(i >> 2) + k] : make_float4(0, 0, 0, 0);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < NV; ++k) {
         const float cv[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
