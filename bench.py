@@ -103,7 +103,7 @@ def _cpu_worker(span):
         return time.perf_counter() - t0
 
 
-def cpu_baseline(index, X, Q, nprobe, k, R, seconds_per_worker=1.5):
+def cpu_baseline(index, X, Q, nprobe, k, R, seconds_per_worker=1.0):
     import multiprocessing as mp
 
     import oracle
