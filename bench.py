@@ -120,14 +120,67 @@ def cpu_baseline(index, X, Q, nprobe, k, R, seconds_per_worker=1.0):
         pool.map(_cpu_worker, spans)
         wall = time.perf_counter() - t0
     total = workers * per_worker
+    model = "unknown CPU"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(total / wall, 1), "unit": "queries/s", "cores": workers,
             "kind": "oracle",
             "sample": f"{total} queries ({per_worker} per worker process, one process per core, "
                       f"single-threaded numpy), same index, nprobe, k and rerank; "
-                      f"wall {wall:.1f} s"}
+                      f"wall {wall:.1f} s; {model}"}
 
 
 # ---------------------------------------------------------------------------
+
+
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+OPERAND_BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
+
+
+def coarse_mfma(cfg, r):
+    """MFMA use of the coarse product for an MFMA coarse form: 2 nq L d FLOP
+    per step over the coarse stage (operand conversion + MFMA kernel). Its
+    roofline is the smaller of the MFMA peak and HBM bandwidth times the
+    arithmetic intensity, since the kernel writes the full FP32 score matrix
+    (4 nq L bytes) and reads the operands."""
+    if r["coarse"] not in MFMA_PEAK_TFLOPS or not r["stage_ms"].get("coarse"):
+        return None
+    flop = 2.0 * cfg.nq * cfg.L * cfg.d
+    nbytes = 4.0 * cfg.nq * cfg.L + OPERAND_BYTES[r["coarse"]] * (cfg.nq + cfg.L) * cfg.d
+    tf = flop / (r["stage_ms"]["coarse"] / 1e3) / 1e12
+    mfma_peak = MFMA_PEAK_TFLOPS[r["coarse"]]
+    hbm_cap = HBM_PEAK_GBS * 1e9 * flop / nbytes / 1e12
+    bound = "mfma" if mfma_peak <= hbm_cap else "hbm"
+    peak = min(mfma_peak, hbm_cap)
+    return {"flop_per_step": flop, "bytes_per_step": nbytes, "achieved": round(tf, 2),
+            "mfma_peak": mfma_peak, "bound": bound, "peak": round(peak, 1), "unit": "TFLOP/s",
+            "frac": round(tf / peak, 4), "mfma_frac": round(tf / mfma_peak, 5)}
+
+
+def distance_error(ids, dist, X, Q, metric):
+    """Largest relative error of the returned FP32 distances against FP64
+    recomputed for the same ids (IP: relative to sum |q_t x_t|)."""
+    worst = 0.0
+    X64 = np.asarray(X)
+    for qi in range(len(ids)):
+        v = ids[qi] >= 0
+        rows = X64[ids[qi][v]].astype(np.float64)
+        q = np.asarray(Q[qi], dtype=np.float64)
+        if metric == "l2":
+            e = ((rows - q) ** 2).sum(1)
+            scale = np.abs(e)
+        else:
+            e = rows @ q
+            scale = (np.abs(rows) * np.abs(q)).sum(1)
+        err = np.abs(dist[qi][v].astype(np.float64) - e) / np.maximum(scale, 1e-30)
+        if err.size:
+            worst = max(worst, float(err.max()))
+    return worst
 
 
 def roofline(config, cfg, r, code_bytes):
@@ -397,16 +450,28 @@ def main():
         stage_ms, count = g.profile_read()
         g.profile(False)
         ms_step = wall * 1000.0 / args.steps
-        rec = recall_at_k(ids[:nrec].cpu().numpy(), gt_ids, 10)
+        ids_h, dist_h = ids[:nrec].cpu().numpy(), dist[:nrec].cpu().numpy()
+        rec = recall_at_k(ids_h, gt_ids, 10)
+        derr = distance_error(ids_h, dist_h, X, Q[:nrec], cfg.metric)
+        # Secondary: the same steps with the results copied to the host.
+        t0 = time.perf_counter()
+        for _ in range(max(2, args.steps // 2)):
+            g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
+            ids.cpu(), dist.cpu()
+        d2h_ms = (time.perf_counter() - t0) * 1000.0 / max(2, args.steps // 2)
         per = {k_: v / max(count, 1) for k_, v in stage_ms.items()}
         scan_ms = per["scan"]
         pts = scanned_main if form == "batched" else scanned
         r = dict(form=form, coarse=coarse, schedule=label, opts=od,
                  qps=cfg.nq / (ms_step / 1000.0), ms_per_step=ms_step,
-                 recall_at_10=rec, stage_ms=per, scan_points=pts,
+                 qps_with_d2h=cfg.nq / (d2h_ms / 1000.0),
+                 recall_at_10=rec, max_rel_dist_err=float(f"{derr:.3g}"), stage_ms=per,
+                 scan_points=pts,
                  scan_gbs=pts * code_bytes / (scan_ms / 1e3) / 1e9 if scan_ms > 0 else None,
                  scan_tlookups=pts * cfg.m / (scan_ms / 1e3) / 1e12 if scan_ms > 0 else None)
-        log(f"{label} {form}/{coarse}: {r['qps']:.0f} q/s, {ms_step:.3f} ms/step, recall@10 {rec:.4f}, "
+        log(f"{label} {form}/{coarse}: {r['qps']:.0f} q/s ({r['qps_with_d2h']:.0f} with results "
+            f"copied to the host), {ms_step:.3f} ms/step, recall@10 {rec:.4f}, max rel. distance "
+            f"error {derr:.2e}, "
             f"stages {', '.join(f'{k_} {v:.3f}ms' for k_, v in per.items())}, scan kernel "
             f"{r['scan_gbs']:.0f} GB/s algorithmic, {r['scan_tlookups']:.2f} T lookups/s")
         results.append(r)
@@ -433,12 +498,16 @@ def main():
                    "soar_lambda": args.soar, "copies": copies, "base_dtype": cfg.base_dtype,
                    "schedule": best["opts"]},
         "recall_at_10": round(best["recall_at_10"], 4),
-        "forms": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()
-                   if k_ not in ("stage_ms", "opts")} |
+        "max_rel_dist_err": best["max_rel_dist_err"],
+        "qps_with_d2h": round(best["qps_with_d2h"], 1),
+        "forms": [{k_: (round(v, 4) if isinstance(v, float) and k_ != "max_rel_dist_err" else v)
+                   for k_, v in r.items() if k_ not in ("stage_ms", "opts")} |
                   {"stage_ms": {s: round(x, 4) for s, x in r["stage_ms"].items()},
-                   "roofline": roofline(args.config, cfg, r, code_bytes)}
+                   "roofline": roofline(args.config, cfg, r, code_bytes),
+                   "coarse_mfma": coarse_mfma(cfg, r)}
                   for r in results],
         "roofline": roofline(args.config, cfg, best, code_bytes),
+        "coarse_mfma": coarse_mfma(cfg, best),
         "cpu_baseline": cpu,
     }
     if args.sweep:

@@ -12,8 +12,9 @@
 // Operands are row-major with the contraction dimension contiguous and
 // zero-padded (queries to [nq_pad x d_pad], centroids to [L_pad x d_pad]),
 // so every lane loads its MFMA fragment as one contiguous run straight from
-// global memory. Workgroup tile: 64 queries x 64 lists, one 32x32 output tile
-// per wavefront.
+// global memory; the contraction loop is unrolled (d_pad is a multiple of 64)
+// so several fragments are in flight before their products are issued.
+// Workgroup tile: 64 queries x 64 lists, one 32x32 output tile per wavefront.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -67,23 +68,41 @@ __global__ void __launch_bounds__(256) coarse_mfma_kernel(Tables t, const void* 
   if constexpr (COARSE == IVF_COARSE_F32) {
     const float* a = reinterpret_cast<const float*>(Aop) + (size_t)(q0 + r) * dp + half;
     const float* b = t.cp_f32 + (size_t)(l0 + r) * dp + half;
-    for (int k = 0; k < t.d_pad; k += 2)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[k], b[k], acc, 0, 0, 0);
+    for (int k0 = 0; k0 < t.d_pad; k0 += 16) {
+      float av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        av[u] = a[k0 + 2 * u];
+        bv[u] = b[k0 + 2 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bv[u], acc, 0, 0, 0);
+    }
   } else if constexpr (COARSE == IVF_COARSE_BF16) {
     const uint16_t* a = reinterpret_cast<const uint16_t*>(Aop) + (size_t)(q0 + r) * dp + half * 8;
     const uint16_t* b = t.cp_bf16 + (size_t)(l0 + r) * dp + half * 8;
-    for (int k = 0; k < t.d_pad; k += 16) {
-      bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k);
-      bf16x8 bv = *reinterpret_cast<const bf16x8*>(b + k);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    for (int k0 = 0; k0 < t.d_pad; k0 += 64) {
+      bf16x8 av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = *reinterpret_cast<const bf16x8*>(a + k0 + 16 * u);
+        bv[u] = *reinterpret_cast<const bf16x8*>(b + k0 + 16 * u);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[u], bv[u], acc, 0, 0, 0);
     }
   } else {
     const uint8_t* a = reinterpret_cast<const uint8_t*>(Aop) + (size_t)(q0 + r) * dp + half * 8;
     const uint8_t* b = t.cp_fp8 + (size_t)(l0 + r) * dp + half * 8;
-    for (int k = 0; k < t.d_pad; k += 16) {
-      long av = *reinterpret_cast<const long*>(a + k);
-      long bv = *reinterpret_cast<const long*>(b + k);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(av, bv, acc, 0, 0, 0);
+    for (int k0 = 0; k0 < t.d_pad; k0 += 64) {
+      long av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        av[u] = *reinterpret_cast<const long*>(a + k0 + 16 * u);
+        bv[u] = *reinterpret_cast<const long*>(b + k0 + 16 * u);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(av[u], bv[u], acc, 0, 0, 0);
     }
   }
   // Lane holds D[8*(j/4) + 4*half + j%4][r] for j = 0..15.
