@@ -6,6 +6,8 @@
 // summed sequentially over t in FP32 with every product and sum rounded on
 // its own (this file is compiled without FP contraction). Smaller is nearer;
 // ties go to the smaller list index.
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 #include "rank_sort.hpp"
@@ -137,45 +139,121 @@ __device__ __forceinline__ int32_t eq2_count(float p, int32_t vmin, int32_t vmax
   return v < vmax ? v : vmax;
 }
 
-// One workgroup per query. Keys (ord(score) << 32 | list) live in LDS; the
-// wanted count is selected by radix selection and sorted. With `rescore`,
-// the first selection keeps widen*nprobe lists by the (approximate) score
-// matrix, those are re-scored canonically, and nprobe are kept.
-__global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __restrict__ Q,
-                                                     int32_t nq, const int32_t* __restrict__ nprobe,
-                                                     int32_t max_nprobe, int32_t widen,
-                                                     int32_t rescore, const float* __restrict__ S,
-                                                     int32_t* __restrict__ probes,
-                                                     int32_t* __restrict__ nprobe_eff,
-                                                     int32_t* __restrict__ err,
-                                                     AdaptiveArgs ad,
-                                                     int32_t* __restrict__ reorder_eff) {
-  extern __shared__ uint64_t keys[];  // [pow2_ceil(L)]
-  __shared__ SelectScratch sc;
-  __shared__ float qv[1024];
-  const int q = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int L = t.L;
-  int np = nprobe[q];
-  if (np < 1 || np > max_nprobe) {
-    if (tid == 0) {
-      nprobe_eff[q] = -1;
-      if (reorder_eff) reorder_eff[q] = -1;
-      atomicOr(err, 1);
+// The `want` smallest (ord(score), list) keys of one score row, held NK per
+// thread in registers (list = tid + 256 i), written to keys[0..want) in no
+// particular order. The want-th smallest ord is found by 4-bit radix passes
+// from the top: per-digit counts are packed 16-bit counters in each thread's
+// registers, summed by wave butterflies and, across the four waves, by 16
+// lanes of wave 0, which also scan them and pick the digit, so no LDS atomic
+// serialises on a popular digit. The passes stop as soon as the chosen digit
+// holds exactly the keys still needed (then every key whose top bits are at
+// most the prefix is taken); after all eight, keys equal to the want-th ord
+// are taken in ascending list order, each one's rank among them counted with
+// ballots. All threads; ends with a barrier. Needs want <= the number of keys
+// (ord 0xffffffff marks a missing key; finite scores never map to it).
+template <int NK>
+__device__ void row_select(const uint32_t (&o)[NK], int want, uint64_t* keys, uint32_t* cnt) {
+  __shared__ uint32_t wsum[IVF_NWAVES][8];
+  __shared__ uint32_t rowc[NK][IVF_NWAVES];
+  __shared__ uint32_t pick[3];  // digit, keys below it, 1 = the digit holds exactly the rest
+  const int tid = threadIdx.x, wave = tid / IVF_WAVE, ln = lane_id();
+  uint32_t prefix = 0, pmask = 0;
+  uint32_t need = (uint32_t)want;
+  bool exact = false;  // stopped early: take every key with (o & pmask) <= prefix
+  for (int shift = 28; shift >= 0; shift -= 4) {
+    uint32_t c[8];
+#pragma unroll
+    for (int w = 0; w < 8; ++w) c[w] = 0u;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      const uint32_t v = o[i];
+      if (v != 0xffffffffu && (v & pmask) == prefix) {
+        const uint32_t d = (v >> shift) & 15u;
+        const uint32_t inc = 1u << ((d & 1u) << 4);
+#pragma unroll
+        for (int w = 0; w < 8; ++w) c[w] += (d >> 1) == (uint32_t)w ? inc : 0u;
+      }
     }
-    for (int p = tid; p < max_nprobe; p += blockDim.x) probes[(size_t)q * max_nprobe + p] = -1;
+    // Per-thread counts <= NK <= 64 and wave sums <= 4096 fit the 16-bit fields.
+#pragma unroll
+    for (int w = 0; w < 8; ++w)
+      for (int s = 1; s < IVF_WAVE; s <<= 1) c[w] += __shfl_xor(c[w], s);
+    if (ln == 0)
+#pragma unroll
+      for (int w = 0; w < 8; ++w) wsum[wave][w] = c[w];
+    __syncthreads();
+    if (wave == 0) {
+      // Lane d < 16: the count of digit d; inclusive scan over the 16 lanes.
+      const uint32_t d = (uint32_t)(ln & 15);
+      uint32_t cd = 0;
+#pragma unroll
+      for (int w = 0; w < IVF_NWAVES; ++w) cd += (wsum[w][d >> 1] >> ((d & 1u) << 4)) & 0xffffu;
+      if (ln >= 16) cd = 0;
+      uint32_t incl = cd;
+      for (int off = 1; off < 16; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off);
+        if (ln >= off) incl += v;
+      }
+      const uint64_t hit = __ballot(ln < 16 && incl >= need);
+      const int b = hit ? __builtin_ctzll(hit) : 15;
+      if (ln == b) {
+        pick[0] = (uint32_t)b;
+        pick[1] = incl - cd;
+        pick[2] = incl == need ? 1u : 0u;
+      }
+    }
+    __syncthreads();
+    need -= pick[1];
+    prefix |= pick[0] << shift;
+    pmask |= 15u << shift;
+    exact = pick[2] != 0;
+    __syncthreads();  // wsum and pick are rewritten by the next pass
+    if (exact) break;  // uniform
+  }
+  if (tid == 0) *cnt = 0;
+  if (exact) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      const bool take = o[i] != 0xffffffffu && (o[i] & pmask) <= prefix;
+      wave_append(take, ((uint64_t)o[i] << 32) | (uint32_t)(tid + IVF_BLOCK * i), keys, cnt);
+    }
+    __syncthreads();
     return;
   }
-  const float* srow = S + (size_t)q * L;
-  int want = rescore ? min(L, np * widen) : np;
-  for (int l = tid; l < L; l += blockDim.x) keys[l] = make_key(srow[l], (uint32_t)l);
-  __syncthreads();
-  uint32_t n = (uint32_t)L;
-  __shared__ uint32_t cnt;
-  if ((uint32_t)want < n) {
-    KeyUnion u{keys, n, nullptr, 0};
-    n = block_compact_le(keys, n, block_kth(u, (uint32_t)want, &sc), &cnt);
+  const uint32_t tord = prefix;  // the want-th smallest ord; `need` keys equal to it are taken
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const uint64_t m = __ballot(o[i] == tord);
+    if (ln == 0) rowc[i][wave] = (uint32_t)__popcll(m);
   }
+  __syncthreads();
+  uint32_t before_rows = 0;  // equal keys in rows < i (all waves)
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const bool eq = o[i] == tord;
+    const uint64_t m = __ballot(eq);
+    uint32_t rank = before_rows + lanes_below(m);
+    for (int w = 0; w < wave; ++w) rank += rowc[i][w];
+    const bool take = o[i] < tord || (eq && rank < need);
+    wave_append(take, ((uint64_t)o[i] << 32) | (uint32_t)(tid + IVF_BLOCK * i), keys, cnt);
+    for (int w = 0; w < IVF_NWAVES; ++w) before_rows += rowc[i][w];
+  }
+  __syncthreads();
+}
+
+// Second half of the selection, shared by both kernels: keys[0..n) hold the
+// first selection. With `rescore` they are re-scored canonically and the
+// np best kept; then they are sorted (by rank into the free space behind
+// them when n <= 512 and 2n <= cap, else bitonic), the adaptive counts are
+// taken from the sorted scores, and the probe row is written.
+__device__ void select_finish(const Tables& t, const float* __restrict__ Q, int q, int np,
+                              int max_nprobe, int rescore, uint64_t* keys, uint32_t n,
+                              uint32_t cap, SelectScratch* sc, uint32_t* cnt, float* qv,
+                              const AdaptiveArgs& ad, int32_t* __restrict__ probes,
+                              int32_t* __restrict__ nprobe_eff,
+                              int32_t* __restrict__ reorder_eff) {
+  const int tid = threadIdx.x;
   if (rescore) {
     // Canonical FP32 re-score of the kept lists; the query is staged in LDS
     // when it fits, else read from global memory.
@@ -191,13 +269,10 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
     __syncthreads();
     if ((uint32_t)np < n) {
       KeyUnion u{keys, n, nullptr, 0};
-      n = block_compact_le(keys, n, block_kth(u, (uint32_t)np, &sc), &cnt);
+      n = block_compact_le(keys, n, block_kth(u, (uint32_t)np, sc), cnt);
     }
   }
-  // Ascending (score, list): by rank into the free space behind the keys
-  // when there is room (n <= 512 and 2n <= the key array), else bitonic.
   const uint64_t* sorted = keys;
-  const uint32_t cap = pow2_ceil((uint32_t)L);
   if (n <= 512 && 2 * n <= cap) {
     __syncthreads();
     block_rank_sort(keys, n, keys + n);
@@ -236,16 +311,114 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
     probes[(size_t)q * max_nprobe + p] = p < npu ? (int32_t)(uint32_t)sorted[p] : -1;
 }
 
+// A request with nprobe out of range: error word, -1 row. True if invalid.
+__device__ __forceinline__ bool reject_row(int q, int np, int max_nprobe,
+                                           int32_t* __restrict__ probes,
+                                           int32_t* __restrict__ nprobe_eff,
+                                           int32_t* __restrict__ err,
+                                           int32_t* __restrict__ reorder_eff) {
+  if (np >= 1 && np <= max_nprobe) return false;
+  if (threadIdx.x == 0) {
+    nprobe_eff[q] = -1;
+    if (reorder_eff) reorder_eff[q] = -1;
+    atomicOr(err, 1);
+  }
+  for (int p = threadIdx.x; p < max_nprobe; p += blockDim.x) probes[(size_t)q * max_nprobe + p] = -1;
+  return true;
+}
+
+// One workgroup per query, L <= 2048: the keys (ord(score) << 32 | list) of
+// the whole row in LDS ([cap] = pow2(L) slots) and the wanted count picked
+// by the byte-wise radix selection of common.hpp.
+__global__ void __launch_bounds__(256) select_lds_kernel(Tables t, const float* __restrict__ Q,
+                                                         int32_t nq, const int32_t* __restrict__ nprobe,
+                                                         int32_t max_nprobe, int32_t widen,
+                                                         int32_t rescore, const float* __restrict__ S,
+                                                         int32_t* __restrict__ probes,
+                                                         int32_t* __restrict__ nprobe_eff,
+                                                         int32_t* __restrict__ err, AdaptiveArgs ad,
+                                                         int32_t* __restrict__ reorder_eff,
+                                                         uint32_t cap) {
+  extern __shared__ uint64_t keys[];
+  __shared__ SelectScratch sc;
+  __shared__ float qv[1024];
+  __shared__ uint32_t cnt;
+  const int q = blockIdx.x;
+  const int L = t.L;
+  const int np = nprobe[q];
+  if (reject_row(q, np, max_nprobe, probes, nprobe_eff, err, reorder_eff)) return;
+  const float* srow = S + (size_t)q * L;
+  const int want = rescore ? min(L, np * widen) : np;
+  for (int l = threadIdx.x; l < L; l += blockDim.x) keys[l] = make_key(srow[l], (uint32_t)l);
+  __syncthreads();
+  uint32_t n = (uint32_t)L;
+  if ((uint32_t)want < n) {
+    KeyUnion u{keys, n, nullptr, 0};
+    n = block_compact_le(keys, n, block_kth(u, (uint32_t)want, &sc), &cnt);
+  }
+  select_finish(t, Q, q, np, max_nprobe, rescore, keys, n, cap, &sc, &cnt, qv, ad, probes,
+                nprobe_eff, reorder_eff);
+}
+
+// One workgroup per query, larger L: the row stays in registers (NK keys per
+// thread, row_select) and LDS holds only the selection ([cap] = twice the
+// largest selection, rounded up to a power of two).
+template <int NK>
+__global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __restrict__ Q,
+                                                     int32_t nq, const int32_t* __restrict__ nprobe,
+                                                     int32_t max_nprobe, int32_t widen,
+                                                     int32_t rescore, const float* __restrict__ S,
+                                                     int32_t* __restrict__ probes,
+                                                     int32_t* __restrict__ nprobe_eff,
+                                                     int32_t* __restrict__ err,
+                                                     AdaptiveArgs ad,
+                                                     int32_t* __restrict__ reorder_eff,
+                                                     uint32_t cap) {
+  extern __shared__ uint64_t keys[];
+  __shared__ SelectScratch sc;
+  __shared__ float qv[1024];
+  __shared__ uint32_t cnt;
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int L = t.L;
+  const int np = nprobe[q];
+  if (reject_row(q, np, max_nprobe, probes, nprobe_eff, err, reorder_eff)) return;
+  const float* srow = S + (size_t)q * L;
+  const int want = rescore ? min(L, np * widen) : np;
+  uint32_t o[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const int l = tid + IVF_BLOCK * i;
+    o[i] = l < L ? f2ord(srow[l]) : 0xffffffffu;
+  }
+  row_select<NK>(o, want, keys, &cnt);
+  select_finish(t, Q, q, np, max_nprobe, rescore, keys, (uint32_t)want, cap, &sc, &cnt, qv, ad,
+                probes, nprobe_eff, reorder_eff);
+}
+
 hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
                                 const int32_t* nprobe, int32_t max_nprobe, int32_t widen,
                                 bool rescore, const Workspace& w, hipStream_t s,
                                 const AdaptiveArgs& ad) {
   if (nq == 0) return hipSuccess;
-  size_t lds = (size_t)pow2_ceil((uint32_t)t.L) * sizeof(uint64_t);
-  hipLaunchKernelGGL(select_kernel, dim3(nq), dim3(256), lds, s, t, Q, nq, nprobe, max_nprobe,
-                     widen, rescore ? 1 : 0, w.scores, w.probes, w.nprobe_eff, w.err, ad,
-                     w.reorder_eff);
-  return hipGetLastError();
+  const int32_t most = rescore ? std::min(t.L, max_nprobe * widen) : max_nprobe;
+  const int nk = (t.L + IVF_BLOCK - 1) / IVF_BLOCK;
+  // Short rows: the whole row in LDS; longer ones: registers, so LDS (and
+  // occupancy) depends only on the selection size.
+  const uint32_t cap = nk <= 8 ? pow2_ceil((uint32_t)t.L)
+                               : 2 * pow2_ceil((uint32_t)(most > 0 ? most : 1));
+  const size_t lds = (size_t)cap * sizeof(uint64_t);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(nq), dim3(256), lds, s, t, Q, nq, nprobe, max_nprobe, widen,
+                       rescore ? 1 : 0, w.scores, w.probes, w.nprobe_eff, w.err, ad,
+                       w.reorder_eff, cap);
+    return hipGetLastError();
+  };
+  if (nk <= 8) return go(select_lds_kernel);
+  if (nk <= 16) return go(select_kernel<16>);
+  if (nk <= 32) return go(select_kernel<32>);
+  if (nk <= 64) return go(select_kernel<64>);
+  return hipErrorInvalidValue;
 }
 
 // Caller-given probe sets: validate counts and list indices, copy.
