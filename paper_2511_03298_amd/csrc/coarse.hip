@@ -361,8 +361,9 @@ __global__ void __launch_bounds__(256) select_lds_kernel(Tables t, const float* 
 }
 
 // One workgroup per query, larger L: the row stays in registers (NK keys per
-// thread, row_select) and LDS holds only the selection ([cap] = twice the
-// largest selection, rounded up to a power of two).
+// thread, row_select) and LDS holds only the selection ([cap] = the largest
+// selection rounded up to a power of two, doubled up to 512 for the rank
+// sort's output).
 template <int NK>
 __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __restrict__ Q,
                                                      int32_t nq, const int32_t* __restrict__ nprobe,
@@ -405,8 +406,8 @@ hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
   const int nk = (t.L + IVF_BLOCK - 1) / IVF_BLOCK;
   // Short rows: the whole row in LDS; longer ones: registers, so LDS (and
   // occupancy) depends only on the selection size.
-  const uint32_t cap = nk <= 8 ? pow2_ceil((uint32_t)t.L)
-                               : 2 * pow2_ceil((uint32_t)(most > 0 ? most : 1));
+  const uint32_t sel = pow2_ceil((uint32_t)(most > 0 ? most : 1));
+  const uint32_t cap = nk <= 8 ? pow2_ceil((uint32_t)t.L) : (sel > 512 ? sel : 2 * sel);
   const size_t lds = (size_t)cap * sizeof(uint64_t);
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(nq), dim3(256), lds, s, t, Q, nq, nprobe, max_nprobe, widen,

@@ -824,3 +824,66 @@ def test_gpu_trained_spilled_index():
     a, ids = ivf.decode_keys(keys)
     assert np.array_equal(ids, res["cand_id"])
     assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# Probe selection on long score rows (L > 2048: keys held in registers,
+# 4-bit radix passes, ties by list order).
+# ---------------------------------------------------------------------------
+
+def _long_row_index(ivf, L, d, metric, seed, groups=None):
+    """An index with one point per list (only the centroids matter here).
+    groups: the centroids are drawn from L / groups distinct rows, so scores
+    tie exactly."""
+    rng = np.random.default_rng(seed)
+    if groups:
+        base = rng.standard_normal((L // groups + 1, d)).astype(np.float32)
+        C = base[rng.integers(0, len(base), size=L)]
+    else:
+        C = rng.standard_normal((L, d)).astype(np.float32)
+    if metric == "ip":
+        C = (C / np.linalg.norm(C, axis=1, keepdims=True)).astype(np.float32)
+    m = 4
+    cb = rng.standard_normal((m, 16, d // m)).astype(np.float32)
+    codes = rng.integers(0, 16, size=(L, m)).astype(np.uint8)
+    g = ivf.GpuIndex(C.copy(), C, cb, codes, np.arange(L + 1), np.arange(L, dtype=np.int32),
+                     metric, probe_centroids=C)
+    return g, C
+
+
+@pytest.mark.parametrize("L,metric,groups", [(3000, "l2", None), (3000, "l2", 7),
+                                             (9000, "ip", None), (4100, "ip", 16)])
+def test_long_row_selection_bit_exact(L, metric, groups):
+    import paper_2511_03298_amd as ivf
+    _gpu()
+    d = 16
+    g, C = _long_row_index(ivf, L, d, metric, seed=L + (groups or 0), groups=groups)
+    rng = np.random.default_rng(5)
+    nq = 24
+    Q = rng.standard_normal((nq, d)).astype(np.float32)
+    if groups:
+        Q[:4] = C[[0, 1, 2, 3]]  # queries on a repeated centroid: ties at the top
+    nprobe = rng.choice([1, 2, 7, 64, 300, 1000], size=nq).astype(np.int32)
+    print(f"[long rows] L={L} metric={metric} groups={groups} nprobe={sorted(set(nprobe.tolist()))}",
+          flush=True)
+    want = []
+    for qi in range(nq):
+        s = oracle.coarse_scores(Q[qi], C, metric)
+        want.append(oracle.select_probes(s, int(nprobe[qi])))
+    got = g.debug_probes(Q, nprobe).cpu().numpy()
+    for qi, p in enumerate(want):
+        assert np.array_equal(got[qi, :len(p)], p), qi
+        assert np.all(got[qi, len(p):] == -1)
+    # MFMA pre-selection widened to every list, then the canonical re-score.
+    if L <= 8192:
+        got = g.debug_probes(Q, nprobe, opts=ivf.make_opts(coarse="bf16", widen=L)).cpu().numpy()
+        for qi, p in enumerate(want):
+            assert np.array_equal(got[qi, :len(p)], p), qi
+    # Adaptive counts read the sorted canonical scores of the long row.
+    ad = dict(nprobe_init=8, nprobe_min=1, reorder_min=50, p0=0.2, p1=0.5)
+    used, reo = g.debug_adaptive(Q, np.full(nq, 64, np.int32), 10, 100,
+                                 opts=ivf.make_opts(adaptive=ad))
+    for qi in range(nq):
+        s = oracle.coarse_scores(Q[qi], C, metric)
+        npq, rq, _ = oracle.adaptive_params(s, 64, metric, 8, 1, 50, 100, 10, 0.2, 0.5)
+        assert int(used[qi]) == npq and int(reo[qi]) == rq, qi
