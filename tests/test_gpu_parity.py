@@ -852,7 +852,8 @@ def _long_row_index(ivf, L, d, metric, seed, groups=None):
 
 
 @pytest.mark.parametrize("L,metric,groups", [(3000, "l2", None), (3000, "l2", 7),
-                                             (9000, "ip", None), (4100, "ip", 16)])
+                                             (9000, "ip", None), (4100, "ip", 16),
+                                             (16384, "l2", None)])
 def test_long_row_selection_bit_exact(L, metric, groups):
     import paper_2511_03298_amd as ivf
     _gpu()
@@ -887,3 +888,32 @@ def test_long_row_selection_bit_exact(L, metric, groups):
         s = oracle.coarse_scores(Q[qi], C, metric)
         npq, rq, _ = oracle.adaptive_params(s, 64, metric, 8, 1, 50, 100, 10, 0.2, 0.5)
         assert int(used[qi]) == npq and int(reo[qi]) == rq, qi
+
+
+def test_largest_m_plain_form():
+    # m = 256 subspaces (d' = 1), the largest the tables allow: 32 code words
+    # per point. The plain form matches the oracle bit for bit; the batched
+    # form (tables for up to 192 subspaces) refuses it.
+    import paper_2511_03298_amd as ivf
+    _gpu()
+    cfg, X, Q, nprobe, index = cached_workload("c6", 6000, 10, L=16, ncomp=16, m=256,
+                                               nprobe=(4, 4))
+    assert index["codebooks"].shape[0] == 256
+    print(f"[m=256] n={len(X)} d={X.shape[1]} L={cfg.L}", flush=True)
+    g = ivf.GpuIndex.from_index(index, X, base_dtype=cfg.base_dtype)
+    res = oracle_stages(index, X, Q, nprobe, cfg.k, cfg.R)
+    P = probes_tensor(res, nprobe)
+    lut, lo, delta, B = [t.cpu().numpy() for t in g.debug_luts(Q, P, nprobe)]
+    for qi, p in enumerate(res["probes"]):
+        for pi, l in enumerate(p):
+            q8, lo_o, d_o, B_o = res["luts"][(qi, int(l))]
+            assert np.array_equal(lut[qi, pi], q8)
+            assert B[qi, pi].view(np.uint32) == np.float32(B_o).view(np.uint32)
+    keys = g.debug_candidates(Q, P, nprobe, cfg.R).cpu().numpy()
+    a, ids = ivf.decode_keys(keys)
+    assert np.array_equal(ids, res["cand_id"])
+    assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+    ids, dist = g.search(Q, nprobe, cfg.k, cfg.R)
+    check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q, cfg.metric, exact_ids=True)
+    with pytest.raises(ivf.IvfError):
+        g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(form="batched"))
