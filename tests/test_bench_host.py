@@ -1,0 +1,57 @@
+"""Host-side checks of the benchmark's contract and its derived figures."""
+
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_distance_error_against_float64():
+    import bench
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((50, 8)).astype(np.float32)
+    Q = rng.standard_normal((4, 8)).astype(np.float32)
+    ids = np.array([[0, 1, -1], [2, 3, 4], [5, -1, -1], [6, 7, 8]])
+    exact = np.zeros(ids.shape, np.float32)
+    for qi in range(4):
+        for j, i in enumerate(ids[qi]):
+            if i >= 0:
+                exact[qi, j] = ((X[i].astype(np.float64) - Q[qi]) ** 2).sum()
+    assert bench.distance_error(ids, exact, X, Q, "l2") < 1e-7
+    bad = exact.copy()
+    bad[1, 2] *= 1.001
+    assert abs(bench.distance_error(ids, bad, X, Q, "l2") - 1e-3) < 1e-5
+
+
+def test_coarse_mfma_roofline_is_the_smaller_bound():
+    import bench
+    from workloads import CONFIGS
+    r = dict(coarse="bf16", stage_ms={"coarse": 0.1})
+    c4 = bench.coarse_mfma(CONFIGS["c4"], r)     # 164 MB score matrix: HBM-bound
+    assert c4["bound"] == "hbm" and c4["peak"] < c4["mfma_peak"]
+    assert abs(c4["achieved"] - 2 * 10_000 * 4096 * 96 / 1e-4 / 1e12) < 0.01
+    c5 = bench.coarse_mfma(CONFIGS["c5"], dict(coarse="bf16", stage_ms={"coarse": 0.1}))
+    assert c5["bound"] == "mfma" and c5["peak"] == 2500.0   # d = 768: compute-bound
+    assert bench.coarse_mfma(CONFIGS["c2"], dict(coarse="exact", stage_ms={"coarse": 0.1})) is None
+
+
+def test_traffic_only_while_sources_match():
+    import bench
+    for (config, form), rec in bench.TRAFFIC.items():
+        t = bench.recorded_traffic(config, form)
+        if bench.source_sha(rec["files"]) == rec["sha"]:
+            assert t == int(rec["fetch_kib"] * 1024 * 2.0 + rec["write_kib"] * 1024)
+        else:
+            assert t is None

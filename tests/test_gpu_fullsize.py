@@ -1,6 +1,7 @@
 """Parity at the benchmark's full size: 1M x 128 integer L2 data, 1024 lists,
 m = 64, 10k queries, nprobe 32, k 10, R 200, searched in the launch
-configurations bench.py times (plain + exact coarse, batched + BF16 coarse);
+configurations bench.py times (plain + exact coarse, batched + BF16 coarse,
+batched + exact coarse);
 sampled queries are recomputed by the oracle one by one.
 """
 
@@ -34,7 +35,8 @@ def full():
 SAMPLE = [0, 1, 997, 4242, 7777, 9999]
 
 
-@pytest.mark.parametrize("form,coarse", [("plain", "exact"), ("batched", "bf16")])
+@pytest.mark.parametrize("form,coarse", [("plain", "exact"), ("batched", "bf16"),
+                                        ("batched", "exact")])
 def test_fullsize_sampled_queries(form, coarse):
     import paper_2511_03298_amd as ivf
     f = full()
