@@ -4,8 +4,8 @@ For one index and one query-batch shape it measures a set of schedules on the
 device and keeps the fastest admissible one:
   * form: plain (one workgroup per query) or batched (persistent list-major);
   * coarse precision: exact FP32, or FP32/BF16/FP8 MFMA pre-selection with
-    widening 2 or 4 -- admitted only when its probe sets agree with the exact
-    ones on at least `min_agree` of the queries (results are otherwise
+    widening 1, 2 or 4 -- admitted only when its probe sets agree with the
+    exact ones on at least `min_agree` of the queries (results are otherwise
     bit-identical, the forms only change the schedule);
   * plain candidate-buffer size (pool_cap), batched persistent grid size and
     number of threshold-tightening rounds.
@@ -33,7 +33,8 @@ def shape_key(g: GpuIndex, nq: int, max_nprobe: int, k: int, rerank: int) -> str
 
 def default_space():
     space = []
-    for coarse, widen in (("exact", 2), ("bf16", 2), ("bf16", 4), ("fp8", 4), ("f32", 2)):
+    for coarse, widen in (("exact", 2), ("bf16", 1), ("bf16", 2), ("bf16", 4), ("fp8", 4),
+                          ("f32", 2)):
         for pool in (0, 2048, 4096):
             space.append(dict(form="plain", coarse=coarse, widen=widen, pool_cap=pool))
         for rounds in (1, 3):
