@@ -2,9 +2,10 @@
 
 KMeans over the lists, PQ codebooks per subspace, Quantize. The heavy steps
 run in the library's kernels: nearest-list assignment (`ivf_assign`, the
-coarse-scoring kernels with top-1 selection) and residual encoding
-(`ivf_encode`). The k-means mean updates are small reductions done on the
-host in float64 so the trained index is reproducible. Lists are selected with
+coarse-scoring kernels with top-1 selection), the codeword assignment of the
+PQ k-means and the residual encoding (`ivf_encode`). The k-means mean
+updates are small reductions done on the host in float64 so the trained
+index is reproducible. Lists are selected with
 normalised centroids for inner product and residuals use the mean centroids
 (section 4.6.1).
 """
@@ -37,18 +38,34 @@ def _normalise(C):
     return C / nrm
 
 
-def _host_kmeans(X, k, iters, rng):
-    """Small k-means for the 16-codeword PQ codebooks (host, float64 means)."""
-    C = X[rng.choice(len(X), size=k, replace=len(X) < k)].astype(np.float64)
+def _pq_kmeans_gpu(resid, m, iters, rng, device):
+    """16-codeword k-means of every PQ subspace at once: the assignment step is
+    the encoding kernel (ivf_encode with one all-zero centroid, so the
+    residual it quantises is the row itself), the means are float64 sums on
+    the host; an empty codeword is reseeded from a random row."""
+    import torch
+    nt, d = resid.shape
+    dsub = d // m
+    sub = resid.reshape(nt, m, dsub)
+    cb = np.empty((m, KSUB, dsub), dtype=np.float64)
+    for j in range(m):
+        cb[j] = sub[rng.choice(nt, size=KSUB, replace=nt < KSUB), j]
+    Rd = torch.from_numpy(np.ascontiguousarray(resid, dtype=np.float32)).to(device)
+    zero = torch.zeros((1, d), dtype=torch.float32, device=device)
+    lists = torch.zeros(nt, dtype=torch.int32, device=device)
     for _ in range(iters):
-        d = ((X[:, None, :].astype(np.float64) - C[None]) ** 2).sum(axis=2)
-        a = np.argmin(d, axis=1)
-        sums, counts = _group_means(X, a, k)
-        C = np.where(counts[:, None] > 0, sums / np.maximum(counts, 1)[:, None], C)
-        empty = counts == 0
-        if empty.any():
-            C[empty] = X[rng.choice(len(X), size=int(empty.sum()))]
-    return C.astype(np.float32)
+        cbd = torch.from_numpy(cb.astype(np.float32)).to(device)
+        codes = encode_codes(Rd, zero, lists, cbd).cpu().numpy().astype(np.int64)
+        for j in range(m):
+            a = codes[:, j]
+            counts = np.bincount(a, minlength=KSUB)
+            sums = np.stack([np.bincount(a, weights=sub[:, j, u].astype(np.float64),
+                                         minlength=KSUB) for u in range(dsub)], axis=1)
+            live = counts > 0
+            cb[j][live] = sums[live] / counts[live][:, None]
+            if (~live).any():
+                cb[j][~live] = sub[rng.choice(nt, size=int((~live).sum())), j]
+    return cb.astype(np.float32)
 
 
 def component_filter(X: np.ndarray, threshold: float, chunk: int = 1 << 18) -> np.ndarray:
@@ -128,15 +145,11 @@ def train_index_gpu(X: np.ndarray, L: int, m: int, metric: str, seed: int = 0,
     cm = cm64.astype(np.float32)
     cp = _normalise(cm.astype(np.float64)).astype(np.float32) if ip else cm.copy()
 
-    dsub = d // m
     pidx = rng.choice(n, size=min(n, pq_train), replace=False)
     resid = X[pidx] - cm[assign[pidx]]
     if log:
         log(f"PQ codebooks: {m} subspaces")
-    codebooks = np.empty((m, KSUB, dsub), dtype=np.float32)
-    for j in range(m):
-        codebooks[j] = _host_kmeans(np.ascontiguousarray(resid[:, j * dsub:(j + 1) * dsub]),
-                                    KSUB, pq_iters, rng)
+    codebooks = _pq_kmeans_gpu(resid, m, pq_iters, rng, device)
     cmd = torch.from_numpy(cm).to(device)
     cbd = torch.from_numpy(codebooks).to(device)
     codes = encode_codes(Xd, cmd, assign_d, cbd)

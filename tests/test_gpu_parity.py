@@ -917,3 +917,24 @@ def test_largest_m_plain_form():
     check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q, cfg.metric, exact_ids=True)
     with pytest.raises(ivf.IvfError):
         g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(form="batched"))
+
+
+def test_gpu_pq_kmeans():
+    # PQ codebook k-means with the encoding kernel as its assignment step:
+    # each iteration's codes are the oracle's nearest codewords, and the
+    # quantisation error does not grow with more iterations.
+    from paper_2511_03298_amd.train import _pq_kmeans_gpu
+    cfg, X, Q, nprobe, index, g, res = case("c2s")
+    off = index["list_offsets"]
+    lists = np.repeat(np.arange(cfg.L), np.diff(off))
+    rows = index["list_ids"].astype(np.int64)
+    resid = (X[rows] - index["cm"][lists]).astype(np.float32)[:8000]
+    errs = []
+    for iters in (1, 4, 10):
+        cb = _pq_kmeans_gpu(resid, cfg.m, iters, np.random.default_rng(3), "cuda")
+        codes = oracle.encode(resid, np.zeros((1, resid.shape[1]), np.float32),
+                              np.zeros(len(resid), np.int64), cb)
+        rec = np.concatenate([cb[j][codes[:, j]] for j in range(cfg.m)], axis=1)
+        errs.append(float(((resid.astype(np.float64) - rec) ** 2).sum(axis=1).mean()))
+    print(f"[pq k-means] mean squared error after 1/4/10 iterations: {errs}", flush=True)
+    assert errs[1] <= errs[0] * (1 + 1e-6) and errs[2] <= errs[1] * (1 + 1e-6)
