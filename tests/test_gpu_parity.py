@@ -938,3 +938,32 @@ def test_gpu_pq_kmeans():
         errs.append(float(((resid.astype(np.float64) - rec) ** 2).sum(axis=1).mean()))
     print(f"[pq k-means] mean squared error after 1/4/10 iterations: {errs}", flush=True)
     assert errs[1] <= errs[0] * (1 + 1e-6) and errs[2] <= errs[1] * (1 + 1e-6)
+
+
+def test_filtered_and_spilled_index_from_the_gpu_trainer():
+    # Component filtration and spilled assignment together, both built by the
+    # GPU trainer: pools bit-exact against the oracle on the same index, the
+    # re-rank on the full rows.
+    import paper_2511_03298_amd as ivf
+    from paper_2511_03298_amd.train import train_index_gpu
+    _gpu()
+    from workloads import make_workload, scaled
+    cfg = scaled("c6", 12_000, 16, L=24, ncomp=24, nprobe=(4, 4))
+    X, Q, nprobe = make_workload(cfg)
+    keep, _ = oracle.component_filter(X, 0.9)
+    tr = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=2, dims=keep, soar=1.0)
+    assert tr["copies"] == 2 and len(tr["dims"]) == len(keep) < X.shape[1]
+    idx = dict(tr, codes=tr["codes"].cpu().numpy(), list_ids=tr["list_ids"].cpu().numpy())
+    print(f"[filtered+spilled] kept {len(keep)} of {X.shape[1]} dims, "
+          f"{len(idx['list_ids'])} entries for {len(X)} rows", flush=True)
+    g = ivf.GpuIndex.from_index(idx, X, base_dtype=cfg.base_dtype)
+    res = oracle_stages(idx, X, Q, nprobe, cfg.k, cfg.R)
+    P = probes_tensor(res, nprobe)
+    for form in ("plain", "batched"):
+        keys = g.debug_candidates(Q, P, nprobe, cfg.R, opts=ivf.make_opts(form=form)).cpu().numpy()
+        a, ids = ivf.decode_keys(keys)
+        assert np.array_equal(ids, res["cand_id"]), form
+        assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32)), form
+    ids, dist = g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(form="batched"))
+    check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q, cfg.metric, exact_ids=True)
+    assert g.device_error() == 0
