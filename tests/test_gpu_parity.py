@@ -967,3 +967,40 @@ def test_filtered_and_spilled_index_from_the_gpu_trainer():
     ids, dist = g.search(Q, nprobe, cfg.k, cfg.R, opts=ivf.make_opts(form="batched"))
     check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q, cfg.metric, exact_ids=True)
     assert g.device_error() == 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_fuzz_shapes(seed):
+    # Random shapes inside the supported range: d not a multiple of 16, any
+    # divisor m, L not a multiple of the tiles, per-query nprobe in [1, L],
+    # R in [k, n]. Probe sets and pools bit-exact in both forms; re-rank
+    # within the tolerance.
+    import paper_2511_03298_amd as ivf
+    _gpu()
+    rng = np.random.default_rng(1000 + seed)
+    name = ("c1", "c3")[seed % 2]
+    d = int(rng.choice([12, 20, 36, 60, 100]))
+    m = int(rng.choice([v for v in range(1, min(d, 128) + 1) if d % v == 0]))
+    L = int(rng.integers(5, 150))
+    n = int(rng.integers(2000, 6000))
+    k = int(rng.integers(1, 20))
+    R = int(rng.integers(k, min(n, 1024) + 1))
+    cfg, X, Q, nprobe, index = cached_workload(name, n, 12, L=L, ncomp=max(4, L // 2), d=d, m=m,
+                                               nprobe=(1, L), k=k, R=R)
+    print(f"[fuzz {seed}] {cfg.metric} n={n} d={d} m={m} L={L} k={k} R={R} "
+          f"nprobe={nprobe.tolist()}", flush=True)
+    g = ivf.GpuIndex.from_index(index, X)
+    res = oracle_stages(index, X, Q, nprobe, k, R)
+    got = g.debug_probes(Q, nprobe).cpu().numpy()
+    for qi, p in enumerate(res["probes"]):
+        assert np.array_equal(got[qi, :len(p)], p), qi
+    P = probes_tensor(res, nprobe)
+    for opts in (ivf.make_opts(), ivf.make_opts(form="batched"),
+                 ivf.make_opts(form="batched", rounds=3)):
+        keys = g.debug_candidates(Q, P, nprobe, R, opts=opts).cpu().numpy()
+        a, ids = ivf.decode_keys(keys)
+        assert np.array_equal(ids, res["cand_id"]), ivf.opts_dict(opts)
+        assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+    ids, dist = g.search(Q, nprobe, k, R, opts=ivf.make_opts(form="batched"))
+    check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q, cfg.metric)
+    assert g.device_error() == 0

@@ -1,0 +1,65 @@
+"""Input generators and the host trainer: determinism and index sanity."""
+
+import hashlib
+
+import numpy as np
+
+from workloads import CONFIGS, make_workload, scaled, spill_index, train_index
+
+
+def _sha(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def test_generator_is_deterministic_and_thread_independent():
+    # More than one 200k-row chunk, so the threaded draw is exercised.
+    cfg = scaled("c3", 450_000, 50, L=40, ncomp=40)
+    a = make_workload(cfg, threads=1)
+    b = make_workload(cfg, threads=4)
+    c = make_workload(cfg)
+    assert _sha(*a) == _sha(*b) == _sha(*c)
+    other = make_workload(scaled("c3", 450_000, 50, L=41, ncomp=41))
+    assert _sha(other[0]) != _sha(a[0])
+
+
+def test_workload_shapes_and_value_ranges():
+    for name in ("c1", "c2", "c3", "c6"):
+        cfg = scaled(name, 5000, 20, L=16, ncomp=16)
+        X, Q, nprobe = make_workload(cfg)
+        assert X.shape == (5000, cfg.d) and Q.shape == (20, cfg.d)
+        assert X.dtype == np.float32 and nprobe.dtype == np.int32
+        assert np.all((nprobe >= cfg.nprobe[0]) & (nprobe <= cfg.nprobe[1]))
+        if cfg.dist == "int255":
+            assert np.all(X == np.round(X)) and X.min() >= 0 and X.max() <= 255
+        if cfg.dist == "sphere":
+            assert np.allclose(np.linalg.norm(X, axis=1), 1.0, atol=1e-5)
+    c5 = scaled("c5", 3000, 4, L=8, ncomp=8)
+    X5, _, _ = make_workload(c5)
+    bits = X5.view(np.uint32)
+    assert np.all(bits & 0xFFFF == 0)  # BF16 values: the low mantissa half is zero
+    assert CONFIGS["c2"].base_dtype == "f32"
+
+
+def test_trained_index_is_a_valid_partition():
+    cfg = scaled("c2", 6000, 10, L=24, ncomp=20)
+    X, Q, _ = make_workload(cfg)
+    idx = train_index(X, cfg)
+    off, lid = idx["list_offsets"], idx["list_ids"]
+    assert off[0] == 0 and off[-1] == len(X) and np.all(np.diff(off) >= 0)
+    assert np.array_equal(np.sort(lid), np.arange(len(X)))  # every row in exactly one list
+    for l in range(cfg.L):
+        assert np.all(np.diff(lid[off[l]:off[l + 1]]) > 0)   # ascending within a list
+    assert idx["codes"].shape == (len(X), cfg.m) and idx["codes"].max() < 16
+    assert idx["codebooks"].shape == (cfg.m, 16, cfg.d // cfg.m)
+    # The spilled copy: two entries per row in two different lists.
+    sp = spill_index(X, idx, 1.0)
+    lists_of = {}
+    for l in range(cfg.L):
+        for i in sp["list_ids"][sp["list_offsets"][l]:sp["list_offsets"][l + 1]]:
+            lists_of.setdefault(int(i), []).append(l)
+    assert len(lists_of) == len(X)
+    assert all(len(v) == 2 and v[0] != v[1] for v in lists_of.values())
+    assert sp["codes"].shape == (2 * len(X), cfg.m)
