@@ -142,12 +142,17 @@ def test_u8_and_f32_rows_rerank_identically():
     check_final(i8.cpu().numpy(), d8.cpu().numpy(), res, X, Q, cfg.metric, exact_ids=True)
 
 
+@pytest.mark.parametrize("form,rounds", [("plain", 0), ("batched", 1), ("batched", 3)])
 @pytest.mark.parametrize("name", ["c1", "c3s"])
-def test_repeat_runs_bit_identical(name):
+def test_repeat_runs_bit_identical(name, form, rounds):
+    # Ten runs, bit for bit: the survivors' append order varies from run to
+    # run in the batched form, the selected keys and the results do not.
+    import paper_2511_03298_amd as ivf
     cfg, X, Q, nprobe, index, g, res = case(name)
+    opts = ivf.make_opts(form=form, coarse="bf16", rounds=rounds)
     outs = []
-    for _ in range(4):
-        ids, dist = g.search(Q, nprobe, cfg.k, cfg.R)
+    for _ in range(10):
+        ids, dist = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
         outs.append((ids.cpu().numpy(), dist.cpu().numpy().view(np.uint32)))
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
