@@ -217,3 +217,17 @@ def test_u8_rows_must_be_bytes():
             ivf.GpuIndex(bad, np.zeros((1, 2), np.float32), np.zeros((1, 16, 2), np.float32),
                          np.zeros((2, 1), np.uint8), [0, 2], [0, 1], "l2", base_dtype="u8",
                          device="cpu")
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # No fallback: without the HIP library every entry of the binding raises.
+    import numpy as np
+    import paper_2511_03298_amd as ivf
+    monkeypatch.setattr(ivf, "LIB_PATH", str(tmp_path / "libivfpq.so"))
+    monkeypatch.setattr(ivf, "_LIB", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        ivf.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        ivf.GpuIndex(np.zeros((4, 2), np.float32), np.zeros((1, 2), np.float32),
+                     np.zeros((1, 16, 2), np.float32), np.zeros((4, 1), np.uint8), [0, 4],
+                     np.arange(4, dtype=np.int32), "l2", device="cpu")
