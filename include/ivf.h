@@ -23,6 +23,12 @@
  *   - Host-side validation happens before anything is enqueued: on a non-OK
  *     status nothing was written and ivf_last_error() describes the problem.
  *     No exception crosses this boundary and the library never aborts.
+ *   - Sharing: searches never write the table memory, so searches of one
+ *     index may be in flight on several streams at once, each with its own
+ *     workspace (a workspace serves one search at a time). The host handle is
+ *     not locked: the graph cache (use_graph) and the profiling ring live in
+ *     it, so calls on one index from several host threads must be serialised
+ *     by the caller, and ivf_destroy must follow the last of them.
  *   - Distances: IVF_METRIC_L2 returns squared Euclidean distances, ascending;
  *     IVF_METRIC_IP returns inner products, descending. Ties are broken by
  *     the smaller id at every selection step.

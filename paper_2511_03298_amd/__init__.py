@@ -259,7 +259,9 @@ class GpuIndex:
                                                   ctypes.byref(opts))
         if nbytes == 0:
             raise IvfError(IVF_ERR_INVALID_ARG, last_error())
-        key = nbytes
+        # One cached workspace per (size, stream): a search enqueued on another
+        # stream gets its own, so two streams never share one in flight.
+        key = (nbytes, torch.cuda.current_stream().cuda_stream)
         ws = self._ws.get(key)
         if ws is None:
             ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
