@@ -158,6 +158,28 @@ def test_repeat_runs_bit_identical(name, form, rounds):
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
 
 
+@pytest.mark.parametrize("form", ["plain", "batched"])
+def test_two_streams_in_flight(form):
+    # One index searched on two streams at once, each search with its own
+    # workspace (the binding keeps one per stream): both equal the oracle.
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case("c3s")
+    opts = ivf.make_opts(form=form)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    outs = []
+    for s in streams:
+        with torch.cuda.stream(s):
+            outs.append(g.search(Q, nprobe, cfg.k, cfg.R, opts=opts))
+    torch.cuda.synchronize()
+    got = [(ids.cpu().numpy(), dist.cpu().numpy()) for ids, dist in outs]
+    for ids, dist in got:
+        check_final(ids, dist, res, X, Q, cfg.metric)
+    assert np.array_equal(got[0][0], got[1][0])
+    assert np.array_equal(got[0][1].view(np.uint32), got[1][1].view(np.uint32))
+    assert g.device_error() == 0
+
+
 def test_nprobe_one_and_all_lists():
     cfg, X, Q, nprobe, index, g, _ = case("c1")
     for npb in (1, cfg.L):
