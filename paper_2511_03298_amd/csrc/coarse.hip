@@ -142,52 +142,71 @@ __device__ __forceinline__ int32_t eq2_count(float p, int32_t vmin, int32_t vmax
 // The `want` smallest (ord(score), list) keys of one score row, held NK per
 // thread in registers (list = tid + 256 i), written to keys[0..want) in no
 // particular order. The want-th smallest ord is found by 4-bit radix passes
-// from the top: per-digit counts are packed 16-bit counters in each thread's
-// registers, summed by wave butterflies and, across the four waves, by 16
-// lanes of wave 0, which also scan them and pick the digit, so no LDS atomic
-// serialises on a popular digit. The passes stop as soon as the chosen digit
-// holds exactly the keys still needed (then every key whose top bits are at
-// most the prefix is taken); after all eight, keys equal to the want-th ord
-// are taken in ascending list order, each one's rank among them counted with
-// ballots. All threads; ends with a barrier. Needs want <= the number of keys
-// (ord 0xffffffff marks a missing key; finite scores never map to it).
+// from the top. Each thread counts its keys per digit in 8-bit fields (four
+// u32, digit d in byte d % 4 of word d / 4); the fields are then spread to
+// 16-bit ones and summed over the wave by a transposing butterfly (every
+// exchange hands half of the remaining counters to the partner lane, so 10
+// exchanges instead of 48), and across the four waves by 16 lanes of wave
+// 0, which also scan them and pick the digit: no LDS atomic serialises on a
+// popular digit. The passes stop as soon as the chosen digit holds exactly
+// the keys still needed (then every key whose top bits are at most the
+// prefix is taken); after all eight, keys equal to the want-th ord are taken
+// in ascending list order, each one's rank among them counted with ballots.
+// All threads; ends with a barrier. Needs want <= the number of keys (ord
+// 0xffffffff marks a missing key; finite scores never map to it).
 template <int NK>
 __device__ void row_select(const uint32_t (&o)[NK], int want, uint64_t* keys, uint32_t* cnt) {
+  static_assert(NK <= 64, "per-thread digit counts must fit 8 bits, wave sums 16 bits");
+  // wsum[wave][v]: 16-bit wave sums; word 2k holds digits 4k (low half) and
+  // 4k + 2 (high half), word 2k + 1 digits 4k + 1 and 4k + 3.
   __shared__ uint32_t wsum[IVF_NWAVES][8];
   __shared__ uint32_t rowc[NK][IVF_NWAVES];
   __shared__ uint32_t pick[3];  // digit, keys below it, 1 = the digit holds exactly the rest
   const int tid = threadIdx.x, wave = tid / IVF_WAVE, ln = lane_id();
+  const bool b5 = (ln & 32) != 0, b4 = (ln & 16) != 0, b3 = (ln & 8) != 0;
   uint32_t prefix = 0, pmask = 0;
   uint32_t need = (uint32_t)want;
   bool exact = false;  // stopped early: take every key with (o & pmask) <= prefix
   for (int shift = 28; shift >= 0; shift -= 4) {
-    uint32_t c[8];
-#pragma unroll
-    for (int w = 0; w < 8; ++w) c[w] = 0u;
+    uint32_t c4[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int i = 0; i < NK; ++i) {
       const uint32_t v = o[i];
       if (v != 0xffffffffu && (v & pmask) == prefix) {
         const uint32_t d = (v >> shift) & 15u;
-        const uint32_t inc = 1u << ((d & 1u) << 4);
+        const uint32_t inc = 1u << ((d & 3u) << 3);
 #pragma unroll
-        for (int w = 0; w < 8; ++w) c[w] += (d >> 1) == (uint32_t)w ? inc : 0u;
+        for (int k = 0; k < 4; ++k) c4[k] += (d >> 2) == (uint32_t)k ? inc : 0u;
       }
     }
-    // Per-thread counts <= NK <= 64 and wave sums <= 4096 fit the 16-bit fields.
+    uint32_t c[8];
 #pragma unroll
-    for (int w = 0; w < 8; ++w)
-      for (int s = 1; s < IVF_WAVE; s <<= 1) c[w] += __shfl_xor(c[w], s);
-    if (ln == 0)
+    for (int k = 0; k < 4; ++k) {
+      c[2 * k] = c4[k] & 0x00ff00ffu;
+      c[2 * k + 1] = (c4[k] >> 8) & 0x00ff00ffu;
+    }
+    // Transposing butterfly: after xor 32, 16 and 8, lane ln holds word
+    // ln >> 3 summed over the eight lanes that differ from it in bits 5..3;
+    // xor 4, 2 and 1 complete the wave sum.
+    uint32_t h4[4], h2[2];
 #pragma unroll
-      for (int w = 0; w < 8; ++w) wsum[wave][w] = c[w];
+    for (int i = 0; i < 4; ++i)
+      h4[i] = (b5 ? c[i + 4] : c[i]) + (uint32_t)__shfl_xor((int)(b5 ? c[i] : c[i + 4]), 32);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      h2[i] = (b4 ? h4[i + 2] : h4[i]) + (uint32_t)__shfl_xor((int)(b4 ? h4[i] : h4[i + 2]), 16);
+    uint32_t h1 = (b3 ? h2[1] : h2[0]) + (uint32_t)__shfl_xor((int)(b3 ? h2[0] : h2[1]), 8);
+#pragma unroll
+    for (int s = 4; s >= 1; s >>= 1) h1 += (uint32_t)__shfl_xor((int)h1, s);
+    if ((ln & 7) == 0) wsum[wave][ln >> 3] = h1;
     __syncthreads();
     if (wave == 0) {
       // Lane d < 16: the count of digit d; inclusive scan over the 16 lanes.
       const uint32_t d = (uint32_t)(ln & 15);
+      const uint32_t word = ((d >> 2) << 1) | (d & 1u), half = ((d >> 1) & 1u) << 4;
       uint32_t cd = 0;
 #pragma unroll
-      for (int w = 0; w < IVF_NWAVES; ++w) cd += (wsum[w][d >> 1] >> ((d & 1u) << 4)) & 0xffffu;
+      for (int w = 0; w < IVF_NWAVES; ++w) cd += (wsum[w][word] >> half) & 0xffffu;
       if (ln >= 16) cd = 0;
       uint32_t incl = cd;
       for (int off = 1; off < 16; off <<= 1) {
@@ -243,10 +262,11 @@ __device__ void row_select(const uint32_t (&o)[NK], int want, uint64_t* keys, ui
 }
 
 // Second half of the selection, shared by both kernels: keys[0..n) hold the
-// first selection. With `rescore` they are re-scored canonically and the
-// np best kept; then they are sorted (by rank into the free space behind
-// them when n <= 512 and 2n <= cap, else bitonic), the adaptive counts are
-// taken from the sorted scores, and the probe row is written.
+// first selection. With `rescore` they are re-scored canonically and, unless
+// n <= 256 (then the whole set is sorted and its first np keys used), cut to
+// the np best; then they are sorted (by rank into the free space behind them
+// when n <= 512 and 2n <= cap, else bitonic), the adaptive counts are taken
+// from the sorted scores, and the probe row is written.
 __device__ void select_finish(const Tables& t, const float* __restrict__ Q, int q, int np,
                               int max_nprobe, int rescore, uint64_t* keys, uint32_t n,
                               uint32_t cap, SelectScratch* sc, uint32_t* cnt, float* qv,
@@ -267,7 +287,10 @@ __device__ void select_finish(const Tables& t, const float* __restrict__ Q, int 
       keys[i] = make_key(canonical_score(t, staged ? qv : qg, l), (uint32_t)l);
     }
     __syncthreads();
-    if ((uint32_t)np < n) {
+    // A short widened set is sorted whole below: its first np keys are the
+    // np best. A longer one is cut to np first.
+    const bool sort_whole = n <= 256 && 2 * n <= cap;
+    if ((uint32_t)np < n && !sort_whole) {
       KeyUnion u{keys, n, nullptr, 0};
       n = block_compact_le(keys, n, block_kth(u, (uint32_t)np, sc), cnt);
     }
