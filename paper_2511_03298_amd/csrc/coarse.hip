@@ -350,9 +350,9 @@ __device__ __forceinline__ bool reject_row(int q, int np, int max_nprobe,
   return true;
 }
 
-// One workgroup per query, L <= 2048: the keys (ord(score) << 32 | list) of
-// the whole row in LDS ([cap] = pow2(L) slots) and the wanted count picked
-// by the byte-wise radix selection of common.hpp.
+// One workgroup per query, 1024 < L <= 2048: the keys (ord(score) << 32 |
+// list) of the whole row in LDS ([cap] = pow2(L) slots) and the wanted count
+// picked by the byte-wise radix selection of common.hpp.
 __global__ void __launch_bounds__(256) select_lds_kernel(Tables t, const float* __restrict__ Q,
                                                          int32_t nq, const int32_t* __restrict__ nprobe,
                                                          int32_t max_nprobe, int32_t widen,
@@ -383,10 +383,10 @@ __global__ void __launch_bounds__(256) select_lds_kernel(Tables t, const float* 
                 nprobe_eff, reorder_eff);
 }
 
-// One workgroup per query, larger L: the row stays in registers (NK keys per
-// thread, row_select) and LDS holds only the selection ([cap] = the largest
-// selection rounded up to a power of two, doubled up to 512 for the rank
-// sort's output).
+// One workgroup per query, L <= 1024 or L > 2048: the row stays in
+// registers (NK keys per thread, row_select) and LDS holds only the selection
+// ([cap] = the largest selection rounded up to a power of two, doubled up to
+// 512 for the rank sort's output).
 template <int NK>
 __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __restrict__ Q,
                                                      int32_t nq, const int32_t* __restrict__ nprobe,
@@ -427,10 +427,12 @@ hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
   if (nq == 0) return hipSuccess;
   const int32_t most = rescore ? std::min(t.L, max_nprobe * widen) : max_nprobe;
   const int nk = (t.L + IVF_BLOCK - 1) / IVF_BLOCK;
-  // Short rows: the whole row in LDS; longer ones: registers, so LDS (and
+  // Rows of 1025..2048 lists: the whole row in LDS (measured faster there
+  // than the register form); shorter and longer rows: registers, so LDS (and
   // occupancy) depends only on the selection size.
+  const bool lds_row = nk > 4 && nk <= 8;
   const uint32_t sel = pow2_ceil((uint32_t)(most > 0 ? most : 1));
-  const uint32_t cap = nk <= 8 ? pow2_ceil((uint32_t)t.L) : (sel > 512 ? sel : 2 * sel);
+  const uint32_t cap = lds_row ? pow2_ceil((uint32_t)t.L) : (sel > 512 ? sel : 2 * sel);
   const size_t lds = (size_t)cap * sizeof(uint64_t);
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(nq), dim3(256), lds, s, t, Q, nq, nprobe, max_nprobe, widen,
@@ -438,6 +440,7 @@ hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
                        w.reorder_eff, cap);
     return hipGetLastError();
   };
+  if (nk <= 4) return go(select_kernel<4>);
   if (nk <= 8) return go(select_lds_kernel);
   if (nk <= 16) return go(select_kernel<16>);
   if (nk <= 32) return go(select_kernel<32>);
