@@ -79,31 +79,31 @@ hipError_t launch_coarse_exact(const Tables& t, const float* Q, int32_t nq, floa
   return hipGetLastError();
 }
 
-// Canonical score of one (query, list) pair, one thread, sequential over t.
-// Rows are fetched in 16-byte vectors when d is a multiple of 4, 16 vectors
-// (64 floats) requested before any is used, since the rows come from the
-// caches with long latency; the accumulation order is the same in both paths.
-__device__ __forceinline__ float canonical_score(const Tables& t, const float* q, int l) {
-  const float* c = t.cp + (size_t)l * t.d;
-  const bool ip = t.metric == IVF_METRIC_IP;
+// Sequential FP32 sum over t = 0..d-1 of q_t c_t (IP) or (q_t - c_t)^2
+// (L2), one thread. Rows are fetched in 16-byte vectors when d is a multiple
+// of 4, 16 vectors (64 floats) requested before any is used, since the rows
+// come from the caches with long latency; the accumulation order is the
+// same in both paths.
+template <bool IP>
+__device__ __forceinline__ float seq_row_sum(const float* q, const float* c, int d) {
   float acc = 0.0f;
   int i = 0;
-  if ((t.d & 3) == 0) {
+  if ((d & 3) == 0) {
     constexpr int NV = 16;
     const float4* c4 = reinterpret_cast<const float4*>(c);
-    for (; i < t.d; i += 4 * NV) {
+    for (; i < d; i += 4 * NV) {
       float4 v[NV];
 #pragma unroll
       for (int k = 0; k < NV; ++k)
-        v[k] = i + 4 * k < t.d ? c4[(i >> 2) + k] : make_float4(0, 0, 0, 0);
+        v[k] = i + 4 * k < d ? c4[(i >> 2) + k] : make_float4(0, 0, 0, 0);
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         const float cv[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int ii = i + 4 * k + e;
-          if (ii < t.d) {
-            if (ip) {
+          if (ii < d) {
+            if (IP) {
               acc = acc + q[ii] * cv[e];
             } else {
               const float df = q[ii] - cv[e];
@@ -114,8 +114,8 @@ __device__ __forceinline__ float canonical_score(const Tables& t, const float* q
       }
     }
   } else {
-    for (; i < t.d; ++i) {
-      if (ip) {
+    for (; i < d; ++i) {
+      if (IP) {
         acc = acc + q[i] * c[i];
       } else {
         const float df = q[i] - c[i];
@@ -123,7 +123,14 @@ __device__ __forceinline__ float canonical_score(const Tables& t, const float* q
       }
     }
   }
-  return ip ? plus_zero(-acc) : acc;
+  return acc;
+}
+
+// Canonical score of one (query, list) pair against the probe centroid.
+__device__ __forceinline__ float canonical_score(const Tables& t, const float* q, int l) {
+  const float* c = t.cp + (size_t)l * t.d;
+  if (t.metric == IVF_METRIC_IP) return plus_zero(-seq_row_sum<true>(q, c, t.d));
+  return seq_row_sum<false>(q, c, t.d);
 }
 
 // Eq. 2 (section 4.2) in FP32, in the order written: the adaptive count
@@ -495,23 +502,9 @@ __global__ void __launch_bounds__(256) bias_kernel(Tables t, const float* __rest
   if (np <= 0) return;  // uniform
   for (int i = threadIdx.x; i < t.d; i += blockDim.x) qs[i] = Q[(size_t)q * t.d + i];
   __syncthreads();
-  const bool vec = (t.d & 3) == 0;
   for (int p = threadIdx.x; p < np; p += blockDim.x) {
     const int l = probes[(size_t)q * max_nprobe + p];
-    const float* c = t.cm + (size_t)l * t.d;
-    float acc = 0.0f;
-    if (vec) {
-      const float4* c4 = reinterpret_cast<const float4*>(c);
-      for (int k4 = 0; k4 < t.d / 4; ++k4) {
-        const float4 v = c4[k4];
-        acc = acc + qs[4 * k4 + 0] * v.x;
-        acc = acc + qs[4 * k4 + 1] * v.y;
-        acc = acc + qs[4 * k4 + 2] * v.z;
-        acc = acc + qs[4 * k4 + 3] * v.w;
-      }
-    } else {
-      for (int k = 0; k < t.d; ++k) acc = acc + qs[k] * c[k];
-    }
+    const float acc = seq_row_sum<true>(qs, t.cm + (size_t)l * t.d, t.d);
     bias[(size_t)q * max_nprobe + p] = plus_zero(-acc);
   }
 }
