@@ -878,9 +878,10 @@ def _long_row_index(ivf, L, d, metric, seed, groups=None):
     return g, C
 
 
-@pytest.mark.parametrize("L,metric,groups", [(3000, "l2", None), (3000, "l2", 7),
-                                             (9000, "ip", None), (4100, "ip", 16),
-                                             (16384, "l2", None)])
+@pytest.mark.parametrize("L,metric,groups", [(1024, "l2", 7), (1500, "l2", None),
+                                             (2048, "ip", 16), (3000, "l2", None),
+                                             (3000, "l2", 7), (9000, "ip", None),
+                                             (4100, "ip", 16), (16384, "l2", None)])
 def test_long_row_selection_bit_exact(L, metric, groups):
     import paper_2511_03298_amd as ivf
     _gpu()
