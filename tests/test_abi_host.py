@@ -231,3 +231,56 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         ivf.GpuIndex(np.zeros((4, 2), np.float32), np.zeros((1, 2), np.float32),
                      np.zeros((1, 16, 2), np.float32), np.zeros((4, 1), np.uint8), [0, 4],
                      np.arange(4, dtype=np.int32), "l2", device="cpu")
+
+
+def test_header_is_plain_c_and_matches_the_binding(tmp_path):
+    # A C99 program (warnings as errors) includes the public header, links
+    # against the library and calls its host-only entry points; it prints
+    # every struct's size and field offsets, which must equal the binding's
+    # ctypes layouts (a field the binding names but the header lacks fails
+    # the compile).
+    import shutil
+    import subprocess
+    ivf, _ = _lib()
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"ivf_index_desc": ivf.IndexDesc, "ivf_search_opts": ivf.SearchOpts,
+               "ivf_table_layout": ivf.TableLayout}
+    lines = []
+    for cname, ct in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in ct._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    src = tmp_path / "abi_check.c"
+    src.write_text("\n".join([
+        "#include <stddef.h>", "#include <stdio.h>", "#include <string.h>", '#include "ivf.h"',
+        "int main(void) {",
+        "  ivf_search_opts o;",
+        "  ivf_index_desc d;",
+        "  memset(&o, 0xff, sizeof o);",
+        "  ivf_default_opts(&o);",
+        "  if (o.form != IVF_FORM_PLAIN || o.widen < 1) return 1;",
+        "  memset(&d, 0, sizeof d);",
+        "  if (ivf_tables_bytes(&d) != 0) return 2;",
+        "  if (strlen(ivf_last_error()) == 0) return 3;",
+        *lines,
+        "  return 0;",
+        "}", ""]))
+    exe = tmp_path / "abi_check"
+    libdir = os.path.dirname(ivf.LIB_PATH)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                        "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                        "-L", libdir, "-l:libivfpq.so", f"-Wl,-rpath,{libdir}"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, (r.returncode, r.stderr)
+    got = {}
+    for line in r.stdout.splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, ct in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(ct), cname
+        for fname, _ in ct._fields_:
+            assert got[(cname, fname)] == getattr(ct, fname).offset, (cname, fname)
