@@ -188,7 +188,9 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem,
                             size_t table_bytes, void* stream, ivf_index** out);
 
 /* Bytes of workspace one ivf_search call with these sizes needs; 0 if the
- * arguments are invalid. max_nprobe bounds every nprobe[q]. */
+ * arguments are invalid. max_nprobe bounds every nprobe[q]. Every search
+ * entry point takes 0 <= nq <= 2^20 queries per call (larger batches are
+ * split by the caller), as the assignment calls take at most 2^20 rows. */
 size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq,
                                   int32_t max_nprobe, int32_t k,
                                   int32_t rerank, const ivf_search_opts* opts);

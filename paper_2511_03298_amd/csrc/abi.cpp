@@ -198,7 +198,8 @@ ivf_status check_opts(const ivf_search_opts& o) {
 ivf_status check_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, int32_t k,
                         int32_t rerank) {
   if (!idx) return fail(IVF_ERR_INVALID_ARG, "index is NULL");
-  if (nq < 0) return fail(IVF_ERR_INVALID_ARG, "nq must be >= 0");
+  if (nq < 0 || nq > MAX_QUERIES)
+    return fail(IVF_ERR_INVALID_ARG, "nq must be in [0, 2^20] per call");
   if (max_nprobe < 1 || max_nprobe > idx->t.L)
     return fail(IVF_ERR_INVALID_ARG, "max_nprobe must be in [1, L]");
   if (rerank < 1 || rerank > MAX_RERANK)
@@ -787,7 +788,8 @@ ivf_status ivf_debug_luts(const ivf_index* idx, const float* queries, int32_t nq
                           uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
                           void* stream) {
   if (!idx) return fail(IVF_ERR_INVALID_ARG, "index is NULL");
-  if (nq < 0) return fail(IVF_ERR_INVALID_ARG, "nq must be >= 0");
+  if (nq < 0 || nq > MAX_QUERIES)
+    return fail(IVF_ERR_INVALID_ARG, "nq must be in [0, 2^20] per call");
   if (max_nprobe < 1 || max_nprobe > idx->t.L)
     return fail(IVF_ERR_INVALID_ARG, "max_nprobe must be in [1, L]");
   if (nq == 0) return IVF_OK;

@@ -13,6 +13,7 @@ constexpr int KSUB = 16;          // codewords per subspace (4-bit codes)
 constexpr int BLOCK_PTS = 64;     // points per packed block (one wavefront)
 constexpr int MAX_M = 256;
 constexpr int MAX_RERANK = 2048;
+constexpr int MAX_QUERIES = 1 << 20;  // queries per search call
 constexpr int MAX_L = 1 << 20;
 constexpr int TILE_L = 64;        // low-precision centroid tables: L padded to this
 constexpr int TILE_D = 64;        // ... and d padded to this

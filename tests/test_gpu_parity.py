@@ -180,6 +180,19 @@ def test_two_streams_in_flight(form):
     assert g.device_error() == 0
 
 
+def test_query_count_limit():
+    # More than 2^20 queries per call are rejected on the host before any
+    # device work; 2^20 itself is a valid size.
+    import ctypes
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case("c1")
+    o = ivf.make_opts()
+    lib = ivf.lib()
+    assert lib.ivf_search_workspace_bytes(g._h, 1 << 20, 1, 1, 1, ctypes.byref(o)) > 0
+    assert lib.ivf_search_workspace_bytes(g._h, (1 << 20) + 1, 1, 1, 1, ctypes.byref(o)) == 0
+    assert "2^20" in ivf.last_error()
+
+
 def test_nprobe_one_and_all_lists():
     cfg, X, Q, nprobe, index, g, _ = case("c1")
     for npb in (1, cfg.L):
