@@ -50,7 +50,7 @@ typedef enum {
   IVF_ERR_INVALID_ARG = 1, /* bad size, pointer, enum or combination       */
   IVF_ERR_DEVICE = 2,      /* no usable gfx950 device, or a HIP call failed */
   IVF_ERR_WORKSPACE = 3,   /* table memory or workspace too small          */
-  IVF_ERR_UNSUPPORTED = 4, /* valid request this build does not implement  */
+  IVF_ERR_UNSUPPORTED = 4, /* valid request the library does not implement */
   IVF_ERR_INTERNAL = 5
 } ivf_status;
 
