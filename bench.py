@@ -6,10 +6,12 @@ scoring, top-nprobe, LUT build + ADC scan + candidate pool, exact re-rank),
 with the index and queries already resident in HBM. Prints one JSON line on
 stdout; progress goes to stderr.
 
-Workload (default): 1,000,000 integer-valued 128-d vectors in [0, 255] from a
-seeded 1000-component mixture (SIFT/BIGANN-like, squared L2), 10,000 queries
-from the same mixture, 1024 lists, PQ with 64 subspaces x 16 codewords
-(4-bit codes), nprobe 32, k 10, re-rank 200.
+Workload (default): 10,000,000 unit-normalised 768-d embedding-like vectors
+stored as BF16 (seeded anisotropic mixture, inner product), a batch of 4096
+queries with per-query nprobe drawn from 4..256, 8192 lists, PQ with 192
+subspaces x 16 codewords (4-bit codes), k 10, FP32-accumulated re-rank of 256
+candidates. `--config c2` selects the 1M x 128 integer-valued L2 workload
+(SIFT/BIGANN-like, 10,000 queries, 1024 lists, m 64, nprobe 32, R 200).
 """
 
 from __future__ import annotations
@@ -31,9 +33,13 @@ from workloads import (CONFIGS, exact_knn, make_workload, recall_at_k, spill_ind
 
 METRIC_NAME = "QPS at recall@10=0.90, 1 GPU: plain vs BF16+batched; ADC-scan HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# Lookup roofline of the vector ALUs: 256 CUs x 64 lanes per clock x 2.4 GHz,
-# two table lookups accumulated per packed 16-bit add.
-LOOKUP_PEAK_T = 256 * 64 * 2.4e9 * 2 / 1e12
+# Lookup roofline of the batched scan: every lookup reads one 16-bit table
+# entry from LDS, and a CU's LDS returns 256 bytes per clock: 128 lookups per
+# clock per CU, x 256 CUs x 2.4 GHz = 78.6 T lookups/s. (The vector ALUs are
+# not the bound: one 3-input add consumes four entries per lane, 256 lookups
+# per clock per CU.)
+LDS_BYTES_PER_CLK = 256
+LOOKUP_PEAK_T = 256 * 2.4e9 * LDS_BYTES_PER_CLK / 2 / 1e12
 
 # HBM traffic of the dominant scan kernel, from rocprofv3 --pmc FETCH_SIZE
 # and --pmc WRITE_SIZE runs (KiB per dispatch, the mean of the timed
@@ -84,10 +90,58 @@ def log(*a):
 
 
 # ---------------------------------------------------------------------------
-# CPU baseline: the oracle, timed on the host cores (forked before GPU init).
+# CPU baseline: the oracle timed on the host cores. Its worker processes are
+# forked from a child that is itself forked right after the data are drawn,
+# before anything touches the GPU; the trained index reaches it as .npy files.
 # ---------------------------------------------------------------------------
 
 _CPU = {}
+INDEX_ARRAYS = ("cm", "cp", "codebooks", "codes", "list_offsets", "list_ids", "dims")
+
+
+def _host(a):
+    return a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+
+
+def save_index(index, path):
+    """Write the index arrays (numpy or device tensors) as .npy files."""
+    os.makedirs(path, exist_ok=True)
+    meta = {k: index[k] for k in ("metric", "copies", "d_base") if k in index}
+    for k in INDEX_ARRAYS:
+        if index.get(k) is not None:
+            np.save(os.path.join(path, k + ".npy"), _host(index[k]))
+    json.dump(meta, open(os.path.join(path, "meta.json"), "w"))
+
+
+def load_index(path, mmap=False):
+    index = json.load(open(os.path.join(path, "meta.json")))
+    for k in INDEX_ARRAYS:
+        f = os.path.join(path, k + ".npy")
+        if os.path.exists(f):
+            index[k] = np.load(f, mmap_mode="r" if mmap else None)
+    return index
+
+
+def physical_cores():
+    """Physical cores of the host (unique (core, socket) pairs of lscpu)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True,
+                             timeout=20).stdout
+        pairs = {ln.strip() for ln in out.splitlines() if ln and not ln.startswith("#")}
+        return len(pairs) or None
+    except (OSError, subprocess.SubprocessError):
+        return None
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def _cpu_worker(span):
@@ -103,36 +157,82 @@ def _cpu_worker(span):
         return time.perf_counter() - t0
 
 
-def cpu_baseline(index, X, Q, nprobe, k, R, seconds_per_worker=1.0):
+def _cpu_server(conn, X, Q, nprobe, k, R, per_worker):
+    """Child process: wait for the index path, time the oracle, send the row."""
     import multiprocessing as mp
 
+    from threadpoolctl import threadpool_limits
+
     import oracle
+    try:
+        path = conn.recv()
+    except EOFError:  # the parent ended without handing over an index
+        return
+    if path is None:
+        return
+    index = load_index(path, mmap=True)
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
-    t0 = time.perf_counter()
-    oracle.search(index, X, Q[:2], nprobe[:2], k, R)
-    per_query = (time.perf_counter() - t0) / 2
-    per_worker = max(2, int(seconds_per_worker / max(per_query, 1e-6)))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.search(index, X, Q[:2], nprobe[:2], k, R)
+        per_query = (time.perf_counter() - t0) / 2
+    # At least 8 queries per worker; 32 unless that would take over ~30 s.
+    per_worker = max(8, min(per_worker, int(30.0 / max(per_query, 1e-6))))
     _CPU.update(index=index, X=X, Q=Q, nprobe=nprobe, k=k, R=R)
     spans = [(w * per_worker, (w + 1) * per_worker) for w in range(workers)]
-    ctx = mp.get_context("fork")
-    with ctx.Pool(workers) as pool:
+    with mp.get_context("fork").Pool(workers) as pool:
         t0 = time.perf_counter()
         pool.map(_cpu_worker, spans)
         wall = time.perf_counter() - t0
     total = workers * per_worker
-    model = "unknown CPU"
-    try:
-        for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                model = ln.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {"value": round(total / wall, 1), "unit": "queries/s", "cores": workers,
-            "kind": "oracle",
-            "sample": f"{total} queries ({per_worker} per worker process, one process per core, "
-                      f"single-threaded numpy), same index, nprobe, k and rerank; "
-                      f"wall {wall:.1f} s; {model}"}
+    phys = physical_cores()
+    conn.send({"value": round(total / wall, 1), "unit": "queries/s", "cores": workers,
+               "kind": "oracle", "physical_cores": phys,
+               "sample": f"{total} queries (the first {min(total, len(Q))} of the batch, "
+                         f"{per_worker} per worker process, one single-threaded process per "
+                         f"core on {workers} of the host's {phys} physical cores), same index, "
+                         f"nprobe, k and rerank as the GPU run; wall {wall:.1f} s; {cpu_model()}"})
+
+
+class CpuBaseline:
+    """Forks the oracle's timing process now (no GPU state yet); run(index)
+    hands it the trained index and waits for its result."""
+
+    def __init__(self, X, Q, nprobe, k, R, per_worker=32):
+        import multiprocessing as mp
+        ctx = mp.get_context("fork")
+        self.conn, child = ctx.Pipe()
+        # Not a daemon: it forks the worker pool itself. close() ends it.
+        self.proc = ctx.Process(target=_cpu_server, args=(child, X, Q, nprobe, k, R, per_worker))
+        self.proc.start()
+        self.done = False
+
+    def run(self, index):
+        import shutil
+        import tempfile
+        base = "/dev/shm" if os.access("/dev/shm", os.W_OK) else None
+        path = tempfile.mkdtemp(prefix="ivf_oracle_", dir=base)
+        try:
+            save_index(index, path)
+            self.conn.send(path)
+            out = self.conn.recv()
+            self.done = True
+        finally:
+            self.close()
+            shutil.rmtree(path, ignore_errors=True)
+        return out
+
+    def close(self):
+        if not self.done:
+            self.done = True
+            try:
+                self.conn.send(None)
+            except (OSError, ValueError):
+                pass
+        self.proc.join(timeout=60)
+        if self.proc.is_alive():
+            self.proc.terminate()
+            self.proc.join(timeout=10)
 
 
 # ---------------------------------------------------------------------------
@@ -183,25 +283,50 @@ def distance_error(ids, dist, X, Q, metric):
     return worst
 
 
+def scan_kernel_name(form, cfg):
+    """The scan-stage kernel of a form, with its template arguments."""
+    words = (cfg.m + 7) // 8
+    if form == "batched":
+        bg = 8 if words * 8 > 96 else 16
+        return (f"batched_scan_kernel<{words}, {'true' if cfg.metric == 'ip' else 'false'}, {bg}> "
+                f"(list-major work items of {bg} queries: tables in LDS, ADC scan, survivors)")
+    return f"scan_plain_kernel<{words}> (one workgroup per query: table build, ADC scan, top-R pool)"
+
+
+# Code arrays small enough to stay in the caches between launches: their
+# scan is not bound by HBM reads.
+CACHE_RESIDENT = {"c1", "c2", "c3", "c6"}
+
+
 def roofline(config, cfg, r, code_bytes):
-    """Roofline of the dominant kernel (the scan stage's kernel) of form r."""
-    kernel = ("batched_scan_kernel (list-major: 16-query tables, ADC scan, survivors)"
-              if r["form"] == "batched" else
-              "scan_plain_kernel (per-query: table build, ADC scan, top-R pool)")
-    code_total = {"c2": 32e6, "c3": 30e6, "c1": 80e3}.get(config, None)
-    streaming = r["form"] == "plain" and code_total is None  # code array >> caches
+    """Roofline of the dominant kernel (the scan stage's kernel) of form r.
+
+    achieved = algorithmic work of the launches of one step / their summed
+    duration (HIP events around the scan stage, on the search stream). The
+    batched form reuses each list's codes for a work item's queries, so it is
+    bound by table lookups (m per query and scanned point) against the LDS
+    lookup peak; the plain form streams ceil(m/2) code bytes per query and
+    point, from HBM when the code array exceeds the caches."""
+    streaming = r["form"] == "plain" and config not in CACHE_RESIDENT
     alg_bytes = r["scan_points"] * code_bytes
-    out = {"kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes,
-           "traffic": recorded_traffic(config, r["form"])}
+    traffic = recorded_traffic(config, r["form"])
+    out = {"kernel": scan_kernel_name(r["form"], cfg), "algorithmic_bytes_per_step": alg_bytes,
+           "traffic": traffic,
+           "traffic_source": (None if traffic is None else
+                              "recorded rocprofv3 FETCH_SIZE + WRITE_SIZE of the same kernel "
+                              "sources (profiles/), scaled by a 1 GiB copy; bytes per step")}
     if streaming:
-        out.update(bound="hbm", achieved=round(r["scan_gbs"], 1), peak=HBM_PEAK_GBS,
-                   unit="GB/s", frac=round(r["scan_gbs"] / HBM_PEAK_GBS, 4))
+        out.update(bound="hbm", achieved=round(r["scan_alg_gbs"], 1), peak=HBM_PEAK_GBS,
+                   unit="GB/s", frac=round(r["scan_alg_gbs"] / HBM_PEAK_GBS, 4))
+        if traffic is not None and r["stage_ms"].get("scan"):
+            out["traffic_gbs"] = round(traffic / (r["stage_ms"]["scan"] / 1e3) / 1e9, 1)
+            out["traffic_frac"] = round(out["traffic_gbs"] / HBM_PEAK_GBS, 4)
     else:
-        # Code arrays of tens of MB stay in L2 / Infinity Cache: the scan is
-        # bound by table lookups on the vector ALUs (m per query and point).
-        out.update(bound="alu", achieved=round(r["scan_tlookups"], 3), peak=round(LOOKUP_PEAK_T, 2),
-                   unit="T lookups/s", frac=round(r["scan_tlookups"] / LOOKUP_PEAK_T, 4),
-                   algorithmic_lookups_per_launch=r["scan_points"] * cfg.m)
+        out.update(bound="alu", achieved=round(r["scan_tlookups"], 3),
+                   peak=round(LOOKUP_PEAK_T, 2), unit="T lookups/s",
+                   frac=round(r["scan_tlookups"] / LOOKUP_PEAK_T, 4),
+                   peak_basis="LDS: 256 B/clk/CU / 2 B per u16 table entry x 256 CUs x 2.4 GHz",
+                   algorithmic_lookups_per_step=r["scan_points"] * cfg.m)
     return out
 
 
@@ -240,14 +365,21 @@ def sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args):
 
     top = int(base.max())
     seen = set()
-    for f in (1 / 32, 1 / 16, 1 / 8, 1 / 4, 1 / 2, 1.0, 1.5, 2.0):
-        nprobe = torch.clamp((base.double() * f).round().to(torch.int32), 1, cfg.L)
+    # Uniform-nprobe workloads: a ladder of nprobe values; per-query ones: the
+    # per-query draws scaled by a factor (clamped to [1, L]).
+    if cfg.nprobe[0] == cfg.nprobe[1]:
+        settings = [(f"static nprobe {v}", torch.full_like(base, v)) for v in
+                    (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256) if v <= cfg.L]
+    else:
+        settings = [(f"static x{f:g}", (base.double() * f).round())
+                    for f in (1 / 16, 1 / 8, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0)]
+    for label, raw in settings:
+        nprobe = torch.clamp(raw.to(torch.int64), 1, cfg.L).to(torch.int32)
         sig = (int(nprobe.min()), int(nprobe.max()), int(nprobe.sum()))
         if sig in seen:
             continue
         seen.add(sig)
-        run(f"static x{f:g}", ivf.make_opts(form="batched", coarse="bf16"), nprobe,
-            int(nprobe.max()))
+        run(label, ivf.make_opts(form="batched", coarse="bf16"), nprobe, int(nprobe.max()))
     # Adaptive (Eq. 2): the configured nprobe is the maximum per query.
     for nmin, p0 in ((1, 0.3), (1, 0.6), (1, 0.9), (max(1, top // 8), 0.6)):
         ad = dict(nprobe_init=8, nprobe_min=nmin, reorder_min=max(cfg.k, cfg.R // 2),
@@ -296,12 +428,54 @@ def batch_sweep(g, cfg, Qd, npd, gt_ids, nrec, args):
     return out
 
 
+def _cache_key(args, cfg):
+    return (f"{args.config}_n{cfg.n}_s{cfg.sigma:g}_f{args.filter}_soar{args.soar}"
+            .replace(".", "p"))
+
+
+def build_index(args, cfg, X, log):
+    """Train the index (host trainer; the GPU one for the 10M-point shapes),
+    or load it from --cache-dir when an earlier run saved it."""
+    gpu_trained = cfg.n > 2_000_000
+    dims = None
+    cache = os.path.join(args.cache_dir, _cache_key(args, cfg)) if args.cache_dir else None
+    if cache and os.path.exists(os.path.join(cache, "meta.json")):
+        log(f"loading the trained index from {cache}")
+        return load_index(cache), gpu_trained, True
+    if args.filter is not None:
+        from paper_2511_03298_amd.train import component_filter
+        dims = component_filter(X, args.filter)
+        log(f"component filtration at {args.filter}: {len(dims)} of {cfg.d} dims kept")
+    if gpu_trained:
+        # 10M-point shapes: assignment and encoding on the GPU (ivf_assign /
+        # ivf_encode); the host trainer would take many minutes.
+        from paper_2511_03298_amd.train import train_index_gpu
+        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index, log=log, dims=dims,
+                                soar=args.soar)
+    else:
+        index = train_index(X, cfg, dims=dims)
+        if args.soar is not None:
+            if dims is not None:
+                raise SystemExit("--soar with --filter needs the GPU trainer")
+            log(f"SOAR spill lists (lambda {args.soar})")
+            index = spill_index(X, index, args.soar)
+    if cache:
+        save_index(index, cache)
+    return index, gpu_trained, False
+
+
+def path_dtype(coarse):
+    """Arithmetic types of a form: coarse operands, 8-bit tables with integer
+    sums, FP32 re-rank."""
+    return {"exact": "f32", "f32": "f32", "bf16": "bf16", "fp8": "fp8"}[coarse] + "+u8+f32"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
     ap.add_argument("--forms", default="plain:exact,batched:bf16",
                     help="comma list of form:coarse[:rN], e.g. plain:exact,batched:bf16:r3 "
                          "(rN: N threshold-tightening rounds of the batched form)")
@@ -321,6 +495,8 @@ def main():
     ap.add_argument("--base-dtype", default=None, choices=("f32", "bf16", "u8"),
                     help="storage of the raw rows for the exact re-rank (default: the "
                          "workload's); u8 needs integer components in [0, 255]")
+    ap.add_argument("--sigma", type=float, default=None,
+                    help="override the mixture spread of the workload (generator calibration)")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure static nprobe values and adaptive (Eq. 2) settings with "
                          "the batched BF16 form; adds a 'sweep' list to the JSON line")
@@ -330,6 +506,9 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this many MiB before timing (a kernel of "
                          "known traffic for scaling FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--cache-dir", default=None,
+                    help="save the trained index and the ground truth here, and load them "
+                         "from here in later runs with the same workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -340,46 +519,45 @@ def main():
     cfg = CONFIGS[args.config]
     if args.base_dtype:
         cfg = dataclasses.replace(cfg, base_dtype=args.base_dtype)
+    if args.sigma is not None:
+        cfg = dataclasses.replace(cfg, sigma=args.sigma)
     t0 = time.time()
-    log(f"generating {args.config}: n={cfg.n} d={cfg.d} nq={cfg.nq}")
+    log(f"generating {args.config}: n={cfg.n} d={cfg.d} nq={cfg.nq} sigma={cfg.sigma}")
     X, Q, nprobe = make_workload(cfg, log=log)
     log(f"generated in {time.time() - t0:.1f}s; training IVF-PQ (L={cfg.L}, m={cfg.m})")
+    # The oracle's timing process is forked now, before the GPU is touched.
+    cpu_job = None if args.no_cpu_baseline else CpuBaseline(X, Q, nprobe, cfg.k, cfg.R)
     t0 = time.time()
-    gpu_trained = cfg.n > 2_000_000
-    dims = None
-    if args.filter is not None:
-        from paper_2511_03298_amd.train import component_filter
-        dims = component_filter(X, args.filter)
-        log(f"component filtration at {args.filter}: {len(dims)} of {cfg.d} dims kept")
-    if gpu_trained:
-        # 10M-point shapes: assignment and encoding on the GPU (ivf_assign /
-        # ivf_encode); the host trainer would take many minutes.
-        from paper_2511_03298_amd.train import train_index_gpu
-        index = train_index_gpu(X, cfg.L, cfg.m, cfg.metric, seed=cfg.index, log=log, dims=dims,
-                                soar=args.soar)
-    else:
-        index = train_index(X, cfg, dims=dims)
-        if args.soar is not None:
-            if dims is not None:
-                raise SystemExit("--soar with --filter needs the GPU trainer")
-            log(f"SOAR spill lists (lambda {args.soar})")
-            index = spill_index(X, index, args.soar)
+    try:
+        index, gpu_trained, loaded = build_index(args, cfg, X, log)
+    except BaseException:
+        if cpu_job is not None:
+            cpu_job.close()
+        raise
     copies = int(index.get("copies", 1))
+    dims = index.get("dims")
     if dims is not None:
         cfg = dataclasses.replace(cfg, m=int(index["codebooks"].shape[0]))
     lens = np.diff(index["list_offsets"])
-    log(f"trained in {time.time() - t0:.1f}s ({'GPU' if gpu_trained else 'host'}); "
+    log(f"index ready in {time.time() - t0:.1f}s ({'cache' if loaded else 'GPU' if gpu_trained else 'host'}); "
         f"list length mean {lens.mean():.0f} max {lens.max()}")
 
     cpu = None
-    if not args.no_cpu_baseline and not gpu_trained:
+    if cpu_job is not None:
         log("timing the CPU oracle on the host cores")
-        cpu = cpu_baseline(index, X, Q, nprobe, cfg.k, cfg.R)
-        log(f"oracle: {cpu['value']} q/s on {cpu['cores']} cores")
+        cpu = cpu_job.run(index)
+        log(f"oracle: {cpu['value']} q/s on {cpu['cores']} cores ({cpu['sample']})")
 
     nrec = min(args.recall_queries, cfg.nq)
     t0 = time.time()
-    gt_ids, _ = exact_knn(X, Q[:nrec], 10, cfg.metric, log=log)
+    gt_file = (os.path.join(args.cache_dir, _cache_key(args, cfg), f"truth{nrec}.npy")
+               if args.cache_dir else None)
+    if gt_file and os.path.exists(gt_file):
+        gt_ids = np.load(gt_file)
+    else:
+        gt_ids, _ = exact_knn(X, Q[:nrec], 10, cfg.metric, log=log)
+        if gt_file:
+            np.save(gt_file, gt_ids)
     log(f"FP64 ground truth for {nrec} queries in {time.time() - t0:.1f}s")
 
     import torch
@@ -394,6 +572,7 @@ def main():
         log(f"copy calibration: one copy kernel reading {nbytes} B and writing {nbytes} B")
         del src, dst
     g = ivf.GpuIndex.from_index(index, X, base_dtype=cfg.base_dtype)
+    del index
     Qd = torch.from_numpy(Q).cuda()
     npd = torch.from_numpy(nprobe).cuda()
     max_np = int(nprobe.max())
@@ -436,44 +615,59 @@ def main():
     for label, opts in runs:
         od = ivf.opts_dict(opts)
         form, coarse = od["form"], od["coarse"]
-        for _ in range(args.warmup):
-            g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
-        torch.cuda.synchronize()
-        g.profile(True)
-        g.profile_read()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        stage_ms, count = g.profile_read()
-        g.profile(False)
-        ms_step = wall * 1000.0 / args.steps
-        ids_h, dist_h = ids[:nrec].cpu().numpy(), dist[:nrec].cpu().numpy()
-        rec = recall_at_k(ids_h, gt_ids, 10)
-        derr = distance_error(ids_h, dist_h, X, Q[:nrec], cfg.metric)
-        # Secondary: the same steps with the results copied to the host.
-        t0 = time.perf_counter()
-        for _ in range(max(2, args.steps // 2)):
-            g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
-            ids.cpu(), dist.cpu()
-        d2h_ms = (time.perf_counter() - t0) * 1000.0 / max(2, args.steps // 2)
+        # Graph-captured schedules run on a side stream (capture needs one).
+        stream = torch.cuda.Stream() if od["use_graph"] else torch.cuda.current_stream()
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
+            torch.cuda.synchronize()
+            g.profile(not od["use_graph"])
+            g.profile_read()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            stage_ms, count = g.profile_read()
+            g.profile(False)
+            if od["use_graph"]:
+                # Per-stage times of the same schedule run eagerly (replays
+                # of a captured graph are not profiled).
+                eager = ivf.make_opts(**{k_: v for k_, v in od.items() if k_ != "use_graph"})
+                g.profile(True)
+                g.profile_read()
+                for _ in range(max(3, args.steps // 2)):
+                    g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=eager,
+                             out=(ids, dist))
+                torch.cuda.synchronize()
+                stage_ms, count = g.profile_read()
+                g.profile(False)
+            ms_step = wall * 1000.0 / args.steps
+            ids_h, dist_h = ids[:nrec].cpu().numpy(), dist[:nrec].cpu().numpy()
+            rec = recall_at_k(ids_h, gt_ids, 10)
+            derr = distance_error(ids_h, dist_h, X, Q[:nrec], cfg.metric)
+            # Secondary: the same steps with the results copied to the host.
+            t0 = time.perf_counter()
+            for _ in range(max(2, args.steps // 2)):
+                g.search(Qd, npd, cfg.k, cfg.R, max_nprobe=max_np, opts=opts, out=(ids, dist))
+                ids.cpu(), dist.cpu()
+            d2h_ms = (time.perf_counter() - t0) * 1000.0 / max(2, args.steps // 2)
         per = {k_: v / max(count, 1) for k_, v in stage_ms.items()}
         scan_ms = per["scan"]
         pts = scanned_main if form == "batched" else scanned
-        r = dict(form=form, coarse=coarse, schedule=label, opts=od,
+        r = dict(form=form, coarse=coarse, schedule=label, opts=od, dtype=path_dtype(coarse),
                  qps=cfg.nq / (ms_step / 1000.0), ms_per_step=ms_step,
                  qps_with_d2h=cfg.nq / (d2h_ms / 1000.0),
                  recall_at_10=rec, max_rel_dist_err=float(f"{derr:.3g}"), stage_ms=per,
                  scan_points=pts,
-                 scan_gbs=pts * code_bytes / (scan_ms / 1e3) / 1e9 if scan_ms > 0 else None,
+                 scan_alg_gbs=pts * code_bytes / (scan_ms / 1e3) / 1e9 if scan_ms > 0 else None,
                  scan_tlookups=pts * cfg.m / (scan_ms / 1e3) / 1e12 if scan_ms > 0 else None)
-        log(f"{label} {form}/{coarse}: {r['qps']:.0f} q/s ({r['qps_with_d2h']:.0f} with results "
-            f"copied to the host), {ms_step:.3f} ms/step, recall@10 {rec:.4f}, max rel. distance "
-            f"error {derr:.2e}, "
+        log(f"{label} {form}/{coarse}{' (graph)' if od['use_graph'] else ''}: {r['qps']:.0f} q/s "
+            f"({r['qps_with_d2h']:.0f} with results copied to the host), {ms_step:.3f} ms/step, "
+            f"recall@10 {rec:.4f}, max rel. distance error {derr:.2e}, "
             f"stages {', '.join(f'{k_} {v:.3f}ms' for k_, v in per.items())}, scan kernel "
-            f"{r['scan_gbs']:.0f} GB/s algorithmic, {r['scan_tlookups']:.2f} T lookups/s")
+            f"{r['scan_alg_gbs']:.0f} GB/s algorithmic, {r['scan_tlookups']:.2f} T lookups/s")
         results.append(r)
 
     ok = [r for r in results if r["recall_at_10"] >= 0.90] or results
@@ -489,11 +683,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+u8",
+        "dtype": best["dtype"],
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.config, args.config), "n": cfg.n,
                    "d": cfg.d, "nq": cfg.nq, "L": cfg.L, "m": cfg.m, "nprobe": list(cfg.nprobe),
-                   "k": cfg.k, "rerank": cfg.R, "form": best["form"], "coarse": best["coarse"],
+                   "k": cfg.k, "rerank": cfg.R, "sigma": cfg.sigma, "form": best["form"],
+                   "coarse": best["coarse"],
                    "filter": args.filter, "dims_kept": None if dims is None else int(len(dims)),
                    "soar_lambda": args.soar, "copies": copies, "base_dtype": cfg.base_dtype,
                    "schedule": best["opts"]},
@@ -512,6 +707,9 @@ def main():
     }
     if args.sweep:
         line["sweep"] = sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args)
+        fast = [p for p in line["sweep"] if p["recall_at_10"] >= 0.90]
+        line["fastest_sweep_point_at_recall_0.90"] = (max(fast, key=lambda p: p["qps"])
+                                                      if fast else None)
     if args.batch_sweep:
         line["batches"] = batch_sweep(g, cfg, Qd, npd, gt_ids, nrec, args)
     print(json.dumps(line), flush=True)

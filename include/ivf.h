@@ -130,8 +130,9 @@ typedef enum { IVF_FORM_PLAIN = 0, IVF_FORM_BATCHED = 1 } ivf_form;
 
 typedef struct {
   int32_t coarse;    /* ivf_coarse                                              */
-  int32_t widen;     /* >= 1; MFMA coarse forms keep widen*nprobe lists before
-                        the canonical re-score (ignored by IVF_COARSE_EXACT)    */
+  int32_t widen;     /* 1..16384; MFMA coarse forms keep min(L, widen*nprobe)
+                        lists before the canonical re-score (ignored by
+                        IVF_COARSE_EXACT)                                      */
   int32_t form;      /* ivf_form                                                */
   int32_t use_graph; /* 1 = capture the whole search into a hipGraph on first
                         use with these exact arguments (sizes, options and
@@ -172,17 +173,25 @@ typedef struct {
   float p0, p1;        /* finite                                              */
 } ivf_search_opts;
 
-/* Defaults: EXACT coarse, widen 2, PLAIN form, no graph, auto pool and grid. */
+/* Entry points without a passage of the paper behind them are marked
+ * "Infrastructure": sizing, layout inspection, error reporting and
+ * profiling that any caller of the path above needs. */
+
+/* Defaults: EXACT coarse, widen 2, PLAIN form, no graph, auto pool and grid.
+ * Infrastructure. */
 void ivf_default_opts(ivf_search_opts* opts);
 
 /* Bytes of device memory ivf_build_tables needs for this index; 0 if the
- * descriptor is invalid (see ivf_last_error). Host only, no device work. */
+ * descriptor is invalid (see ivf_last_error). Host only, no device work.
+ * Infrastructure. */
 size_t ivf_tables_bytes(const ivf_index_desc* desc);
 
 /* Lay out the index in `table_mem` (>= ivf_tables_bytes, 256-byte aligned):
  * packed 4-bit code blocks per list (step 3 operand), slot ids, centroid
  * copies and low-precision centroid tables. Synchronises `stream` before it
  * returns, so the descriptor's arrays may be freed afterwards (except base).
+ * A list_ids entry outside [0, n) (or, with copies >= 2, a point in more
+ * lists) is found on the device and reported as IVF_ERR_INVALID_ARG.
  * On success *out receives a host handle that references table_mem. */
 ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem,
                             size_t table_bytes, void* stream, ivf_index** out);
@@ -190,7 +199,8 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem,
 /* Bytes of workspace one ivf_search call with these sizes needs; 0 if the
  * arguments are invalid. max_nprobe bounds every nprobe[q]. Every search
  * entry point takes 0 <= nq <= 2^20 queries per call (larger batches are
- * split by the caller), as the assignment calls take at most 2^20 rows. */
+ * split by the caller), as the assignment calls take at most 2^20 rows.
+ * Infrastructure. */
 size_t ivf_search_workspace_bytes(const ivf_index* idx, int32_t nq,
                                   int32_t max_nprobe, int32_t k,
                                   int32_t rerank, const ivf_search_opts* opts);
@@ -214,8 +224,11 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
                       int64_t* out_ids, float* out_dist, void* stream);
 
 /* Steps 2-5 on caller-given probe sets: probes [nq,max_nprobe] int32 list
- * indices in visiting order, nprobe [nq] how many of each row are used.
- * Same outputs and workspace as ivf_search. */
+ * indices in visiting order, nprobe [nq] how many of each row are used. The
+ * first nprobe[q] entries of a row must be distinct lists in [0, L) (the
+ * probe set of Alg. 2 is a set of clusters); a row that breaks this sets
+ * bit 2 of the device error word and is answered as an invalid nprobe is
+ * (ids -1, distances NaN). Same outputs and workspace as ivf_search. */
 ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries,
                                   int32_t nq, const int32_t* probes,
                                   const int32_t* nprobe, int32_t max_nprobe,
@@ -289,15 +302,22 @@ typedef struct {
   int32_t words_per_point, m_padded, blocks, L_padded, d_padded, reserved;
 } ivf_table_layout;
 
+/* Infrastructure. */
 ivf_status ivf_get_table_layout(const ivf_index* idx, ivf_table_layout* out);
 
 /* Reads and clears the device error word kept in `workspace` (synchronises
- * `stream`). Returns 0 when no device-side violation was recorded, else a
- * bit mask: 1 = an nprobe[q] out of range. Returns -1 on a HIP failure. */
-int32_t ivf_get_device_error(const ivf_index* idx, void* workspace,
-                             void* stream);
+ * `stream`) into *out_mask (host): 0 when no device-side violation was
+ * recorded since the last read, else a bit mask: 1 = an nprobe[q] out of
+ * range; 2 = a caller-given probe row (ivf_search_with_probes,
+ * ivf_debug_candidates) with a list index outside [0, L) or a list named
+ * twice. Returns IVF_ERR_INVALID_ARG for a NULL argument, IVF_ERR_DEVICE when
+ * a HIP call fails (*out_mask is then 0). Infrastructure: no passage of the
+ * paper defines it. */
+ivf_status ivf_get_device_error(const ivf_index* idx, void* workspace,
+                                int32_t* out_mask, void* stream);
 
-/* Per-stage timing of ivf_search / ivf_search_with_probes. While enabled,
+/* Per-stage timing of ivf_search / ivf_search_with_probes (infrastructure).
+ * While enabled,
  * every search records HIP events on its stream around its stages
  * (IVF_STAGE_*): coarse scoring, probe selection, scan preparation (IP
  * biases; batched form: first-list pass and each round's work-list build),
@@ -316,7 +336,8 @@ ivf_status ivf_profile_read(ivf_index* idx, float* ms /* [IVF_NSTAGES] */,
 
 /* ---- Index construction on the GPU (Alg. 1) ----------------------------- */
 
-/* Workspace of ivf_assign for `chunk` rows per pass (1..2^20). */
+/* Workspace of ivf_assign for `chunk` rows per pass (1..2^20).
+ * Infrastructure. */
 size_t ivf_assign_workspace_bytes(int32_t L, int32_t d, int32_t chunk,
                                   int32_t coarse);
 
@@ -361,10 +382,11 @@ ivf_status ivf_assign_spill(const float* centroids, int32_t L, int32_t d,
                             size_t workspace_bytes, int32_t* out_list,
                             void* stream);
 
-/* Frees the host handle only; table_mem stays the caller's. */
+/* Frees the host handle only; table_mem stays the caller's. Infrastructure. */
 void ivf_destroy(ivf_index* idx);
 
-/* Message for the last non-OK status on this thread ("" if none). */
+/* Message for the last non-OK status on this thread ("" if none).
+ * Infrastructure. */
 const char* ivf_last_error(void);
 
 #ifdef __cplusplus

@@ -86,7 +86,7 @@ def _declare(lib):
         "ivf_debug_coarse_scores": (I32, [P, P, I32, P, P, SZ, P, P]),
         "ivf_debug_candidates": (I32, [P, P, I32, P, P, I32, I32, P, P, SZ, P, P]),
         "ivf_get_table_layout": (I32, [P, P]),
-        "ivf_get_device_error": (I32, [P, P, P]),
+        "ivf_get_device_error": (I32, [P, P, P, P]),
         "ivf_destroy": (None, [P]),
         "ivf_profile_enable": (I32, [P, I32]),
         "ivf_profile_read": (I32, [P, P, P]),
@@ -259,13 +259,15 @@ class GpuIndex:
                                                   ctypes.byref(opts))
         if nbytes == 0:
             raise IvfError(IVF_ERR_INVALID_ARG, last_error())
-        # One cached workspace per (size, stream): a search enqueued on another
-        # stream gets its own, so two streams never share one in flight.
-        key = (nbytes, torch.cuda.current_stream().cuda_stream)
-        ws = self._ws.get(key)
-        if ws is None:
+        # One cached workspace per stream (a search enqueued on another stream
+        # gets its own, so two streams never share one in flight); a stream's
+        # workspace is replaced only when a call needs a different size.
+        stream = torch.cuda.current_stream().cuda_stream
+        ws = self._ws.get(stream)
+        if ws is None or ws.numel() != nbytes:
             ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-            self._ws = {key: ws}
+            self._ws[stream] = ws
+        self._last_ws = ws
         return ws
 
     def _queries(self, queries):
@@ -408,10 +410,14 @@ class GpuIndex:
         return dict(zip(STAGES, list(ms))), cnt.value
 
     def device_error(self) -> int:
-        ws = next(iter(self._ws.values()), None)
+        """Device error mask of the last search's workspace (read and cleared):
+        1 = an nprobe out of range, 2 = a bad caller-given probe row."""
+        ws = getattr(self, "_last_ws", None)
         if ws is None:
             return 0
-        return int(lib().ivf_get_device_error(self._h, ws.data_ptr(), _stream()))
+        mask = ctypes.c_int32()
+        check(lib().ivf_get_device_error(self._h, ws.data_ptr(), ctypes.byref(mask), _stream()))
+        return mask.value
 
 
 def assign_lists(centroids, X, metric: str, coarse: str = "bf16", widen: int = 4,

@@ -65,13 +65,16 @@ ivf_status hip_fail(hipError_t e, const char* what) {
 
 int32_t round_up_i(int64_t x, int64_t a) { return (int32_t)((x + a - 1) / a * a); }
 
+constexpr int32_t MAX_LISTS = 16384;
+constexpr int32_t MAX_WIDEN = MAX_LISTS;
+
 // Validate the descriptor and compute the table layout. Returns an empty
 // string when valid, else the reason.
 std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t* max_len) {
   if (!d) return "desc is NULL";
   if (d->n < 1 || d->n >= (int64_t)1 << 31) return "n must be in [1, 2^31)";
   if (d->d < 1) return "d must be >= 1";
-  if (d->L < 1 || d->L > 16384) return "L must be in [1, 16384]";
+  if (d->L < 1 || d->L > MAX_LISTS) return "L must be in [1, 16384]";
   if (d->m < 1 || d->m > MAX_M) return "m must be in [1, 256]";
   if (d->d % d->m != 0) return "d must be a multiple of m";
   if (d->metric != IVF_METRIC_L2 && d->metric != IVF_METRIC_IP) return "unknown metric";
@@ -132,9 +135,9 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
   lay->probe_fp8 = take((size_t)lay->L_padded * lay->d_padded);
   lay->probe_fp8_scale = take((size_t)lay->L_padded * 4);
   lay->dims = take(d->dims ? (size_t)d->d * 4 : 0);
-  // Build-time scratch: a spilled index's per-point numbering array and flag,
-  // then the copy of the CSR offsets (int64), then the end.
-  take(copies > 1 ? (size_t)(d->n + 64) * 4 : 0);
+  // Build-time scratch: a spilled index's per-point numbering array and flag
+  // (else just the flag word), then the copy of the CSR offsets (int64).
+  take(copies > 1 ? (size_t)(d->n + 64) * 4 : 64);
   take((size_t)(d->L + 1) * 8);
   lay->total = o;
   if (max_len) *max_len = (int32_t)mx;
@@ -145,9 +148,11 @@ size_t list_off_section(const ivf_index_desc* d, const ivf_table_layout& lay) {
   return lay.total - align_up((size_t)(d->L + 1) * 8);
 }
 
-// Numbering scratch of a spilled index: [n] int32, then the flag word.
+// Numbering scratch of a spilled index: [n] int32, then the flag word; on
+// an index without copies only the flag word.
 size_t copies_section(const ivf_index_desc* d, const ivf_table_layout& lay) {
-  return list_off_section(d, lay) - align_up((size_t)(d->n + 64) * 4);
+  const bool spilled = d->copies > 1;
+  return list_off_section(d, lay) - align_up(spilled ? (size_t)(d->n + 64) * 4 : 64);
 }
 
 ivf_status check_device() {
@@ -173,7 +178,9 @@ uint32_t f32_bits(float f) {
 ivf_status check_opts(const ivf_search_opts& o) {
   if (o.coarse < IVF_COARSE_EXACT || o.coarse > IVF_COARSE_FP8)
     return fail(IVF_ERR_INVALID_ARG, "opts.coarse out of range");
-  if (o.widen < 1) return fail(IVF_ERR_INVALID_ARG, "opts.widen must be >= 1");
+  // widen * max_nprobe stays below 2^28 (L <= 16384), in range of int32.
+  if (o.widen < 1 || o.widen > MAX_WIDEN)
+    return fail(IVF_ERR_INVALID_ARG, "opts.widen must be in [1, 16384]");
   if (o.form != IVF_FORM_PLAIN && o.form != IVF_FORM_BATCHED)
     return fail(IVF_ERR_INVALID_ARG, "opts.form out of range");
   if (o.use_graph != 0 && o.use_graph != 1)
@@ -377,20 +384,22 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
                          cbytes, hipMemcpyDeviceToDevice, s));
   IVF_HIP(hipMemsetAsync((void*)t.codebooks, 0, cb_pad_bytes, s));
   IVF_HIP(hipMemcpyAsync((void*)t.codebooks, desc->codebooks, cb_bytes, hipMemcpyDeviceToDevice, s));
-  IVF_HIP(launch_pack(t, desc->codes, list_off_dev, desc->list_ids, s));
+  // Flag word: set on the device when a list entry names a point outside
+  // [0, n) (the pack kernel then reads no codes for it) or, on a spilled
+  // index, a point in more than `copies` lists.
+  int32_t* first = (int32_t*)(base + copies_section(desc, lay));
+  int32_t* flag = t.copies > 1 ? first + desc->n : first;
+  IVF_HIP(launch_fill_u32((uint32_t*)flag, 0u, 1, s));
+  IVF_HIP(launch_pack(t, desc->codes, list_off_dev, desc->list_ids, flag, s));
   IVF_HIP(launch_aux_tables(t, s));
-  if (t.copies > 1) {
-    int32_t* first = (int32_t*)(base + copies_section(desc, lay));
-    int32_t* flag = first + desc->n;
-    IVF_HIP(launch_number_copies(t, first, flag, s));
-    int32_t too_many = 0;
-    IVF_HIP(hipMemcpyAsync(&too_many, flag, 4, hipMemcpyDeviceToHost, s));
-    IVF_HIP(hipStreamSynchronize(s));
-    if (too_many)
-      return fail(IVF_ERR_INVALID_ARG,
-                  "a list entry names a point outside [0, n) or one in more than copies lists");
-  }
+  if (t.copies > 1) IVF_HIP(launch_number_copies(t, first, flag, s));
+  int32_t bad_entry = 0;
+  IVF_HIP(hipMemcpyAsync(&bad_entry, flag, 4, hipMemcpyDeviceToHost, s));
   IVF_HIP(hipStreamSynchronize(s));
+  if (bad_entry)
+    return fail(IVF_ERR_INVALID_ARG, t.copies > 1
+                    ? "a list entry names a point outside [0, n) or one in more than copies lists"
+                    : "a list entry names a point outside [0, n)");
 
   ivf_index* idx = new (std::nothrow) ivf_index;
   if (!idx) return fail(IVF_ERR_INTERNAL, "out of host memory");
@@ -511,13 +520,13 @@ hipError_t prof_mark(const ivf_index* idx, hipStream_t s, int stage) {
 ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, int32_t k,
                         int32_t rerank, const ivf_search_opts* opts, void* workspace,
                         size_t workspace_bytes, ivf_search_opts* o, Workspace* w) {
-  ivf_status st = check_search(idx, nq, max_nprobe, k, rerank);
-  if (st != IVF_OK) return st;
-  if (idx->prof) idx->prof->cur = -1;  // only entries that call prof_begin are timed
   ivf_default_opts(o);
   if (opts) *o = *opts;
-  st = check_opts(*o);
+  ivf_status st = check_opts(*o);
   if (st != IVF_OK) return st;
+  st = check_search(idx, nq, max_nprobe, k, rerank);
+  if (st != IVF_OK) return st;
+  if (idx->prof) idx->prof->cur = -1;  // only entries that call prof_begin are timed
   if (o->spill_cap > 16384 - rerank * idx->t.copies)
     return fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be at most 16384 - rerank * copies");
   st = check_form(idx, *o);
@@ -901,8 +910,8 @@ ivf_status ivf_assign(const float* centroids, int32_t L, int32_t d, int32_t metr
   if (L < 1 || L > 16384 || d < 1 || n < 0 || chunk < 1 || chunk > (1 << 20))
     return fail(IVF_ERR_INVALID_ARG, "invalid assign sizes");
   if (metric != IVF_METRIC_L2 && metric != IVF_METRIC_IP) return fail(IVF_ERR_INVALID_ARG, "unknown metric");
-  if (coarse < IVF_COARSE_EXACT || coarse > IVF_COARSE_FP8 || widen < 1)
-    return fail(IVF_ERR_INVALID_ARG, "invalid coarse form or widen");
+  if (coarse < IVF_COARSE_EXACT || coarse > IVF_COARSE_FP8 || widen < 1 || widen > MAX_WIDEN)
+    return fail(IVF_ERR_INVALID_ARG, "invalid coarse form or widen (1..16384)");
   if (n == 0) return IVF_OK;
   if (!centroids || !X || !out_list || !workspace) return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   if ((uintptr_t)workspace % ALIGN) return fail(IVF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -984,18 +993,18 @@ ivf_status ivf_encode(const float* X, int64_t n, int32_t d, const float* centroi
   return IVF_OK;
 }
 
-int32_t ivf_get_device_error(const ivf_index* idx, void* workspace, void* stream) {
-  if (!idx || !workspace) {
-    g_last_error = "NULL argument";
-    return -1;
-  }
+ivf_status ivf_get_device_error(const ivf_index* idx, void* workspace, int32_t* out_mask,
+                                void* stream) {
+  if (out_mask) *out_mask = 0;
+  if (!idx || !workspace || !out_mask) return fail(IVF_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
   int32_t v[4] = {0, 0, 0, 0};
   // The error word is the first 16 bytes of every workspace layout.
-  if (hipMemcpyAsync(v, workspace, 16, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
-  if (hipStreamSynchronize(s) != hipSuccess) return -1;
-  if (launch_fill_u32((uint32_t*)workspace, 0u, 4, s) != hipSuccess) return -1;
-  return v[0];
+  IVF_HIP(hipMemcpyAsync(v, workspace, 16, hipMemcpyDeviceToHost, s));
+  IVF_HIP(hipStreamSynchronize(s));
+  IVF_HIP(launch_fill_u32((uint32_t*)workspace, 0u, 4, s));
+  *out_mask = v[0];
+  return IVF_OK;
 }
 
 }  // extern "C"

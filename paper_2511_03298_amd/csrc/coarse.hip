@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(256) select_lds_kernel(Tables t, const float* 
   const int np = nprobe[q];
   if (reject_row(q, np, max_nprobe, probes, nprobe_eff, err, reorder_eff)) return;
   const float* srow = S + (size_t)q * L;
-  const int want = rescore ? min(L, np * widen) : np;
+  const int want = rescore ? (int)min((int64_t)L, (int64_t)np * widen) : np;
   for (int l = threadIdx.x; l < L; l += blockDim.x) keys[l] = make_key(srow[l], (uint32_t)l);
   __syncthreads();
   uint32_t n = (uint32_t)L;
@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
   const int np = nprobe[q];
   if (reject_row(q, np, max_nprobe, probes, nprobe_eff, err, reorder_eff)) return;
   const float* srow = S + (size_t)q * L;
-  const int want = rescore ? min(L, np * widen) : np;
+  const int want = rescore ? (int)min((int64_t)L, (int64_t)np * widen) : np;
   uint32_t o[NK];
 #pragma unroll
   for (int i = 0; i < NK; ++i) {
@@ -432,7 +432,8 @@ hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
                                 bool rescore, const Workspace& w, hipStream_t s,
                                 const AdaptiveArgs& ad) {
   if (nq == 0) return hipSuccess;
-  const int32_t most = rescore ? std::min(t.L, max_nprobe * widen) : max_nprobe;
+  const int32_t most =
+      rescore ? (int32_t)std::min<int64_t>(t.L, (int64_t)max_nprobe * widen) : max_nprobe;
   const int nk = (t.L + IVF_BLOCK - 1) / IVF_BLOCK;
   // Rows of 1025..2048 lists: the whole row in LDS (measured faster there
   // than the register form); shorter and longer rows: registers, so LDS (and
@@ -455,20 +456,32 @@ hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
   return hipErrorInvalidValue;
 }
 
-// Caller-given probe sets: validate counts and list indices, copy.
+// Caller-given probe sets: validate counts and list indices, copy. The
+// used part of a row must name distinct lists in [0, L): a bitmap of the
+// lists seen so far (L <= 16384 bits in LDS) finds a repeated one.
 __global__ void copy_probes_kernel(const int32_t* __restrict__ probes_in,
                                    const int32_t* __restrict__ nprobe, int32_t nq,
                                    int32_t max_nprobe, int32_t L, int32_t* __restrict__ probes,
                                    int32_t* __restrict__ nprobe_eff, int32_t* __restrict__ err) {
   const int q = blockIdx.x;
   __shared__ int bad;
+  __shared__ uint32_t seen[16384 / 32];
+  const int words = (L + 31) / 32;
   if (threadIdx.x == 0) bad = 0;
+  for (int i = threadIdx.x; i < words; i += blockDim.x) seen[i] = 0u;
   __syncthreads();
   int np = nprobe[q];
   bool okn = np >= 1 && np <= max_nprobe;
   for (int p = threadIdx.x; p < max_nprobe; p += blockDim.x) {
     int l = probes_in[(size_t)q * max_nprobe + p];
-    if (okn && p < np && (l < 0 || l >= L)) bad = 1;
+    if (okn && p < np) {
+      if (l < 0 || l >= L) {
+        bad = 1;
+      } else {
+        const uint32_t bit = 1u << (l & 31);
+        if (atomicOr(&seen[l >> 5], bit) & bit) bad = 1;  // listed twice
+      }
+    }
     probes[(size_t)q * max_nprobe + p] = l;
   }
   __syncthreads();

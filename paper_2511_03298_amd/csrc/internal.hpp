@@ -104,8 +104,9 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
                          int32_t rerank, const ivf_search_opts& o, char* base);
 
 // ---- launchers (each enqueues on `s`, returns hipSuccess or an error) ----
+// flag[0] is set to 1 when a list entry names a point outside [0, n).
 hipError_t launch_pack(const Tables& t, const uint8_t* codes, const int64_t* list_off_dev,
-                       const int32_t* list_ids, hipStream_t s);
+                       const int32_t* list_ids, int32_t* flag, hipStream_t s);
 // Spilled index: slot values id * copies + c (see tables.hip); first [n] and
 // flag [1] are scratch, flag[0] = 1 when a point lies in too many lists.
 hipError_t launch_number_copies(const Tables& t, int32_t* first, int32_t* flag, hipStream_t s);

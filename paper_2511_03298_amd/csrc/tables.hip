@@ -14,7 +14,8 @@ __global__ void __launch_bounds__(256) pack_kernel(Tables t, const uint8_t* __re
                                                    const int64_t* __restrict__ list_off,
                                                    const int32_t* __restrict__ list_ids,
                                                    uint32_t* __restrict__ out_codes,
-                                                   int32_t* __restrict__ out_ids) {
+                                                   int32_t* __restrict__ out_ids,
+                                                   int32_t* __restrict__ flag) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= (int64_t)t.blocks * BLOCK_PTS) return;
   const int blk = (int)(slot / BLOCK_PTS);
@@ -26,8 +27,12 @@ __global__ void __launch_bounds__(256) pack_kernel(Tables t, const uint8_t* __re
   }
   const int l = lo;
   const int64_t p = (int64_t)(blk - t.block_off[l]) * BLOCK_PTS + lane;
-  const bool valid = p < t.list_len[l];
-  const int32_t id = valid ? list_ids[list_off[l] + p] : -1;
+  const bool entry = p < t.list_len[l];
+  const int32_t id = entry ? list_ids[list_off[l] + p] : -1;
+  // An entry naming no row of base is reported (and its codes not read).
+  const bool in_range = id >= 0 && (int64_t)id < t.n;
+  if (entry && !in_range) flag[0] = 1;
+  const bool valid = entry && in_range;
   // Code row: the point's (one copy per point) or the list entry's (spilled).
   const int64_t row = t.copies > 1 ? list_off[l] + p : (int64_t)id;
   for (int w = 0; w < t.words; ++w) {
@@ -44,12 +49,12 @@ __global__ void __launch_bounds__(256) pack_kernel(Tables t, const uint8_t* __re
 }
 
 hipError_t launch_pack(const Tables& t, const uint8_t* codes, const int64_t* list_off_dev,
-                       const int32_t* list_ids, hipStream_t s) {
+                       const int32_t* list_ids, int32_t* flag, hipStream_t s) {
   const int64_t slots = (int64_t)t.blocks * BLOCK_PTS;
   if (slots == 0) return hipSuccess;
   const int grid = (int)((slots + 255) / 256);
   hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(256), 0, s, t, codes, list_off_dev, list_ids,
-                     const_cast<uint32_t*>(t.codes), const_cast<int32_t*>(t.slot_ids));
+                     const_cast<uint32_t*>(t.codes), const_cast<int32_t*>(t.slot_ids), flag);
   return hipGetLastError();
 }
 
@@ -137,8 +142,8 @@ __global__ void copies_final_kernel(int32_t* __restrict__ slot_ids, int64_t slot
 
 hipError_t launch_number_copies(const Tables& t, int32_t* first, int32_t* flag, hipStream_t s) {
   const int64_t slots = (int64_t)t.blocks * BLOCK_PTS;
-  hipError_t e = launch_fill_u32((uint32_t*)flag, 0u, 1, s);
-  if (e != hipSuccess || slots == 0) return e;
+  hipError_t e = hipSuccess;
+  if (slots == 0) return e;
   const unsigned grid = (unsigned)((slots + 255) / 256);
   int32_t* ids = const_cast<int32_t*>(t.slot_ids);
   for (int r = 0; r < t.copies; ++r) {

@@ -131,7 +131,18 @@ def test_search_argument_validation_without_index():
     assert lib.ivf_search_workspace_bytes(None, 10, 4, 10, 100, ctypes.byref(o)) == 0
     st = lib.ivf_search(None, None, 1, None, 1, 1, 1, None, None, 0, None, None, None)
     assert st == ivf.IVF_ERR_INVALID_ARG
-    assert lib.ivf_get_device_error(None, None, None) == -1
+    mask = ctypes.c_int32(7)
+    st = lib.ivf_get_device_error(None, None, ctypes.byref(mask), None)
+    assert st == ivf.IVF_ERR_INVALID_ARG and mask.value == 0
+    # widen is bounded before any index is looked at (no int32 overflow of
+    # widen * nprobe on the device).
+    huge = ivf.make_opts(coarse="bf16", widen=1 << 30)
+    st = lib.ivf_search(None, None, 1, None, 1, 1, 1, ctypes.byref(huge), None, 0, None, None,
+                        None)
+    assert st == ivf.IVF_ERR_INVALID_ARG and "widen" in ivf.last_error()
+    st = lib.ivf_assign(0x10000, 8, 4, 0, 0x10000, 10, 10, 2, 1 << 30, 0x10000, 1 << 20,
+                        0x10000, None)
+    assert st == ivf.IVF_ERR_INVALID_ARG and "widen" in ivf.last_error()
 
 
 def test_every_export_has_a_prototype():

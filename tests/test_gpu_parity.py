@@ -270,6 +270,48 @@ def test_invalid_nprobe_sets_error_word():
     assert g.device_error() == 0  # cleared by the read
 
 
+@pytest.mark.parametrize("form", ["plain", "batched"])
+def test_bad_probe_rows_rejected(form):
+    # Caller-given probe rows: a list named twice or outside [0, L) sets bit 2
+    # of the error word; that row is answered as (-1, NaN), the others are
+    # searched normally.
+    ivf = _gpu()
+    cfg, X, Q, nprobe, index, g, res = case("c1")
+    nq = 6
+    P = probes_tensor({"probes": res["probes"][:nq]}, nprobe[:nq]).clone()
+    npb = np.asarray(nprobe[:nq], dtype=np.int32)
+    P[1, 2] = P[1, 0]          # repeated list
+    P[4, 1] = cfg.L            # out of range
+    opts = ivf.make_opts(form=form)
+    ids, dist = g.search_with_probes(Q[:nq], P, npb, cfg.k, cfg.R, opts=opts)
+    torch.cuda.synchronize()
+    assert g.device_error() == 2
+    ids, dist = ids.cpu().numpy(), dist.cpu().numpy()
+    for qi in (1, 4):
+        assert np.all(ids[qi] == -1) and np.all(np.isnan(dist[qi]))
+    ok = [0, 2, 3, 5]
+    sub = {k: v[ok] for k, v in res.items() if k in ("ids", "dist")}
+    check_final(ids[ok], dist[ok], sub, X, Q[ok], cfg.metric)
+    assert g.device_error() == 0
+
+
+def test_list_id_out_of_range_rejected_at_build():
+    # An unspilled index whose list names a row outside [0, n): the build
+    # reports it instead of reading codes out of bounds.
+    ivf = _gpu()
+    cfg, X, Q, nprobe, index, g, _ = case("c1")
+    lid = index["list_ids"].copy()
+    off = index["list_offsets"]
+    lid[off[1]] = len(X) + 5
+    with pytest.raises(ivf.IvfError, match="outside"):
+        ivf.GpuIndex(X, index["cm"], index["codebooks"], index["codes"], off, lid,
+                     cfg.metric, probe_centroids=index["cp"])
+    lid[off[1]] = -3
+    with pytest.raises(ivf.IvfError, match="outside"):
+        ivf.GpuIndex(X, index["cm"], index["codebooks"], index["codes"], off, lid,
+                     cfg.metric, probe_centroids=index["cp"])
+
+
 @pytest.mark.parametrize("name", ["c2s", "c4s"])
 def test_multiple_probed_lists_ragged_batch(name):
     # nq not a multiple of any tile, per-query nprobe spanning 1..L.

@@ -65,6 +65,35 @@ def test_hand_worked_lut_example():
     assert np.all(np.abs(a - exact) <= 2 * float(delta) / 2)
 
 
+def test_hand_worked_pairwise_lo_sum():
+    # m = 4 subspace minima (1, 2^-24, 2^-24, 2^-24): the pairwise sum that
+    # forms B is 1 + 2^-23, a sequential one would be 1 (fixture derivation).
+    g = json.load(open(os.path.join(GOLDEN, "lut_pairwise_lo_sum.json")))
+    i = np.arange(16)
+    assert g["expected_q8"] == [(i * i + 2 * i).tolist(), (i * i).tolist(),
+                                ((i * i + 2) // 4).tolist(), ((i * i + 8) // 16).tolist()]
+    assert g["expected_lo"] == [1.0] + [2.0 ** -24] * 3
+    assert g["expected_B"] == 1.0 + 2.0 ** -23
+    q = np.array(g["q"], dtype=np.float32)
+    cm = np.array(g["cm"], dtype=np.float32)
+    cb = np.array(g["codebooks"], dtype=np.float32)
+    T = oracle.lut_float(q, cm, cb, g["metric"])
+    q8, lo, delta, B = oracle.quantize_lut(T, oracle.list_bias(q, cm, g["metric"]))
+    assert q8.tolist() == g["expected_q8"]
+    assert lo.tolist() == g["expected_lo"]
+    assert float(delta) == g["expected_delta"]
+    assert int(np.float32(B).view(np.uint32)) == int(g["expected_B_bits"], 16)
+    S, a = oracle.scan_list(q8, delta, B, np.array(g["points_codes"]))
+    assert S.tolist() == g["expected_S"]
+    assert a.tolist() == g["expected_a"]
+    # The exact squared distance to the reconstructed vector (cm = 0, so
+    # x^ = concatenated codewords), in float64, within m * delta / 2.
+    for c, av in zip(g["points_codes"], a.tolist()):
+        xh = np.array([cb[j, c[j], 0] for j in range(4)], dtype=np.float64)
+        exact = float(((q.astype(np.float64) - xh) ** 2).sum())
+        assert abs(av - exact) <= 4 * float(delta) / 2
+
+
 # ------------------------------------------------ brute force (section 1)
 
 @pytest.mark.parametrize("name", ["c1", "c3"])
@@ -379,6 +408,34 @@ def test_hardness_closed_form():
     # Negative e (non-unit query) clamps to 0; e_K <= 0 gives 1.
     assert oracle.hardness(np.array([-1.5, -0.5], F), 2, "ip") == F(0.0)
     assert oracle.hardness(np.array([-1.5, -1.2], F), 2, "ip") == F(1.0)
+
+
+def test_adaptive_params_hand_worked():
+    F = np.float32
+    # Six lists scored out of order: sorted by (score, list) they are lists
+    # 1, 3, 4, 0, 5, 2 with scores 1, 2, 4, 5, 8, 9.
+    row = np.array([5.0, 1.0, 9.0, 2.0, 4.0, 8.0], F)
+    # nprobe_init 3: e_1 = 1, e_3 = 4, p = 1/4. Eq. 2 with p0 = 0, p1 = 1:
+    # ReLU(1/4) * (1/4 + 1) = 5/16 (exact).
+    #   nprobe:  v_min 2, v_max 6:  2 + floor(4 * 5/16 = 1.25) = 3
+    #   reorder: v_min 20 (reorder_min, within [k, R] = [10, 100]), v_max 100:
+    #            20 + floor(80 * 5/16 = 25) = 45
+    npb, reo, p = oracle.adaptive_params(row, 6, "l2", 3, 2, 20, 100, 10, 0.0, 1.0)
+    assert (npb, reo, float(p)) == (3, 45, 0.25)
+    # nprobe_init above nprobe_max: K = nprobe_max = 2, e_2 = 2, p = 1/2,
+    # ReLU(1/2) * 3/2 = 3/4; nprobe has v_min = v_max = 2; reorder
+    # 20 + floor(80 * 3/4 = 60) = 80.
+    npb, reo, p = oracle.adaptive_params(row, 2, "l2", 3, 2, 20, 100, 10, 0.0, 1.0)
+    assert (npb, reo, float(p)) == (2, 80, 0.5)
+    # reorder_min below k is raised to k = 10: 10 + floor(90 * 5/16 = 28.125) = 38.
+    npb, reo, p = oracle.adaptive_params(row, 6, "l2", 3, 2, 4, 100, 10, 0.0, 1.0)
+    assert (npb, reo) == (3, 38)
+    # Inner product: e = 1 + s. Sorted scores -0.75, -0.5, 0 (lists 1, 3, 2):
+    # e_1 = 1/4, e_3 = 1, p = 1/4 as above -> (3, 45). Read as L2 (e = s),
+    # e_3 = 0 would give p = 1 and (6, 100).
+    row_ip = np.array([0.5, -0.75, 0.0, -0.5, 0.25, 0.75], F)
+    npb, reo, p = oracle.adaptive_params(row_ip, 6, "ip", 3, 2, 20, 100, 10, 0.0, 1.0)
+    assert (npb, reo, float(p)) == (3, 45, 0.25)
 
 
 @pytest.mark.parametrize("name", ["c1", "c3"])
