@@ -178,6 +178,7 @@ def _cpu_server(conn, X, Q, nprobe, k, R, per_worker):
         per_query = (time.perf_counter() - t0) / 2
     # At least 8 queries per worker; 32 unless that would take over ~30 s.
     per_worker = max(8, min(per_worker, int(30.0 / max(per_query, 1e-6))))
+    log(f"oracle: {per_query:.3f} s per query; {workers} processes x {per_worker} queries")
     _CPU.update(index=index, X=X, Q=Q, nprobe=nprobe, k=k, R=R)
     spans = [(w * per_worker, (w + 1) * per_worker) for w in range(workers)]
     with mp.get_context("fork").Pool(workers) as pool:

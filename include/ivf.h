@@ -277,6 +277,21 @@ ivf_status ivf_debug_luts(const ivf_index* idx, const float* queries,
                           uint8_t* out_lut, float* out_lo, float* out_delta,
                           float* out_B, void* stream);
 
+/* Step 2 as the BATCHED form computes it (its own table builders: the scan
+ * kernel's per-item builder for L2, the per-query table plus list bias for
+ * IP), for every (q, p < nprobe[q]) of caller-given probes (rows as in
+ * ivf_search_with_probes): out_lut [nq,max_nprobe,m,16] uint8,
+ * out_delta and out_B [nq,max_nprobe] FP32; entries with p >= nprobe[q]
+ * are left untouched. The workspace is sized by ivf_search_workspace_bytes
+ * for (nq, max_nprobe, 1, 1) with opts.form = IVF_FORM_BATCHED (m <= 192).
+ * Same quantities as ivf_debug_luts (sections 2.4, 2.5, 4.5.1). */
+ivf_status ivf_debug_batched_luts(const ivf_index* idx, const float* queries,
+                                  int32_t nq, const int32_t* probes,
+                                  const int32_t* nprobe, int32_t max_nprobe,
+                                  void* workspace, size_t workspace_bytes,
+                                  uint8_t* out_lut, float* out_delta, float* out_B,
+                                  void* stream);
+
 /* Steps 2-4 on caller-given probes: out_keys [nq,rerank] uint64 candidate
  * keys in ascending order, key = (ord(a) << 32) | id, where a is the FP32
  * ADC value and ord maps float order onto unsigned order (sign bit set:

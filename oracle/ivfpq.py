@@ -236,7 +236,8 @@ def rerank(q: np.ndarray, X: np.ndarray, cand_ids: np.ndarray, k: int,
     q64 = np.asarray(q, dtype=np.float64)
     ids = np.asarray(cand_ids, dtype=np.int64)
     ids = ids[ids >= 0]
-    rows = np.asarray(X, dtype=np.float64)[ids] if len(ids) else np.zeros((0, len(q)))
+    # Gather the candidate rows first, then widen them (not the whole base).
+    rows = np.asarray(X[ids], dtype=np.float64) if len(ids) else np.zeros((0, len(q)))
     if metric == "l2":
         e = ((rows - q64[None, :]) ** 2).sum(axis=1)
         order = np.lexsort((ids, e))

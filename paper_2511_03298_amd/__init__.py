@@ -28,7 +28,7 @@ EXPORTED = [
     "ivf_debug_candidates", "ivf_get_table_layout", "ivf_get_device_error", "ivf_destroy",
     "ivf_last_error", "ivf_profile_enable", "ivf_profile_read", "ivf_debug_coarse_scores",
     "ivf_assign_workspace_bytes", "ivf_assign", "ivf_encode", "ivf_debug_adaptive",
-    "ivf_assign_spill_workspace_bytes", "ivf_assign_spill",
+    "ivf_assign_spill_workspace_bytes", "ivf_assign_spill", "ivf_debug_batched_luts",
 ]
 STAGES = ("coarse", "select", "prep", "scan", "merge", "rerank")
 
@@ -97,6 +97,7 @@ def _declare(lib):
         "ivf_assign_spill_workspace_bytes": (SZ, [I32, I32, I32]),
         "ivf_assign_spill": (I32, [P, I32, I32, P, I64, P, ctypes.c_float, I32, P, SZ, P, P]),
         "ivf_debug_adaptive": (I32, [P, P, I32, P, I32, I32, I32, P, P, SZ, P, P, P]),
+        "ivf_debug_batched_luts": (I32, [P, P, I32, P, P, I32, P, SZ, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -383,6 +384,24 @@ class GpuIndex:
         check(lib().ivf_debug_luts(self._h, _ptr(q), nq, _ptr(pr), _ptr(npb), max_nprobe,
                                    _ptr(lut), _ptr(lo), _ptr(delta), _ptr(B), _stream()))
         return lut, lo, delta, B
+
+    def debug_batched_luts(self, queries, probes, nprobe):
+        """The batched form's tables for caller-given probes: (lut u8
+        [nq,max_nprobe,m,16], delta, B [nq,max_nprobe]) device tensors."""
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        pr = probes.to(device=self.device, dtype=torch.int32).contiguous()
+        max_nprobe = pr.shape[1]
+        npb = self._nprobe(nprobe, nq)
+        ws = self.workspace(nq, max_nprobe, 1, 1, make_opts(form="batched"))
+        lut = torch.zeros((nq, max_nprobe, self.m, 16), dtype=torch.uint8, device=self.device)
+        delta = torch.zeros((nq, max_nprobe), dtype=torch.float32, device=self.device)
+        B = torch.zeros((nq, max_nprobe), dtype=torch.float32, device=self.device)
+        check(lib().ivf_debug_batched_luts(self._h, _ptr(q), nq, _ptr(pr), _ptr(npb), max_nprobe,
+                                           ws.data_ptr(), ws.numel(), _ptr(lut), _ptr(delta),
+                                           _ptr(B), _stream()))
+        return lut, delta, B
 
     def debug_candidates(self, queries, probes, nprobe, rerank: int, opts=None):
         import torch

@@ -520,8 +520,11 @@ hipError_t prof_mark(const ivf_index* idx, hipStream_t s, int stage) {
 ivf_status begin_search(const ivf_index* idx, int32_t nq, int32_t max_nprobe, int32_t k,
                         int32_t rerank, const ivf_search_opts* opts, void* workspace,
                         size_t workspace_bytes, ivf_search_opts* o, Workspace* w) {
-  ivf_default_opts(o);
-  if (opts) *o = *opts;
+  // `opts` may point at *o: read it before *o is written.
+  ivf_search_opts req;
+  ivf_default_opts(&req);
+  if (opts) req = *opts;
+  *o = req;
   ivf_status st = check_opts(*o);
   if (st != IVF_OK) return st;
   st = check_search(idx, nq, max_nprobe, k, rerank);
@@ -806,6 +809,34 @@ ivf_status ivf_debug_luts(const ivf_index* idx, const float* queries, int32_t nq
     return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
   IVF_HIP(launch_debug_luts(idx->t, queries, nq, probes, nprobe, max_nprobe, out_lut, out_lo,
                             out_delta, out_B, (hipStream_t)stream));
+  return IVF_OK;
+}
+
+ivf_status ivf_debug_batched_luts(const ivf_index* idx, const float* queries, int32_t nq,
+                                  const int32_t* probes, const int32_t* nprobe,
+                                  int32_t max_nprobe, void* workspace, size_t workspace_bytes,
+                                  uint8_t* out_lut, float* out_delta, float* out_B,
+                                  void* stream) {
+  ivf_search_opts req, o;
+  ivf_default_opts(&req);
+  req.form = IVF_FORM_BATCHED;
+  Workspace w;
+  ivf_status st =
+      begin_search(idx, nq, max_nprobe, 1, 1, &req, workspace, workspace_bytes, &o, &w);
+  if (st != IVF_OK) return st;
+  if (!w.qlut && idx->t.metric == IVF_METRIC_IP)
+    return fail(IVF_ERR_INTERNAL, "batched workspace plan has no per-query tables");
+  if (nq == 0) return IVF_OK;
+  if (!queries || !probes || !nprobe || !out_lut || !out_delta || !out_B)
+    return fail(IVF_ERR_INVALID_ARG, "a required pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  IVF_HIP(launch_fill_u32((uint32_t*)w.err, 0u, 4, s));
+  IVF_HIP(launch_copy_probes(probes, nprobe, nq, max_nprobe, idx->t.L, w, s));
+  const float* Qs = queries;
+  st = search_queries(idx, queries, nq, w, s, &Qs);
+  if (st != IVF_OK) return st;
+  IVF_HIP(launch_bias(idx->t, Qs, nq, max_nprobe, w, s));
+  IVF_HIP(launch_debug_batched_luts(idx->t, Qs, nq, max_nprobe, w, out_lut, out_delta, out_B, s));
   return IVF_OK;
 }
 

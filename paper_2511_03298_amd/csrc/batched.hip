@@ -35,6 +35,19 @@ inline int item_queries_rt(int W) { return W * 8 > 96 ? 8 : 16; }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
+// One three-input add and one byte extract per instruction, kept as written
+// (the compiler would otherwise rebalance the sums into more instructions).
+__device__ __forceinline__ uint32_t add3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+__device__ __forceinline__ uint32_t bfe8(uint32_t x, int shift) {
+  uint32_t r;
+  asm("v_bfe_u32 %0, %1, %2, 8" : "=v"(r) : "v"(x), "i"(shift));
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Work list: (query, probe slot) pairs of one round grouped by list. A pair
 // belongs to the round [lo, hi) when p1[q] <= p < nprobe_eff[q], lo <= p < hi
@@ -73,7 +86,8 @@ __global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t ma
     if (hist[l]) atomicAdd(&cnt[l], hist[l]);
 }
 
-// Exclusive scans of per-list pair counts and item counts (one workgroup).
+// Exclusive scans of per-list pair counts and item counts (one workgroup);
+// the items of one list are consecutive, lists in ascending order.
 __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, int32_t BG,
                                                          const int32_t* __restrict__ cnt,
                                                          int32_t* __restrict__ list_start,
@@ -419,10 +433,12 @@ __global__ void __launch_bounds__(256) query_lut_kernel(Tables t, const float* _
 // Phase 2: persistent list-major scan.
 // ---------------------------------------------------------------------------
 
-template <int W, int BG>
+// Per-workgroup LDS of the scan kernel. The per-wave subspace minima are
+// needed only by the generic L2 builder (wave_build_lut).
+template <int W, int BG, bool NEED_LO>
 struct BatchShared {
   uint16_t lut16[W * 8 * (BG / 8) * 16 * 8];
-  float lo[IVF_NWAVES][W * 8];
+  float lo[NEED_LO ? IVF_NWAVES : 1][NEED_LO ? W * 8 : 1];
   float B[BG], delta[BG];
   uint64_t thr[BG];
   // Per query pair k (queries 2k, 2k+1 in the low, high half): 1 + the
@@ -430,9 +446,6 @@ struct BatchShared {
   uint32_t slim[BG / 2];
   int32_t qid[BG], slot[BG];
   int32_t item, next, l, nqi;
-  // Per wave: the current block's code words, then (after the word loop)
-  // its BG sums per point for the rare exact-key path.
-  uint32_t stage[IVF_NWAVES][(W * 2 > BG ? W * 2 : BG) * BLOCK_PTS / 2];
 };
 
 // Codebooks are staged in LDS when they fit beside the tables.
@@ -445,20 +458,26 @@ constexpr bool lane_build() { return W * 8 <= 2 * IVF_WAVE; }
 
 // PER_QUERY (inner product): the tables come from query_lut_kernel and are
 // only copied per item; otherwise (L2) each item builds its residual tables.
+// Three workgroups per CU (12 waves) fit the LDS of every shape; the register
+// budget is set to match (the unrolled word loop would otherwise hoist
+// most of its table reads and leave room for one).
 template <int W, bool PER_QUERY, int BG>
-__global__ void __launch_bounds__(256) batched_scan_kernel(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+batched_scan_kernel(
     Tables t, const float* __restrict__ Q, int32_t max_nprobe, const float* __restrict__ bias,
     const uint64_t* __restrict__ thr, const int32_t* __restrict__ list_start,
+    const int32_t* __restrict__ list_cnt,
     const int32_t* __restrict__ item_start, const int32_t* __restrict__ item_list,
     const int32_t* __restrict__ pairs, uint32_t* __restrict__ queue,
     int32_t* __restrict__ spill_cnt, uint64_t* __restrict__ spill, int32_t cap,
     const uint32_t* __restrict__ qlut, const float* __restrict__ qlo_sum,
     const float* __restrict__ qdelta) {
-  __shared__ BatchShared<W, BG> sh;
+  constexpr bool per_query = PER_QUERY;
+  constexpr bool need_lo = !per_query && !lane_build<W>();
+  __shared__ BatchShared<W, BG, need_lo> sh;
   constexpr int HALVES = BG / 8;
   extern __shared__ __align__(16) unsigned char dyn[];
   // L2 only: per-wave residual operand and (when they fit) the codebooks.
-  constexpr bool per_query = PER_QUERY;
   float* rq_all = reinterpret_cast<float*>(dyn);         // [4][d] per-wave query operand
   float* cb_s = rq_all + IVF_NWAVES * t.d;               // [m*16*d'] (when staged)
   const float* cb = cb_in_lds<W>() ? cb_s : t.codebooks;
@@ -484,7 +503,7 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
     if (tid < BG) {
       const int l = item_list[item];
       const int first = (item - item_start[l]) * BG;
-      const int nqi = min(BG, list_start[l + 1] - list_start[l] - first);
+      const int nqi = min(BG, list_cnt[l] - first);
       const bool v = tid < nqi;
       const int pi = list_start[l] + first + tid;
       const int q = v ? pairs[2 * pi] : -1;
@@ -499,6 +518,17 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
     __syncthreads();
     if (tid == 0) sh.next = (int32_t)atomicAdd(queue, 1u);  // overlaps this item
     const int l = sh.l, nqi = sh.nqi;
+    const int n_l = t.list_len[l];
+    const int blk0 = t.block_off[l];
+    const int nblk = (n_l + BLOCK_PTS - 1) / BLOCK_PTS;
+    // Each wave's first code block is requested now; its latency overlaps
+    // the table set-up below.
+    uint32_t nx[W];
+    if (wave < nblk) {
+      const uint32_t* cw = t.codes + (size_t)(blk0 + wave) * W * BLOCK_PTS + ln;
+#pragma unroll
+      for (int w = 0; w < W; ++w) nx[w] = cw[w * BLOCK_PTS];
+    }
     if constexpr (per_query) {
       // Copy the queries' tables into the interleaved layout. Lane (c, pp)
       // of task (subspaces 4jg..4jg+3, half h) moves code c of queries
@@ -541,8 +571,8 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
           wave_build_lut_lanes2<W, HALVES>(t, qg, c, cbT, g, sh.lut16, &sh.B[g], &sh.delta[g]);
         } else {
           for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
-          wave_build_lut<W>(t, rq, cb, 0.0f, ItemStore{sh.lut16, g, HALVES}, sh.lo[wave],
-                            &sh.B[g], &sh.delta[g]);
+          wave_build_lut<W>(t, rq, cb, 0.0f, ItemStore{sh.lut16, g, HALVES},
+                            sh.lo[need_lo ? wave : 0], &sh.B[g], &sh.delta[g]);
         }
       } else {
         for (int e = ln; e < W * 8 * 16; e += IVF_WAVE)
@@ -573,26 +603,20 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       if ((g & 1) == 0) sh.slim[g >> 1] = lim | (other << 16);
     }
     __syncthreads();
-    const int n_l = t.list_len[l];
-    const int blk0 = t.block_off[l];
-    const int nblk = (n_l + BLOCK_PTS - 1) / BLOCK_PTS;
-    // Code words: the next block's words are loaded into registers while the
-    // current block, staged in this wave's LDS slice, is scanned.
-    uint32_t* stage = sh.stage[wave];
-    uint32_t nx[W];
-    if (wave < nblk) {
-      const uint32_t* cw = t.codes + (size_t)(blk0 + wave) * W * BLOCK_PTS + ln;
-#pragma unroll
-      for (int w = 0; w < W; ++w) nx[w] = cw[w * BLOCK_PTS];
-    }
+    // Code words stay in registers: the current block in `cur`, the wave's
+    // next block in flight into `nx` (when there is none the current block is
+    // requested again and not used; a branch would make the compiler wait
+    // for the loads before the lookups).
     const unsigned char* lutb = reinterpret_cast<const unsigned char*>(sh.lut16);
 #pragma unroll 1
     for (int bi = wave; bi < nblk; bi += IVF_NWAVES) {
       const int blk = blk0 + bi;
+      uint32_t cur[W];
 #pragma unroll
-      for (int w = 0; w < W; ++w) stage[w * BLOCK_PTS + ln] = nx[w];
-      if (bi + IVF_NWAVES < nblk) {
-        const uint32_t* cw = t.codes + (size_t)(blk + IVF_NWAVES) * W * BLOCK_PTS + ln;
+      for (int w = 0; w < W; ++w) cur[w] = nx[w];
+      {
+        const int nb = bi + IVF_NWAVES < nblk ? blk + IVF_NWAVES : blk;
+        const uint32_t* cw = t.codes + (size_t)nb * W * BLOCK_PTS + ln;
 #pragma unroll
         for (int w = 0; w < W; ++w) nx[w] = cw[w * BLOCK_PTS];
       }
@@ -605,26 +629,30 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       uint32_t acc[NACC];
 #pragma unroll
       for (int k = 0; k < NACC; ++k) acc[k] = 0u;
-#pragma unroll 1
-      for (int w = 0; w < W; ++w) {
-        const uint32_t x = stage[w * BLOCK_PTS + ln];
-        const uint32_t base = (uint32_t)(w * 8 * SUBB);
 #pragma unroll
-        for (int s = 0; s < 8; s += 2) {
-          const uint32_t n0 = __builtin_amdgcn_ubfe(x, 4 * s, 4);
-          const uint32_t n1 = __builtin_amdgcn_ubfe(x, 4 * s + 4, 4);
-          const unsigned char* r0 = lutb + ((n0 << 4) + base + s * SUBB);
-          const unsigned char* r1 = lutb + ((n1 << 4) + base + (s + 1) * SUBB);
+      for (int w = 0; w < W; ++w) {
+        // Byte k of ev / od: the code of subspace 8w + 2k / 8w + 2k + 1,
+        // times 16 (the byte offset of its row within the subspace).
+        const uint32_t ev = (cur[w] << 4) & 0xf0f0f0f0u;
+        const uint32_t od = cur[w] & 0xf0f0f0f0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const unsigned char* r0 = lutb + bfe8(ev, 8 * k) + (uint32_t)(w * 8 + 2 * k) * SUBB;
+          const unsigned char* r1 = lutb + bfe8(od, 8 * k) + (uint32_t)(w * 8 + 2 * k + 1) * SUBB;
 #pragma unroll
           for (int h = 0; h < HALVES; ++h) {
             const uint4 a = *reinterpret_cast<const uint4*>(r0 + 256 * h);
             const uint4 b = *reinterpret_cast<const uint4*>(r1 + 256 * h);
-            acc[4 * h + 0] = acc[4 * h + 0] + a.x + b.x;
-            acc[4 * h + 1] = acc[4 * h + 1] + a.y + b.y;
-            acc[4 * h + 2] = acc[4 * h + 2] + a.z + b.z;
-            acc[4 * h + 3] = acc[4 * h + 3] + a.w + b.w;
+            acc[4 * h + 0] = add3(acc[4 * h + 0], a.x, b.x);
+            acc[4 * h + 1] = add3(acc[4 * h + 1], a.y, b.y);
+            acc[4 * h + 2] = add3(acc[4 * h + 2], a.z, b.z);
+            acc[4 * h + 3] = add3(acc[4 * h + 3], a.w, b.w);
           }
         }
+        // One word's table reads and adds stay together: without this fence
+        // the scheduler hoists later words' reads and runs out of registers.
+        // The other resident waves hide each word's LDS latency.
+        __builtin_amdgcn_sched_barrier(0);
       }
       const bool valid = bi * BLOCK_PTS + ln < n_l;
       // Pre-check in the integer domain: per half, the saturating difference
@@ -646,18 +674,14 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       }
       if (!valid) cand = 0;
       // Rare path: exact keys for the candidate (point, query) pairs.
-      uint16_t* sv = reinterpret_cast<uint16_t*>(stage);
-#pragma unroll
-      for (int g = 0; g < BG; ++g)
-        sv[g * BLOCK_PTS + ln] = (uint16_t)((acc[g >> 1] >> (16 * (g & 1))) & 0xffffu);
       const uint32_t id = cand ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
       // Which candidates pass on the full key; lane g collects query g's count.
       uint32_t passbits = 0, count = 0;
-#pragma unroll 1
+#pragma unroll
       for (int g = 0; g < BG; ++g) {
         const bool c = (cand >> g) & 1u;
         if (__ballot(c) == 0) continue;
-        const uint32_t S = sv[g * BLOCK_PTS + ln];
+        const uint32_t S = (acc[g >> 1] >> (16 * (g & 1))) & 0xffffu;
         const uint64_t key = make_key(plus_zero(sh.B[g] + sh.delta[g] * (float)S), id);
         const bool pass = c && key <= sh.thr[g];
         passbits |= pass ? 1u << g : 0u;
@@ -667,14 +691,14 @@ __global__ void __launch_bounds__(256) batched_scan_kernel(
       // One reservation per query with survivors, all issued together.
       uint32_t base = 0;
       if (ln < BG && count) base = (uint32_t)atomicAdd(&spill_cnt[sh.qid[ln]], (int)count);
-#pragma unroll 1
+#pragma unroll
       for (int g = 0; g < BG; ++g) {
         const bool pass = (passbits >> g) & 1u;
         const uint64_t mask = __ballot(pass);
         if (mask == 0) continue;
         const uint32_t pos = (uint32_t)__shfl((int)base, g) + lanes_below(mask);
         if (pass && pos < (uint32_t)cap) {
-          const uint32_t S = sv[g * BLOCK_PTS + ln];
+          const uint32_t S = (acc[g >> 1] >> (16 * (g & 1))) & 0xffffu;
           spill[(size_t)sh.qid[g] * cap + pos] =
               make_key(plus_zero(sh.B[g] + sh.delta[g] * (float)S), id);
         }
@@ -808,7 +832,7 @@ hipError_t launch_batched_pairs(const Tables& t, int32_t nq, int32_t max_nprobe,
   hipError_t e;
   if ((e = launch_fill_u32((uint32_t*)w.list_cnt, 0u, (size_t)t.L, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32((uint32_t*)w.spill_cnt, 0u, (size_t)nq, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(w.queue, 0u, 4, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(w.queue, 0u, 1, s)) != hipSuccess) return e;
   const RoundSel sel{w.nprobe_eff, w.p1, w.redo, lo, hi};
   const int64_t np_total = (int64_t)nq * max_nprobe;
   const unsigned g1 = (unsigned)((np_total + PAIR_CHUNK - 1) / PAIR_CHUNK);
@@ -846,7 +870,8 @@ static hipError_t launch_main_w(const Tables& t, const float* Q, int32_t max_npr
     if (per_cu > 6) per_cu = 6;
     if (w.grid > 0) per_cu = w.grid;
     hipLaunchKernelGGL(kernel, dim3(cus * per_cu), block, lds, s, t, Q, max_nprobe, w.bias,
-                       w.thr, w.list_start, w.item_start, w.item_list, w.pairs, w.queue,
+                       w.thr, w.list_start, w.list_cnt, w.item_start, w.item_list, w.pairs,
+                       w.queue,
                        w.spill_cnt, w.spill, w.spill_cap, qlut, w.qlo_sum, w.qdelta);
     return hipGetLastError();
   };
@@ -886,6 +911,104 @@ hipError_t launch_batched_merge(const Tables& t, int32_t nq, int32_t R, const Wo
                        w.nprobe_eff, w.spill_cnt, w.spill, w.cand, w.thr, w.redo);
   }
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Parity export of the batched form's tables. Per (query, probe slot) the
+// table the scan would use, as u8 [m][16] with its scale delta and constant
+// B: for L2 the scan kernel's own per-item builder for this W (the query in
+// slot 0 of an item, one wave), for inner product the per-query table of
+// query_lut_kernel with B = its pairwise sum of the minima + the list bias.
+// ---------------------------------------------------------------------------
+
+template <int W>
+__global__ void __launch_bounds__(IVF_WAVE) batched_lut_export_kernel(
+    Tables t, const float* __restrict__ Q, int32_t max_nprobe, const int32_t* __restrict__ probes,
+    const int32_t* __restrict__ nprobe_eff, const float* __restrict__ bias,
+    const uint8_t* __restrict__ qlut, const float* __restrict__ qlo_sum,
+    const float* __restrict__ qdelta, uint8_t* __restrict__ out_lut, float* __restrict__ out_delta,
+    float* __restrict__ out_B) {
+  constexpr int HALVES = item_queries<W>() / 8;
+  constexpr int MP = W * 8;
+  __shared__ uint16_t lut16[MP * HALVES * 16 * 8];
+  __shared__ float lo[MP];
+  __shared__ float sB, sD;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  const int q = blockIdx.x, p = blockIdx.y;
+  const size_t qp = (size_t)q * max_nprobe + p;
+  if (p >= nprobe_eff[q]) return;  // uniform over the wave
+  const int ln = threadIdx.x;
+  uint8_t* out = out_lut + qp * t.m * KSUB;
+  if (t.metric == IVF_METRIC_IP) {
+    for (int e = ln; e < t.m * KSUB; e += IVF_WAVE)
+      out[e] = qlut[((size_t)q * KSUB + (e & 15)) * t.m_pad + (e >> 4)];
+    if (ln == 0) {
+      out_delta[qp] = qdelta[q];
+      out_B[qp] = qlo_sum[q] + bias[qp];
+    }
+    return;
+  }
+  const int l = probes[qp];
+  const float* qg = Q + (size_t)q * t.d;
+  const float* c = t.cm + (size_t)l * t.d;
+  if constexpr (lane_build<W>()) {
+    float* cbT = reinterpret_cast<float*>(dyn);  // [16*d'][m_pad], as in the scan kernel
+    const int per = KSUB * t.dsub;
+    for (int i = ln; i < t.m * per; i += IVF_WAVE) cbT[(i % per) * MP + i / per] = t.codebooks[i];
+    __syncthreads();
+    if constexpr (MP <= IVF_WAVE)
+      wave_build_lut_lanes<W>(t, qg, c, cbT, 0, lut16, &sB, &sD);
+    else
+      wave_build_lut_lanes2<W, HALVES>(t, qg, c, cbT, 0, lut16, &sB, &sD);
+  } else {
+    float* rq = reinterpret_cast<float*>(dyn);  // [d] residual query
+    float* cb_s = rq + t.d;                     // [m*16*d'] when staged
+    for (int i = ln; i < t.d; i += IVF_WAVE) rq[i] = qg[i] - c[i];
+    if constexpr (cb_in_lds<W>())
+      for (int i = ln; i < t.m * KSUB * t.dsub; i += IVF_WAVE) cb_s[i] = t.codebooks[i];
+    __syncthreads();
+    wave_build_lut<W>(t, rq, cb_in_lds<W>() ? cb_s : t.codebooks, 0.0f,
+                      ItemStore{lut16, 0, HALVES}, lo, &sB, &sD);
+  }
+  __syncthreads();
+  for (int e = ln; e < t.m * KSUB; e += IVF_WAVE)
+    out[e] = (uint8_t)lut16[(((e >> 4) * HALVES) * 16 + (e & 15)) * 8];
+  if (ln == 0) {
+    out_delta[qp] = sD;
+    out_B[qp] = sB;
+  }
+}
+
+template <int W>
+static hipError_t launch_lut_export_w(const Tables& t, const float* Q, int32_t nq,
+                                      int32_t max_nprobe, const Workspace& w, uint8_t* out_lut,
+                                      float* out_delta, float* out_B, hipStream_t s) {
+  if (t.metric == IVF_METRIC_IP) {
+    hipLaunchKernelGGL(query_lut_kernel<W>, dim3((nq + IVF_NWAVES - 1) / IVF_NWAVES), dim3(256), 0,
+                       s, t, Q, nq, w.qlut, w.qlo_sum, w.qdelta);
+  }
+  const size_t lds = t.metric == IVF_METRIC_IP ? 0
+                     : lane_build<W>()     ? (size_t)W * 8 * KSUB * t.dsub * 4
+                                           : (size_t)t.d * 4 +
+                                   (cb_in_lds<W>() ? (size_t)t.m * KSUB * t.dsub * 4 : 0);
+  hipLaunchKernelGGL(batched_lut_export_kernel<W>, dim3(nq, max_nprobe), dim3(IVF_WAVE), lds, s, t,
+                     Q, max_nprobe, w.probes, w.nprobe_eff, w.bias, w.qlut, w.qlo_sum, w.qdelta,
+                     out_lut, out_delta, out_B);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_batched_luts(const Tables& t, const float* Q, int32_t nq,
+                                     int32_t max_nprobe, const Workspace& w, uint8_t* out_lut,
+                                     float* out_delta, float* out_B, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  switch (t.words) {
+#define X(N) \
+  case N: return launch_lut_export_w<N>(t, Q, nq, max_nprobe, w, out_lut, out_delta, out_B, s);
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+    X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
+#undef X
+    default: return hipErrorNotSupported;
+  }
 }
 
 // Queries whose survivors overflowed in any round: the plain scan again.

@@ -83,7 +83,7 @@ struct Workspace {
   int32_t* item_start;  // [L+1]
   int32_t* item_list;   // [nq*max_nprobe] list of each work item
   int32_t* pairs;       // [nq*max_nprobe][2] (query, probe slot) grouped by list
-  uint32_t* queue;      // [4] work-queue counter
+  uint32_t* queue;      // [1] work-queue counter
   int32_t* spill_cnt;   // [nq] survivors per query
   uint64_t* spill;      // [nq][spill_cap] survivors
   int32_t* redo;        // [nq] 1 = survivors overflowed, recompute
@@ -154,6 +154,12 @@ hipError_t launch_batched_redo(const Tables& t, const float* Q, int32_t nq, int3
 hipError_t launch_debug_luts(const Tables& t, const float* Q, int32_t nq, const int32_t* probes,
                              const int32_t* nprobe, int32_t max_nprobe, uint8_t* out_lut, float* out_lo, float* out_delta, float* out_B,
                              hipStream_t s);
+// Batched form's tables per (q, p < nprobe_eff[q]) of w.probes, from the
+// builders the batched scan uses: out_lut [nq][max_nprobe][m][16] u8,
+// out_delta / out_B [nq][max_nprobe]. Needs w.bias for inner product.
+hipError_t launch_debug_batched_luts(const Tables& t, const float* Q, int32_t nq,
+                                     int32_t max_nprobe, const Workspace& w, uint8_t* out_lut,
+                                     float* out_delta, float* out_B, hipStream_t s);
 // pool: [nq][rerank] keys with point ids in their low 32 bits; reorder:
 // per-query re-rank sizes (<= rerank) or nullptr for all of them.
 hipError_t launch_rerank(const Tables& t, const float* Q, int32_t nq, int32_t k, int32_t rerank,

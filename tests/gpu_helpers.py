@@ -28,13 +28,12 @@ def unpack_tables(tables_u8, layout, m):
 def check_final(ids_g, dist_g, res, X, Q, metric, exact_ids=False):
     """GPU re-rank vs the oracle's FP64 re-rank of the same candidates."""
     ids_o, dist_o = res["ids"], res["dist"]
-    X64 = X.astype(np.float64)
     for qi in range(len(Q)):
         g = ids_g[qi]
         o = ids_o[qi]
         assert (g >= 0).sum() == (o >= 0).sum(), qi
         valid = g >= 0
-        rows = X64[g[valid]]
+        rows = X[g[valid]].astype(np.float64)
         q64 = Q[qi].astype(np.float64)
         if metric == "l2":
             e64 = ((rows - q64) ** 2).sum(1)
@@ -57,7 +56,7 @@ def check_final(ids_g, dist_g, res, X, Q, metric, exact_ids=False):
             if mism:
                 kth = do[-1]
                 for i in mism:
-                    r = X64[i]
+                    r = X[i].astype(np.float64)
                     e = ((r - q64) ** 2).sum() if metric == "l2" else r @ q64
                     assert abs(e - kth) <= TIE_BAND * max(abs(kth), 1e-30) + \
                         (TIE_BAND * scale.max() if metric == "ip" else 0), (qi, i)

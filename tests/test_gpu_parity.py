@@ -108,6 +108,22 @@ def test_luts_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_batched_luts_bit_exact(name):
+    # The batched form's own table builders (per-item L2 builders for every
+    # word count used here, the per-query IP table plus list bias), per
+    # (query, probed list), against the oracle's tables.
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    P = probes_tensor(res, nprobe)
+    lut, delta, B = [t.cpu().numpy() for t in g.debug_batched_luts(Q, P, nprobe)]
+    for qi, p in enumerate(res["probes"]):
+        for pi, l in enumerate(p):
+            q8, lo_o, d_o, B_o = res["luts"][(qi, int(l))]
+            assert np.array_equal(lut[qi, pi], q8), (qi, l)
+            assert delta[qi, pi].view(np.uint32) == np.float32(d_o).view(np.uint32), (qi, l)
+            assert B[qi, pi].view(np.uint32) == np.float32(B_o).view(np.uint32), (qi, l)
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_candidates_bit_exact(name):
     import paper_2511_03298_amd as ivf
     cfg, X, Q, nprobe, index, g, res = case(name)
