@@ -478,8 +478,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
     ap.add_argument("--forms", default="plain:exact,batched:bf16",
-                    help="comma list of form:coarse[:rN], e.g. plain:exact,batched:bf16:r3 "
-                         "(rN: N threshold-tightening rounds of the batched form)")
+                    help="comma list of form:coarse[:rN][:wN][:aN][:gN], e.g. "
+                         "plain:exact,batched:bf16:r3:w1:a32 (rN: threshold-tightening rounds of "
+                         "the batched form; wN / aN: widening factor / additive margin of an MFMA "
+                         "coarse form; gN: persistent workgroups per CU)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuned schedule (paper_2511_03298_amd.tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -602,8 +604,9 @@ def main():
     for spec in args.forms.split(","):
         parts = spec.split(":")
         form, coarse = (parts + ["exact"])[:2]
-        rounds = int(parts[2][1:]) if len(parts) > 2 and parts[2].startswith("r") else 0
-        runs.append(("fixed", ivf.make_opts(coarse=coarse, form=form, rounds=rounds)))
+        extra = {"r": "rounds", "w": "widen", "a": "widen_add", "g": "grid"}
+        kw = {extra[p_[0]]: int(p_[1:]) for p_ in parts[2:] if p_ and p_[0] in extra}
+        runs.append(("fixed", ivf.make_opts(coarse=coarse, form=form, **kw)))
     if not args.no_tune:
         from paper_2511_03298_amd.tune import autotune
         t0 = time.time()

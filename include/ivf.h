@@ -114,7 +114,8 @@ typedef struct {
 /* Coarse-scoring precision (step 1). IVF_COARSE_EXACT scores every list with
  * the canonical FP32 formula on the vector ALUs. The MFMA forms compute an
  * approximate score matrix (FP32, BF16, or FP8 e4m3 with per-row scales, all
- * with FP32 accumulation), keep the widen*nprobe best lists, re-score those
+ * with FP32 accumulation), keep the widen*nprobe + widen_add best lists,
+ * re-score those
  * with the canonical FP32 formula and keep the nprobe best. */
 typedef enum {
   IVF_COARSE_EXACT = 0,
@@ -171,6 +172,10 @@ typedef struct {
   int32_t nprobe_min;  /* >= 1                                                */
   int32_t reorder_min; /* >= 1                                                */
   float p0, p1;        /* finite                                              */
+  int32_t widen_add;   /* 0..16384: MFMA coarse forms keep min(L, widen*nprobe
+                          + widen_add) lists for the canonical re-score (an
+                          additive margin: the approximate scores only misorder
+                          lists near the cut)                                  */
 } ivf_search_opts;
 
 /* Entry points without a passage of the paper behind them are marked

@@ -57,7 +57,8 @@ class SearchOpts(ctypes.Structure):
                 ("rounds", ctypes.c_int32), ("spill_cap", ctypes.c_int32),
                 ("adaptive", ctypes.c_int32), ("nprobe_init", ctypes.c_int32),
                 ("nprobe_min", ctypes.c_int32), ("reorder_min", ctypes.c_int32),
-                ("p0", ctypes.c_float), ("p1", ctypes.c_float)]
+                ("p0", ctypes.c_float), ("p1", ctypes.c_float),
+                ("widen_add", ctypes.c_int32)]
 
 
 class TableLayout(ctypes.Structure):
@@ -131,7 +132,7 @@ def check(status: int):
 def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
               use_graph: bool = False, pool_cap: int = 0, grid: int = 0,
               rounds: int = 0, spill_cap: int = 0,
-              adaptive: Optional[dict] = None) -> SearchOpts:
+              adaptive: Optional[dict] = None, widen_add: int = 0) -> SearchOpts:
     """adaptive: dict(nprobe_init, nprobe_min, reorder_min, p0, p1) turns on
     the per-query probe count and re-rank size of Eq. 2 (nprobe[q] and
     rerank are the maxima)."""
@@ -140,6 +141,7 @@ def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
     o.coarse, o.widen, o.form = COARSE[coarse], int(widen), FORM[form]
     o.use_graph, o.pool_cap, o.grid = int(bool(use_graph)), int(pool_cap), int(grid)
     o.rounds, o.spill_cap = int(rounds), int(spill_cap)
+    o.widen_add = int(widen_add)
     if adaptive:
         o.adaptive = 1
         o.nprobe_init = int(adaptive["nprobe_init"])
@@ -154,7 +156,7 @@ def opts_dict(o: SearchOpts) -> dict:
     inv_f = {v: k for k, v in FORM.items()}
     d = dict(coarse=inv_c[o.coarse], widen=o.widen, form=inv_f[o.form],
              use_graph=bool(o.use_graph), pool_cap=o.pool_cap, grid=o.grid,
-             rounds=o.rounds, spill_cap=o.spill_cap)
+             rounds=o.rounds, spill_cap=o.spill_cap, widen_add=o.widen_add)
     if o.adaptive:
         d["adaptive"] = dict(nprobe_init=o.nprobe_init, nprobe_min=o.nprobe_min,
                              reorder_min=o.reorder_min, p0=o.p0, p1=o.p1)

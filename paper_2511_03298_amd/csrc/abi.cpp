@@ -181,6 +181,8 @@ ivf_status check_opts(const ivf_search_opts& o) {
   // widen * max_nprobe stays below 2^28 (L <= 16384), in range of int32.
   if (o.widen < 1 || o.widen > MAX_WIDEN)
     return fail(IVF_ERR_INVALID_ARG, "opts.widen must be in [1, 16384]");
+  if (o.widen_add < 0 || o.widen_add > MAX_LISTS)
+    return fail(IVF_ERR_INVALID_ARG, "opts.widen_add must be in [0, 16384]");
   if (o.form != IVF_FORM_PLAIN && o.form != IVF_FORM_BATCHED)
     return fail(IVF_ERR_INVALID_ARG, "opts.form out of range");
   if (o.use_graph != 0 && o.use_graph != 1)
@@ -288,6 +290,7 @@ void ivf_default_opts(ivf_search_opts* o) {
   if (!o) return;
   o->coarse = IVF_COARSE_EXACT;
   o->widen = 2;
+  o->widen_add = 0;
   o->form = IVF_FORM_PLAIN;
   o->use_graph = 0;
   o->pool_cap = 0;
@@ -607,11 +610,12 @@ ivf_status run_coarse(const ivf_index* idx, const float* Q, int32_t nq, const in
   if (o.coarse == IVF_COARSE_EXACT) {
     IVF_HIP(launch_coarse_exact(t, Q, nq, w.scores, s));
     IVF_HIP(prof_mark(idx, s, IVF_STAGE_SELECT));
-    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, 1, false, w, s, ad));
+    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, 1, 0, false, w, s, ad));
   } else {
     IVF_HIP(launch_coarse_mfma(t, Q, nq, o.coarse, w, s));
     IVF_HIP(prof_mark(idx, s, IVF_STAGE_SELECT));
-    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, o.widen, true, w, s, ad));
+    IVF_HIP(launch_select_probes(t, Q, nq, nprobe, max_nprobe, o.widen, o.widen_add, true, w,
+                                 s, ad));
   }
   return IVF_OK;
 }
@@ -637,6 +641,7 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
     if (!s) return fail(IVF_ERR_INVALID_ARG, "graph capture needs a non-default stream");
     std::vector<uint64_t> key = {(uint64_t)nq, (uint64_t)max_nprobe, (uint64_t)k,
                                  (uint64_t)rerank, (uint64_t)o.coarse, (uint64_t)o.widen,
+                                 (uint64_t)o.widen_add,
                                  (uint64_t)o.form, (uint64_t)o.pool_cap, (uint64_t)o.grid,
                                  (uint64_t)o.rounds, (uint64_t)o.spill_cap,
                                  (uint64_t)o.adaptive, (uint64_t)o.nprobe_init,
@@ -961,10 +966,10 @@ ivf_status ivf_assign(const float* centroids, int32_t L, int32_t d, int32_t metr
     w.probes = out_list + r0;  // max_nprobe = 1: one list per row
     if (coarse == IVF_COARSE_EXACT) {
       IVF_HIP(launch_coarse_exact(a.t, Xc, rows, w.scores, s));
-      IVF_HIP(launch_select_probes(a.t, Xc, rows, a.ones, 1, 1, false, w, s));
+      IVF_HIP(launch_select_probes(a.t, Xc, rows, a.ones, 1, 1, 0, false, w, s));
     } else {
       IVF_HIP(launch_coarse_mfma(a.t, Xc, rows, coarse, w, s));
-      IVF_HIP(launch_select_probes(a.t, Xc, rows, a.ones, 1, widen, true, w, s));
+      IVF_HIP(launch_select_probes(a.t, Xc, rows, a.ones, 1, widen, 0, true, w, s));
     }
   }
   return IVF_OK;
@@ -1004,7 +1009,7 @@ ivf_status ivf_assign_spill(const float* centroids, int32_t L, int32_t d, const 
     Workspace w = a.w;
     w.probes = out_list + r0;
     IVF_HIP(launch_spill_loss(X + r0 * d, rows, d, centroids, L, primary + r0, lam, w.scores, s));
-    IVF_HIP(launch_select_probes(a.t, X + r0 * d, rows, a.ones, 1, 1, false, w, s));
+    IVF_HIP(launch_select_probes(a.t, X + r0 * d, rows, a.ones, 1, 1, 0, false, w, s));
     IVF_HIP(launch_spill_fix(primary + r0, rows, L, out_list + r0, s));
   }
   return IVF_OK;

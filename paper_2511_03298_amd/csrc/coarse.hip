@@ -363,7 +363,8 @@ __device__ __forceinline__ bool reject_row(int q, int np, int max_nprobe,
 __global__ void __launch_bounds__(256) select_lds_kernel(Tables t, const float* __restrict__ Q,
                                                          int32_t nq, const int32_t* __restrict__ nprobe,
                                                          int32_t max_nprobe, int32_t widen,
-                                                         int32_t rescore, const float* __restrict__ S,
+                                                         int32_t widen_add, int32_t rescore,
+                                                         const float* __restrict__ S,
                                                          int32_t* __restrict__ probes,
                                                          int32_t* __restrict__ nprobe_eff,
                                                          int32_t* __restrict__ err, AdaptiveArgs ad,
@@ -378,7 +379,7 @@ __global__ void __launch_bounds__(256) select_lds_kernel(Tables t, const float* 
   const int np = nprobe[q];
   if (reject_row(q, np, max_nprobe, probes, nprobe_eff, err, reorder_eff)) return;
   const float* srow = S + (size_t)q * L;
-  const int want = rescore ? (int)min((int64_t)L, (int64_t)np * widen) : np;
+  const int want = rescore ? (int)min((int64_t)L, (int64_t)np * widen + widen_add) : np;
   for (int l = threadIdx.x; l < L; l += blockDim.x) keys[l] = make_key(srow[l], (uint32_t)l);
   __syncthreads();
   uint32_t n = (uint32_t)L;
@@ -398,7 +399,8 @@ template <int NK>
 __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __restrict__ Q,
                                                      int32_t nq, const int32_t* __restrict__ nprobe,
                                                      int32_t max_nprobe, int32_t widen,
-                                                     int32_t rescore, const float* __restrict__ S,
+                                                     int32_t widen_add, int32_t rescore,
+                                                     const float* __restrict__ S,
                                                      int32_t* __restrict__ probes,
                                                      int32_t* __restrict__ nprobe_eff,
                                                      int32_t* __restrict__ err,
@@ -415,7 +417,7 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
   const int np = nprobe[q];
   if (reject_row(q, np, max_nprobe, probes, nprobe_eff, err, reorder_eff)) return;
   const float* srow = S + (size_t)q * L;
-  const int want = rescore ? (int)min((int64_t)L, (int64_t)np * widen) : np;
+  const int want = rescore ? (int)min((int64_t)L, (int64_t)np * widen + widen_add) : np;
   uint32_t o[NK];
 #pragma unroll
   for (int i = 0; i < NK; ++i) {
@@ -429,11 +431,12 @@ __global__ void __launch_bounds__(256) select_kernel(Tables t, const float* __re
 
 hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
                                 const int32_t* nprobe, int32_t max_nprobe, int32_t widen,
-                                bool rescore, const Workspace& w, hipStream_t s,
-                                const AdaptiveArgs& ad) {
+                                int32_t widen_add, bool rescore, const Workspace& w,
+                                hipStream_t s, const AdaptiveArgs& ad) {
   if (nq == 0) return hipSuccess;
   const int32_t most =
-      rescore ? (int32_t)std::min<int64_t>(t.L, (int64_t)max_nprobe * widen) : max_nprobe;
+      rescore ? (int32_t)std::min<int64_t>(t.L, (int64_t)max_nprobe * widen + widen_add)
+              : max_nprobe;
   const int nk = (t.L + IVF_BLOCK - 1) / IVF_BLOCK;
   // Rows of 1025..2048 lists: the whole row in LDS (measured faster there
   // than the register form); shorter and longer rows: registers, so LDS (and
@@ -444,6 +447,7 @@ hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
   const size_t lds = (size_t)cap * sizeof(uint64_t);
   auto go = [&](auto kernel) {
     hipLaunchKernelGGL(kernel, dim3(nq), dim3(256), lds, s, t, Q, nq, nprobe, max_nprobe, widen,
+                       widen_add,
                        rescore ? 1 : 0, w.scores, w.probes, w.nprobe_eff, w.err, ad,
                        w.reorder_eff, cap);
     return hipGetLastError();

@@ -116,9 +116,9 @@ hipError_t launch_coarse_exact(const Tables& t, const float* Q, int32_t nq, floa
                                hipStream_t s);
 hipError_t launch_coarse_mfma(const Tables& t, const float* Q, int32_t nq, int coarse,
                               const Workspace& w, hipStream_t s);
-// Select per query the nprobe[q]*widen best lists of `scores` and, when
-// widen > 1 or the scores are approximate, re-score them canonically and
-// keep the nprobe[q] best. Writes probes / nprobe_eff; with `ad.on`, the
+// Select per query the min(L, nprobe[q]*widen + widen_add) best lists of
+// `scores` and, when the scores are approximate (`rescore`), re-score them
+// canonically and keep the nprobe[q] best. Writes probes / nprobe_eff; with `ad.on`, the
 // adaptive probe count and re-rank size of Eq. 2 (reorder_eff).
 struct AdaptiveArgs {
   int32_t on, nprobe_init, nprobe_min, reorder_min, k, R;
@@ -126,7 +126,7 @@ struct AdaptiveArgs {
 };
 hipError_t launch_select_probes(const Tables& t, const float* Q, int32_t nq,
                                 const int32_t* nprobe, int32_t max_nprobe, int32_t widen,
-                                bool rescore, const Workspace& w, hipStream_t s,
+                                int32_t widen_add, bool rescore, const Workspace& w, hipStream_t s,
                                 const AdaptiveArgs& ad = AdaptiveArgs{});
 hipError_t launch_copy_probes(const int32_t* probes, const int32_t* nprobe, int32_t nq,
                               int32_t max_nprobe, int32_t L, const Workspace& w,

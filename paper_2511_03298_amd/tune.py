@@ -4,11 +4,14 @@ For one index and one query-batch shape it measures a set of schedules on the
 device and keeps the fastest admissible one:
   * form: plain (one workgroup per query) or batched (persistent list-major);
   * coarse precision: exact FP32, or FP32/BF16/FP8 MFMA pre-selection with
-    widening 1, 2 or 4 -- admitted only when its probe sets agree with the
-    exact ones on at least `min_agree` of the queries (results are otherwise
-    bit-identical, the forms only change the schedule);
+    widening x1, x2 or x4 or an additive margin of 16-64 lists -- admitted
+    only when its probe sets agree with the exact ones on at least
+    `min_agree` of the queries (results are otherwise bit-identical, the
+    forms only change the schedule);
   * plain candidate-buffer size (pool_cap), batched persistent grid size and
-    number of threshold-tightening rounds.
+    number of threshold-tightening rounds;
+  * then the fastest schedule captured into a hipGraph and replayed on a
+    side stream (use_graph), kept when faster.
 Results are cached in a JSON file keyed by the device architecture and the
 shape (n, d, L, m, metric, nq, max_nprobe, k, rerank).
 """
@@ -31,29 +34,36 @@ def shape_key(g: GpuIndex, nq: int, max_nprobe: int, k: int, rerank: int) -> str
     return f"{arch}|n{g.n}|d{g.d}|L{g.L}|m{g.m}|{g.metric}|nq{nq}|p{max_nprobe}|k{k}|R{rerank}"
 
 
+COARSE_SPACE = (("exact", 2, 0), ("bf16", 1, 0), ("bf16", 1, 16), ("bf16", 1, 32),
+                ("bf16", 1, 64), ("bf16", 2, 0), ("bf16", 4, 0), ("fp8", 1, 64), ("fp8", 4, 0),
+                ("f32", 2, 0))
+
+
 def default_space():
     space = []
-    for coarse, widen in (("exact", 2), ("bf16", 1), ("bf16", 2), ("bf16", 4), ("fp8", 4),
-                          ("f32", 2)):
+    for coarse, widen, add in COARSE_SPACE:
+        c = dict(coarse=coarse, widen=widen, widen_add=add)
         for pool in (0, 2048, 4096):
-            space.append(dict(form="plain", coarse=coarse, widen=widen, pool_cap=pool))
+            space.append(dict(c, form="plain", pool_cap=pool))
         for rounds in (1, 3):
             for grid, pool in ((0, 0), (2, 0), (4, 0), (0, 4096)):
-                space.append(dict(form="batched", coarse=coarse, widen=widen, grid=grid,
-                                  pool_cap=pool, rounds=rounds))
+                space.append(dict(c, form="batched", grid=grid, pool_cap=pool, rounds=rounds))
     return space
 
 
-def _time(g, Qd, npd, k, rerank, max_nprobe, opts, ids, dist, reps):
+def _time(g, Qd, npd, k, rerank, max_nprobe, opts, ids, dist, reps, stream=None):
+    """Milliseconds per search; graph-captured schedules run on `stream`."""
     import torch
-    g.search(Qd, npd, k, rerank, max_nprobe=max_nprobe, opts=opts, out=(ids, dist))
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(reps):
+    stream = stream or torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
         g.search(Qd, npd, k, rerank, max_nprobe=max_nprobe, opts=opts, out=(ids, dist))
-    stop.record()
-    torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(reps):
+            g.search(Qd, npd, k, rerank, max_nprobe=max_nprobe, opts=opts, out=(ids, dist))
+        stop.record(stream)
+        torch.cuda.synchronize()
     return start.elapsed_time(stop) / reps
 
 
@@ -86,12 +96,13 @@ def autotune(g: GpuIndex, queries, nprobe, k: int, rerank: int,
     trials = []
     t0 = time.time()
     for cand in space or default_space():
-        ck = (cand["coarse"], cand["widen"])
+        ck = (cand["coarse"], cand["widen"], cand.get("widen_add", 0))
         if ck not in agree:
             if cand["coarse"] == "exact":
                 agree[ck] = 1.0
             else:
-                o = make_opts(coarse=cand["coarse"], widen=cand["widen"])
+                o = make_opts(coarse=cand["coarse"], widen=cand["widen"],
+                              widen_add=cand.get("widen_add", 0))
                 p = g.debug_probes(Qd, npd, max_nprobe=max_nprobe, opts=o).cpu()
                 agree[ck] = float((p == exact).all(dim=1).float().mean())
         if agree[ck] < min_agree:
@@ -102,7 +113,19 @@ def autotune(g: GpuIndex, queries, nprobe, k: int, rerank: int,
         if log:
             log(f"tune {cand}: {ms:.3f} ms")
     best = min(trials, key=lambda r: r["ms"])
-    best_opts = {k_: best[k_] for k_ in ("form", "coarse", "widen", "pool_cap", "grid", "rounds") if k_ in best}
+    best_opts = {k_: best[k_] for k_ in ("form", "coarse", "widen", "widen_add", "pool_cap",
+                                         "grid", "rounds") if k_ in best}
+    # The same schedule captured into a hipGraph and replayed (a side stream:
+    # capture needs one), kept when faster.
+    side = torch.cuda.Stream()
+    gms = _time(g, Qd, npd, k, rerank, max_nprobe, make_opts(**best_opts, use_graph=True), ids,
+                dist, reps, stream=side)
+    trials.append(dict(best_opts, use_graph=True, ms=gms, probe_agreement=best["probe_agreement"]))
+    if log:
+        log(f"tune {best_opts} graph-captured: {gms:.3f} ms (eager {best['ms']:.3f} ms)")
+    if gms < best["ms"]:
+        best_opts["use_graph"] = True
+        best = trials[-1]
     report = dict(key=key, best=opts_dict(make_opts(**best_opts)), best_ms=best["ms"],
                   trials=trials, seconds=round(time.time() - t0, 2))
     if cache_path:

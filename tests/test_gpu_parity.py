@@ -406,6 +406,31 @@ def test_mfma_probe_sets(name, coarse):
 
 
 @pytest.mark.parametrize("coarse", ["bf16", "fp8"])
+@pytest.mark.parametrize("name", ["c1", "c3s", "c5s"])
+def test_mfma_additive_margin(name, coarse):
+    # widen 1 plus a margin of lists: min(L, nprobe + add) lists re-scored.
+    # A margin covering every list is exact; a smaller one gives valid sets
+    # (distinct lists in canonical order, none better than the true ones).
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    full = g.debug_probes(Q, nprobe, opts=ivf.make_opts(coarse=coarse, widen=1,
+                                                        widen_add=cfg.L)).cpu().numpy()
+    for qi, p in enumerate(res["probes"]):
+        assert np.array_equal(full[qi, :len(p)], p), qi
+    for add in (0, 4):
+        got = g.debug_probes(Q, nprobe, opts=ivf.make_opts(coarse=coarse, widen=1,
+                                                           widen_add=add)).cpu().numpy()
+        for qi, p in enumerate(res["probes"]):
+            mine = got[qi, :len(p)]
+            assert len(set(mine.tolist())) == len(p) and np.all(got[qi, len(p):] == -1)
+            sm = canonical_sorted(index, Q[qi], cfg.metric, mine)
+            so = canonical_sorted(index, Q[qi], cfg.metric, p)
+            assert np.all(np.diff(sm) >= 0) and np.all(sm >= so)
+    with pytest.raises(ivf.IvfError, match="widen_add"):
+        g.debug_probes(Q, nprobe, opts=ivf.make_opts(coarse=coarse, widen=1, widen_add=-1))
+
+
+@pytest.mark.parametrize("coarse", ["bf16", "fp8"])
 @pytest.mark.parametrize("name", ["c2s", "c3s"])
 def test_mfma_search_matches_oracle_on_equal_probe_sets(name, coarse):
     import paper_2511_03298_amd as ivf
