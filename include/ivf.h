@@ -19,7 +19,8 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
  *     every call only enqueues work on it and returns, unless noted.
  *   - The library never allocates device memory. Table memory and search
- *     workspace are sized by the *_bytes queries and owned by the caller.
+ *     workspace are sized by the *_bytes queries and owned by the caller
+ *     (ivf_search_static instead uses a fixed array of the code object).
  *   - Host-side validation happens before anything is enqueued: on a non-OK
  *     status nothing was written and ivf_last_error() describes the problem.
  *     No exception crosses this boundary and the library never aborts.
@@ -241,6 +242,34 @@ ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries,
                                   const ivf_search_opts* opts, void* workspace,
                                   size_t workspace_bytes, int64_t* out_ids,
                                   float* out_dist, void* stream);
+
+/* Bytes of the library's static scratch array (one per device). */
+#define IVF_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* ivf_search without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, hosts that
+ * forbid hipMalloc). The workspace is a file-scope device array of
+ * IVF_STATIC_SCRATCH_BYTES in the library's code object: every device holds
+ * its own copy from the first call on it until the process ends, and this
+ * call neither allocates nor frees device memory. Same arguments (minus the
+ * workspace), outputs and validation as ivf_search, with these limits:
+ *   - a request whose workspace (ivf_search_workspace_bytes) exceeds
+ *     IVF_STATIC_SCRATCH_BYTES fails with IVF_ERR_WORKSPACE before any work
+ *     is enqueued: split the batch. With the BATCHED form and spill_cap 0 the
+ *     survivor capacity is the largest one (at most the automatic one,
+ *     at least 256 keys) that fits; results do not depend on it;
+ *   - opts->use_graph must be 0 (the caller may capture the call itself);
+ *   - the scratch is shared by every call on one device and keeps the last
+ *     call's contents (each search clears what it needs): calls that overlap
+ *     on one device, on different streams or host threads, race. Serialise
+ *     them, e.g. on one stream.
+ * The device is the current one (hipGetDevice), which must be the device of
+ * idx's table memory. */
+ivf_status ivf_search_static(const ivf_index* idx, const float* queries,
+                             int32_t nq, const int32_t* nprobe,
+                             int32_t max_nprobe, int32_t k, int32_t rerank,
+                             const ivf_search_opts* opts, int64_t* out_ids,
+                             float* out_dist, void* stream);
 
 /* Step 1 only: out_probes [nq,max_nprobe] int32 list indices ordered by
  * (canonical score, list index); entries past the query's probe count

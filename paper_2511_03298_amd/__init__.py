@@ -21,6 +21,7 @@ METRIC = {"l2": 0, "ip": 1}
 DTYPE = {"f32": 0, "bf16": 1, "u8": 2}
 COARSE = {"exact": 0, "f32": 1, "bf16": 2, "fp8": 3}
 FORM = {"plain": 0, "batched": 1}
+STATIC_SCRATCH_BYTES = 64 << 20  # IVF_STATIC_SCRATCH_BYTES of ivf.h
 
 EXPORTED = [
     "ivf_default_opts", "ivf_tables_bytes", "ivf_build_tables", "ivf_search_workspace_bytes",
@@ -29,6 +30,7 @@ EXPORTED = [
     "ivf_last_error", "ivf_profile_enable", "ivf_profile_read", "ivf_debug_coarse_scores",
     "ivf_assign_workspace_bytes", "ivf_assign", "ivf_encode", "ivf_debug_adaptive",
     "ivf_assign_spill_workspace_bytes", "ivf_assign_spill", "ivf_debug_batched_luts",
+    "ivf_search_static",
 ]
 STAGES = ("coarse", "select", "prep", "scan", "merge", "rerank")
 
@@ -99,6 +101,7 @@ def _declare(lib):
         "ivf_assign_spill": (I32, [P, I32, I32, P, I64, P, ctypes.c_float, I32, P, SZ, P, P]),
         "ivf_debug_adaptive": (I32, [P, P, I32, P, I32, I32, I32, P, P, SZ, P, P, P]),
         "ivf_debug_batched_luts": (I32, [P, P, I32, P, P, I32, P, SZ, P, P, P, P]),
+        "ivf_search_static": (I32, [P, P, I32, P, I32, I32, I32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -310,6 +313,25 @@ class GpuIndex:
         check(lib().ivf_search(self._h, _ptr(q), nq, _ptr(npb), max_nprobe, k, rerank,
                                ctypes.byref(opts), ws.data_ptr(), ws.numel(), _ptr(ids),
                                _ptr(dist), _stream()))
+        self._keep = (q, npb)
+        return ids, dist
+
+    def search_static(self, queries, nprobe, k: int, rerank: int, max_nprobe: int,
+                      opts: Optional[SearchOpts] = None, out=None):
+        """ivf_search_static: the search with the library's fixed device scratch
+        instead of a workspace (outputs may be passed in through `out`)."""
+        import torch
+        q = self._queries(queries)
+        nq = q.shape[0]
+        npb = self._nprobe(nprobe, nq)
+        opts = opts or make_opts()
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=self.device)
+            dist = torch.empty((nq, k), dtype=torch.float32, device=self.device)
+        else:
+            ids, dist = out
+        check(lib().ivf_search_static(self._h, _ptr(q), nq, _ptr(npb), max_nprobe, k, rerank,
+                                      ctypes.byref(opts), _ptr(ids), _ptr(dist), _stream()))
         self._keep = (q, npb)
         return ids, dist
 

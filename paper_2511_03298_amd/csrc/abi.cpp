@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -64,6 +65,32 @@ ivf_status hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 int32_t round_up_i(int64_t x, int64_t a) { return (int32_t)((x + a - 1) / a * a); }
+
+// Workspace of ivf_search_static. The name is a host-side stand-in: kernels
+// and copies get the per-device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) char scratch[IVF_STATIC_SCRATCH_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[SCRATCH_DEVICES] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device (each device holds its own copy at its own address).
+ivf_status static_scratch(void** out) {
+  int dev = -1;
+  IVF_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_DEVICES)
+    return fail(IVF_ERR_DEVICE, "device ordinal beyond the 64 the static scratch tracks");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    IVF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || (uintptr_t)p % 256) return fail(IVF_ERR_INTERNAL, "static scratch address invalid");
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return IVF_OK;
+}
 
 constexpr int32_t MAX_LISTS = 16384;
 constexpr int32_t MAX_WIDEN = MAX_LISTS;
@@ -704,6 +731,49 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
   if (st != IVF_OK) return st;
   return run_scan_and_rerank(idx, Qs, queries, nq, max_nprobe, k, rerank, o, w, out_ids, out_dist,
                              s);
+}
+
+ivf_status ivf_search_static(const ivf_index* idx, const float* queries, int32_t nq,
+                             const int32_t* nprobe, int32_t max_nprobe, int32_t k, int32_t rerank,
+                             const ivf_search_opts* opts, int64_t* out_ids, float* out_dist,
+                             void* stream) {
+  ivf_search_opts o;
+  ivf_default_opts(&o);
+  if (opts) o = *opts;
+  ivf_status st = check_opts(o);
+  if (st != IVF_OK) return st;
+  st = check_search(idx, nq, max_nprobe, k, rerank);
+  if (st != IVF_OK) return st;
+  if (o.use_graph) return fail(IVF_ERR_INVALID_ARG, "ivf_search_static needs opts.use_graph == 0");
+  const int32_t pool = rerank * idx->t.copies;
+  if (o.spill_cap > 16384 - pool)
+    return fail(IVF_ERR_INVALID_ARG, "opts.spill_cap must be at most 16384 - rerank * copies");
+  const size_t cap = IVF_STATIC_SCRATCH_BYTES;
+  if (o.form == IVF_FORM_BATCHED && o.spill_cap == 0) {
+    // The largest survivor capacity (from the automatic one down to 256
+    // keys, in steps of 256) whose workspace fits the scratch.
+    int32_t c = batched_spill_cap(pool, nq);
+    if (c > 16384 - 256) c = 16384 - 256;  // the range an explicit spill_cap takes
+    ivf_search_opts t = o;
+    for (;;) {
+      t.spill_cap = c;
+      if (plan_workspace(idx->t, nq, max_nprobe, k, rerank, t, nullptr).total <= cap || c <= 256)
+        break;
+      c = c - 256 > 256 ? (c - 1) / 256 * 256 : 256;
+    }
+    o.spill_cap = c;
+  }
+  const size_t need = plan_workspace(idx->t, nq, max_nprobe, k, rerank, o, nullptr).total;
+  if (need > cap)
+    return fail(IVF_ERR_WORKSPACE, "request needs " + std::to_string(need) +
+                                       " bytes of workspace; the static scratch holds " +
+                                       std::to_string(cap) + " (split the batch)");
+  if (nq == 0) return IVF_OK;
+  void* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st != IVF_OK) return st;
+  return ivf_search(idx, queries, nq, nprobe, max_nprobe, k, rerank, &o, ws, cap, out_ids,
+                    out_dist, stream);
 }
 
 ivf_status ivf_search_with_probes(const ivf_index* idx, const float* queries, int32_t nq,
