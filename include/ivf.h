@@ -116,8 +116,7 @@ typedef struct {
  * the canonical FP32 formula on the vector ALUs. The MFMA forms compute an
  * approximate score matrix (FP32, BF16, or FP8 e4m3 with per-row scales, all
  * with FP32 accumulation), keep the widen*nprobe + widen_add best lists,
- * re-score those
- * with the canonical FP32 formula and keep the nprobe best. */
+ * re-score those with the canonical FP32 formula and keep the nprobe best. */
 typedef enum {
   IVF_COARSE_EXACT = 0,
   IVF_COARSE_F32 = 1,
@@ -132,9 +131,9 @@ typedef enum { IVF_FORM_PLAIN = 0, IVF_FORM_BATCHED = 1 } ivf_form;
 
 typedef struct {
   int32_t coarse;    /* ivf_coarse                                              */
-  int32_t widen;     /* 1..16384; MFMA coarse forms keep min(L, widen*nprobe)
-                        lists before the canonical re-score (ignored by
-                        IVF_COARSE_EXACT)                                      */
+  int32_t widen;     /* 1..16384; MFMA coarse forms keep min(L, widen*nprobe
+                        + widen_add) lists before the canonical re-score
+                        (ignored by IVF_COARSE_EXACT)                         */
   int32_t form;      /* ivf_form                                                */
   int32_t use_graph; /* 1 = capture the whole search into a hipGraph on first
                         use with these exact arguments (sizes, options and

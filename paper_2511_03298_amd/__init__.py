@@ -13,7 +13,9 @@ import os
 from typing import Optional
 
 PKG_DIR = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG_DIR, "libivfpq.so")
+# IVFPQ_LIB selects another build of the same library (the host-sanitizer
+# build of the ABI tests); by default the in-tree one.
+LIB_PATH = os.environ.get("IVFPQ_LIB") or os.path.join(PKG_DIR, "libivfpq.so")
 
 IVF_OK, IVF_ERR_INVALID_ARG, IVF_ERR_DEVICE, IVF_ERR_WORKSPACE = 0, 1, 2, 3
 IVF_ERR_UNSUPPORTED, IVF_ERR_INTERNAL = 4, 5

@@ -31,13 +31,40 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build (argument
+# validation, layout and workspace planning run on the CPU): the sanitizers
+# instrument host code only, the device code is compiled as usual. The
+# shared sanitizer runtime has to be preloaded into the process that loads
+# the library (see asan_runtime()).
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all",
+                  "-shared-libsan"]
+ASAN_OUT = os.path.join(BUILD_DIR, "asan", "libivfpq_asan.so")
+
+
+def asan_runtime() -> str:
+    """Path of the shared ASan runtime of hipcc's clang."""
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("the clang ASan runtime was not found")
+    return path
+
+
+def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False) -> str:
+    bdir = os.path.join(BUILD_DIR, "asan") if sanitize else BUILD_DIR
+    out = ASAN_OUT if sanitize else OUT
+    extra = SANITIZE_FLAGS if sanitize else []
+    # The sanitized library records where its runtime lives, so programs
+    # linked against it find it.
+    link_extra = [f"-Wl,-rpath,{os.path.dirname(asan_runtime())}"] if sanitize else []
+    os.makedirs(bdir, exist_ok=True)
     cc = hipcc()
 
     def compile_one(src):
-        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-        cmd = [cc, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+        cmd = [cc, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
@@ -47,13 +74,13 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = OUT + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    tmp = out + ".tmp"
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *extra, *link_extra, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

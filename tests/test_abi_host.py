@@ -282,7 +282,8 @@ def test_header_is_plain_c_and_matches_the_binding(tmp_path):
     libdir = os.path.dirname(ivf.LIB_PATH)
     r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
                         "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
-                        "-L", libdir, "-l:libivfpq.so", f"-Wl,-rpath,{libdir}"],
+                        "-L", libdir, f"-l:{os.path.basename(ivf.LIB_PATH)}",
+                        f"-Wl,-rpath,{libdir}"],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
