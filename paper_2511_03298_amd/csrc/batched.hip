@@ -198,13 +198,6 @@ struct ItemStore {
     lut16[((j * halves + (g >> 3)) * 16 + code) * 8 + (g & 7)] = (uint16_t)v;
   }
 };
-struct QueryStore {
-  uint8_t* row;  // [16][m_pad]
-  int m_pad;
-  __device__ __forceinline__ void operator()(int j, int code, uint32_t v) const {
-    row[code * m_pad + j] = (uint8_t)v;
-  }
-};
 
 template <int W, class Store>
 __device__ __forceinline__ void wave_build_lut(const Tables& t, const float* rq, const float* cb_s,
@@ -413,22 +406,6 @@ __device__ __forceinline__ void wave_build_lut_lanes2(const Tables& t, const flo
   }
 }
 
-// Inner product: the table does not depend on the list (only the bias
-// does), so it is built once per query: one wave per query writes the u8
-// table, the pairwise sum of the subspace minima and delta.
-template <int W>
-__global__ void __launch_bounds__(256) query_lut_kernel(Tables t, const float* __restrict__ Q,
-                                                        int32_t nq, uint8_t* __restrict__ qlut,
-                                                        float* __restrict__ qlo_sum,
-                                                        float* __restrict__ qdelta) {
-  __shared__ float lo[IVF_NWAVES][W * 8];
-  const int q = blockIdx.x * IVF_NWAVES + wave_index();
-  if (q >= nq) return;  // per wave; no barriers below
-  const QueryStore store{qlut + (size_t)q * KSUB * t.m_pad, t.m_pad};
-  wave_build_lut<W>(t, Q + (size_t)q * t.d, t.codebooks, 0.0f, store, lo[wave_index()],
-                    qlo_sum + q, qdelta + q);
-}
-
 // ---------------------------------------------------------------------------
 // Phase 2: persistent list-major scan.
 // ---------------------------------------------------------------------------
@@ -456,8 +433,8 @@ constexpr bool cb_in_lds() { return W <= 16; }
 template <int W>
 constexpr bool lane_build() { return W * 8 <= 2 * IVF_WAVE; }
 
-// PER_QUERY (inner product): the tables come from query_lut_kernel and are
-// only copied per item; otherwise (L2) each item builds its residual tables.
+// PER_QUERY (inner product): the tables come from the first-list pass (one
+// per query, published by the plain kernel) and are only copied per item; otherwise (L2) each item builds its residual tables.
 // Three workgroups per CU (12 waves) fit the LDS of every shape; the register
 // budget is set to match (the unrolled word loop would otherwise hoist
 // most of its table reads and leave room for one).
@@ -808,21 +785,8 @@ hipError_t launch_batched_first(const Tables& t, const float* Q, int32_t nq, int
   if (nq == 0) return hipSuccess;
   hipError_t e;
   if ((e = launch_fill_u32((uint32_t*)w.redo, 0u, (size_t)nq, s)) != hipSuccess) return e;
-  if (t.metric == IVF_METRIC_IP) {
-    switch (t.words) {
-#define X(N)                                                                                   \
-  case N:                                                                                      \
-    hipLaunchKernelGGL(query_lut_kernel<N>, dim3((nq + IVF_NWAVES - 1) / IVF_NWAVES), dim3(256), \
-                       0, s, t, Q, nq, w.qlut, w.qlo_sum, w.qdelta);                            \
-    break;
-      X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
-      X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24)
-#undef X
-      default: return hipErrorNotSupported;
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  // First lists per query -> pool, threshold, first probe rank of the rounds.
+  // First lists per query -> pool, threshold, first probe rank of the rounds
+  // and, for inner product, the per-query tables of the list-major scan.
   return launch_scan_plain_ex(t, Q, nq, max_nprobe, R, w, w.p1, w.thr, nullptr, s);
 }
 
@@ -917,8 +881,9 @@ hipError_t launch_batched_merge(const Tables& t, int32_t nq, int32_t R, const Wo
 // Parity export of the batched form's tables. Per (query, probe slot) the
 // table the scan would use, as u8 [m][16] with its scale delta and constant
 // B: for L2 the scan kernel's own per-item builder for this W (the query in
-// slot 0 of an item, one wave), for inner product the per-query table of
-// query_lut_kernel with B = its pairwise sum of the minima + the list bias.
+// slot 0 of an item, one wave), for inner product the per-query table the
+// first-list pass publishes, with B = its pairwise sum of the minima + the
+// list bias.
 // ---------------------------------------------------------------------------
 
 template <int W>
@@ -984,8 +949,9 @@ static hipError_t launch_lut_export_w(const Tables& t, const float* Q, int32_t n
                                       int32_t max_nprobe, const Workspace& w, uint8_t* out_lut,
                                       float* out_delta, float* out_B, hipStream_t s) {
   if (t.metric == IVF_METRIC_IP) {
-    hipLaunchKernelGGL(query_lut_kernel<W>, dim3((nq + IVF_NWAVES - 1) / IVF_NWAVES), dim3(256), 0,
-                       s, t, Q, nq, w.qlut, w.qlo_sum, w.qdelta);
+    // The per-query tables come from the first-list pass, as in the search.
+    hipError_t e = launch_scan_plain_ex(t, Q, nq, max_nprobe, 1, w, w.p1, w.thr, nullptr, s);
+    if (e != hipSuccess) return e;
   }
   const size_t lds = t.metric == IVF_METRIC_IP ? 0
                      : lane_build<W>()     ? (size_t)W * 8 * KSUB * t.dsub * 4

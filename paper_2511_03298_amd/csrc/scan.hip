@@ -126,7 +126,10 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
                                                          uint64_t* __restrict__ cand,
                                                          int32_t* __restrict__ p1_out,
                                                          uint64_t* __restrict__ thr_out,
-                                                         const int32_t* __restrict__ only) {
+                                                         const int32_t* __restrict__ only,
+                                                         uint8_t* __restrict__ qlut_out,
+                                                         float* __restrict__ qlo_out,
+                                                         float* __restrict__ qdelta_out) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ ScanShared<W> sh;
   const int q = blockIdx.x;
@@ -166,6 +169,17 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
     lut_float(t, qv, 0, Tf);
     __syncthreads();
     lut_quantize(t, Tf, sh.lo, sh.lut8, &sh.st);
+    if (qlut_out) {
+      // First-list pass of the batched form: publish the query's table for
+      // the list-major scan (code-major: entry (j, c) at c * m_pad + j).
+      uint8_t* dst = qlut_out + (size_t)q * KSUB * t.m_pad;
+      for (int e = tid; e < t.m_pad * KSUB; e += blockDim.x)
+        dst[e] = sh.lut8[(e % t.m_pad) * KSUB + e / t.m_pad];
+      if (tid == 0) {
+        qlo_out[q] = sh.st.lo_sum;
+        qdelta_out[q] = sh.st.delta;
+      }
+    }
   }
   const int lane = lane_id();
   int seen = 0, p_end = np;
@@ -299,8 +313,11 @@ static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t n
                                       hipStream_t s) {
   const int32_t cap = scan_cap(R, w.pool_cap);
   size_t lds = (size_t)(R + cap) * 8 + (size_t)t.m_pad * KSUB * 4 + (size_t)t.d * 4;
+  const bool pub = p1_out && t.metric == IVF_METRIC_IP;
   hipLaunchKernelGGL(scan_plain_kernel<W>, dim3(nq), dim3(256), lds, s, t, Q, nq, max_nprobe, R,
-                     cap, w.probes, w.nprobe_eff, w.bias, w.cand, p1_out, thr_out, only);
+                     cap, w.probes, w.nprobe_eff, w.bias, w.cand, p1_out, thr_out, only,
+                     pub ? w.qlut : nullptr, pub ? w.qlo_sum : nullptr,
+                     pub ? w.qdelta : nullptr);
   return hipGetLastError();
 }
 
