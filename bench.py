@@ -157,19 +157,21 @@ def _cpu_worker(span):
         return time.perf_counter() - t0
 
 
-def _cpu_server(conn, X, Q, nprobe, k, R, per_worker):
-    """Child process: wait for the index path, time the oracle, send the row."""
+def _cpu_server(conn, X, Q, k, R, per_worker):
+    """Child process: wait for the index path and the per-query probe counts
+    of the measured operating point, time the oracle, send the row."""
     import multiprocessing as mp
 
     from threadpoolctl import threadpool_limits
 
     import oracle
     try:
-        path = conn.recv()
+        msg = conn.recv()
     except EOFError:  # the parent ended without handing over an index
         return
-    if path is None:
+    if msg is None:
         return
+    path, nprobe = msg
     index = load_index(path, mmap=True)
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
     with threadpool_limits(1):
@@ -196,34 +198,37 @@ def _cpu_server(conn, X, Q, nprobe, k, R, per_worker):
 
 
 class CpuBaseline:
-    """Forks the oracle's timing process now (no GPU state yet); run(index)
-    hands it the trained index and waits for its result."""
+    """Forks the oracle's timing process now (no GPU state yet); stage(index)
+    writes the trained index for it, run(nprobe) hands over the per-query
+    probe counts of the measured operating point and waits for the result."""
 
-    def __init__(self, X, Q, nprobe, k, R, per_worker=32):
+    def __init__(self, X, Q, k, R, per_worker=32):
         import multiprocessing as mp
         ctx = mp.get_context("fork")
         self.conn, child = ctx.Pipe()
         # Not a daemon: it forks the worker pool itself. close() ends it.
-        self.proc = ctx.Process(target=_cpu_server, args=(child, X, Q, nprobe, k, R, per_worker))
+        self.proc = ctx.Process(target=_cpu_server, args=(child, X, Q, k, R, per_worker))
         self.proc.start()
         self.done = False
+        self.path = None
 
-    def run(self, index):
-        import shutil
+    def stage(self, index):
         import tempfile
         base = "/dev/shm" if os.access("/dev/shm", os.W_OK) else None
-        path = tempfile.mkdtemp(prefix="ivf_oracle_", dir=base)
+        self.path = tempfile.mkdtemp(prefix="ivf_oracle_", dir=base)
+        save_index(index, self.path)
+
+    def run(self, nprobe):
         try:
-            save_index(index, path)
-            self.conn.send(path)
+            self.conn.send((self.path, np.asarray(nprobe, dtype=np.int32)))
             out = self.conn.recv()
             self.done = True
         finally:
             self.close()
-            shutil.rmtree(path, ignore_errors=True)
         return out
 
     def close(self):
+        import shutil
         if not self.done:
             self.done = True
             try:
@@ -234,6 +239,9 @@ class CpuBaseline:
         if self.proc.is_alive():
             self.proc.terminate()
             self.proc.join(timeout=10)
+        if self.path:
+            shutil.rmtree(self.path, ignore_errors=True)
+            self.path = None
 
 
 # ---------------------------------------------------------------------------
@@ -331,6 +339,44 @@ def roofline(config, cfg, r, code_bytes):
     return out
 
 
+NPROBE_LADDER = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256)
+FACTOR_LADDER = (1 / 16, 1 / 8, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0)
+RECALL_TARGET = 0.90
+
+
+def probe_ladder(cfg, base):
+    """Probe settings in ascending order: uniform nprobe values for workloads
+    with one configured nprobe, else the per-query draws `base` scaled by a
+    factor (rounded, clamped to [1, L])."""
+    import torch
+    if cfg.nprobe[0] == cfg.nprobe[1]:
+        return [(f"static nprobe {v}", torch.full_like(base, v, dtype=torch.int32))
+                for v in NPROBE_LADDER if v <= cfg.L]
+    return [(f"static x{f:g}", torch.clamp((base.double() * f).round().to(torch.int64), 1,
+                                           cfg.L).to(torch.int32)) for f in FACTOR_LADDER]
+
+
+def operating_point(g, cfg, Qd, npd, gt_ids, nrec, ids, dist):
+    """The measured operating point: the first (cheapest) setting of the probe
+    ladder whose Recall@10 reaches the target, searched with the batched BF16
+    form; the configured draws when no setting reaches it. Returns (label,
+    per-query nprobe tensor, the ladder's recalls)."""
+    import paper_2511_03298_amd as ivf
+    opts = ivf.make_opts(form="batched", coarse="bf16")
+    tried = []
+    for label, nprobe in probe_ladder(cfg, npd):
+        g.search(Qd, nprobe, cfg.k, cfg.R, max_nprobe=int(nprobe.max()), opts=opts,
+                 out=(ids, dist))
+        rec = recall_at_k(ids[:nrec].cpu().numpy(), gt_ids, 10)
+        tried.append({"setting": label, "mean_nprobe": round(float(nprobe.float().mean()), 2),
+                      "recall_at_10": round(rec, 4)})
+        log(f"operating point search: {label} (mean nprobe {tried[-1]['mean_nprobe']}): "
+            f"recall@10 {rec:.4f}")
+        if rec >= RECALL_TARGET:
+            return label, nprobe, tried
+    return "configured nprobe (no setting reached the target)", npd, tried
+
+
 def sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args):
     """Static nprobe values (scaled per query for per-query workloads) and
     adaptive settings (section 4.2, Eq. 2) of the batched BF16 form: QPS,
@@ -366,16 +412,7 @@ def sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args):
 
     top = int(base.max())
     seen = set()
-    # Uniform-nprobe workloads: a ladder of nprobe values; per-query ones: the
-    # per-query draws scaled by a factor (clamped to [1, L]).
-    if cfg.nprobe[0] == cfg.nprobe[1]:
-        settings = [(f"static nprobe {v}", torch.full_like(base, v)) for v in
-                    (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256) if v <= cfg.L]
-    else:
-        settings = [(f"static x{f:g}", (base.double() * f).round())
-                    for f in (1 / 16, 1 / 8, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0)]
-    for label, raw in settings:
-        nprobe = torch.clamp(raw.to(torch.int64), 1, cfg.L).to(torch.int32)
+    for label, nprobe in probe_ladder(cfg, npd):
         sig = (int(nprobe.min()), int(nprobe.max()), int(nprobe.sum()))
         if sig in seen:
             continue
@@ -529,7 +566,12 @@ def main():
     X, Q, nprobe = make_workload(cfg, log=log)
     log(f"generated in {time.time() - t0:.1f}s; training IVF-PQ (L={cfg.L}, m={cfg.m})")
     # The oracle's timing process is forked now, before the GPU is touched.
-    cpu_job = None if args.no_cpu_baseline else CpuBaseline(X, Q, nprobe, cfg.k, cfg.R)
+    cpu_job = None if args.no_cpu_baseline else CpuBaseline(X, Q, cfg.k, cfg.R)
+    if cpu_job is not None:
+        # On any early exit the child is told to stop before the interpreter
+        # joins it (atexit handlers run in reverse registration order).
+        import atexit
+        atexit.register(cpu_job.close)
     t0 = time.time()
     try:
         index, gpu_trained, loaded = build_index(args, cfg, X, log)
@@ -545,11 +587,8 @@ def main():
     log(f"index ready in {time.time() - t0:.1f}s ({'cache' if loaded else 'GPU' if gpu_trained else 'host'}); "
         f"list length mean {lens.mean():.0f} max {lens.max()}")
 
-    cpu = None
     if cpu_job is not None:
-        log("timing the CPU oracle on the host cores")
-        cpu = cpu_job.run(index)
-        log(f"oracle: {cpu['value']} q/s on {cpu['cores']} cores ({cpu['sample']})")
+        cpu_job.stage(index)
 
     nrec = min(args.recall_queries, cfg.nq)
     t0 = time.time()
@@ -577,10 +616,21 @@ def main():
     g = ivf.GpuIndex.from_index(index, X, base_dtype=cfg.base_dtype)
     del index
     Qd = torch.from_numpy(Q).cuda()
-    npd = torch.from_numpy(nprobe).cuda()
-    max_np = int(nprobe.max())
+    npd_cfg = torch.from_numpy(nprobe).cuda()
     ids = torch.empty((cfg.nq, cfg.k), dtype=torch.int64, device="cuda")
     dist = torch.empty((cfg.nq, cfg.k), dtype=torch.float32, device="cuda")
+
+    # The operating point every form is measured at: the cheapest probe
+    # setting reaching Recall@10 >= 0.90 (no interpolation).
+    op_label, npd, ladder = operating_point(g, cfg, Qd, npd_cfg, gt_ids, nrec, ids, dist)
+    max_np = int(npd.max())
+    log(f"operating point: {op_label}, mean nprobe {float(npd.float().mean()):.1f}, "
+        f"max {max_np}")
+    cpu = None
+    if cpu_job is not None:
+        log("timing the CPU oracle on the host cores at the operating point")
+        cpu = cpu_job.run(npd.cpu().numpy())
+        log(f"oracle: {cpu['value']} q/s on {cpu['cores']} cores ({cpu['sample']})")
 
     # Algorithmic bytes of one scan launch: ceil(m/2) code bytes per
     # (query, scanned point), from the probe sets the GPU selects.
@@ -691,6 +741,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.config, args.config), "n": cfg.n,
                    "d": cfg.d, "nq": cfg.nq, "L": cfg.L, "m": cfg.m, "nprobe": list(cfg.nprobe),
+                   "operating_point": {"setting": op_label,
+                                       "mean_nprobe": round(float(npd.float().mean()), 2),
+                                       "max_nprobe": max_np, "ladder": ladder},
                    "k": cfg.k, "rerank": cfg.R, "sigma": cfg.sigma, "form": best["form"],
                    "coarse": best["coarse"],
                    "filter": args.filter, "dims_kept": None if dims is None else int(len(dims)),
@@ -710,7 +763,7 @@ def main():
         "cpu_baseline": cpu,
     }
     if args.sweep:
-        line["sweep"] = sweep(g, cfg, Qd, npd, gt_ids, nrec, lens, ids, dist, args)
+        line["sweep"] = sweep(g, cfg, Qd, npd_cfg, gt_ids, nrec, lens, ids, dist, args)
         fast = [p for p in line["sweep"] if p["recall_at_10"] >= 0.90]
         line["fastest_sweep_point_at_recall_0.90"] = (max(fast, key=lambda p: p["qps"])
                                                       if fast else None)

@@ -55,3 +55,40 @@ def test_traffic_only_while_sources_match():
             assert t == int(rec["fetch_kib"] * 1024 * 2.0 + rec["write_kib"] * 1024)
         else:
             assert t is None
+
+
+def test_probe_ladder_settings():
+    import torch
+
+    import bench
+    from workloads import CONFIGS, scaled
+    c2 = CONFIGS["c2"]
+    base = torch.full((5,), 32, dtype=torch.int32)
+    lad = bench.probe_ladder(c2, base)
+    vals = [int(t[0]) for _, t in lad]
+    assert vals == list(bench.NPROBE_LADDER) and all(t.dtype == torch.int32 for _, t in lad)
+    small = scaled("c2", n=4000, nq=5, L=20, ncomp=20)   # values above L are left out
+    assert [int(t[0]) for _, t in bench.probe_ladder(small, base)] == [1, 2, 3, 4, 6, 8, 12, 16]
+    c5 = CONFIGS["c5"]
+    draws = torch.tensor([4, 7, 100, 256], dtype=torch.int32)
+    lad = bench.probe_ladder(c5, draws)
+    assert [lbl for lbl, _ in lad][0] == "static x0.0625"
+    x16 = dict(lad)["static x0.0625"]
+    assert x16.tolist() == [1, 1, 6, 16]          # rounded, clamped to >= 1
+    x2 = dict(lad)["static x2"]
+    assert x2.tolist() == [8, 14, 200, 512]
+    assert all(int(t.max()) <= c5.L for _, t in lad)
+
+
+def test_cpu_baseline_times_the_oracle_at_the_given_probe_counts():
+    import bench
+    from workloads import make_workload, scaled, train_index
+    cfg = scaled("c1", n=600, nq=4, L=8, ncomp=8)
+    X, Q, nprobe = make_workload(cfg)
+    index = train_index(X, cfg)
+    job = bench.CpuBaseline(X, Q, cfg.k, cfg.R, per_worker=2)
+    job.stage(index)
+    row = job.run(np.full(cfg.nq, 3, dtype=np.int32))
+    assert row["kind"] == "oracle" and row["unit"] == "queries/s" and row["value"] > 0
+    assert row["cores"] >= 1 and "queries" in row["sample"]
+    assert job.path is None   # staged files removed
