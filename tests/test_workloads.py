@@ -63,3 +63,15 @@ def test_trained_index_is_a_valid_partition():
     assert len(lists_of) == len(X)
     assert all(len(v) == 2 and v[0] != v[1] for v in lists_of.values())
     assert sp["codes"].shape == (2 * len(X), cfg.m)
+
+
+def test_calibrated_spreads_are_frozen():
+    # The spreads chosen so that Recall@10 = 0.90 falls at a mid-range probe
+    # setting of each full-size workload (the sweep values are recorded next
+    # to CONFIGS); a change here changes every measured number.
+    want = {"c1": 0.1, "c2": 60.0, "c3": 1.0, "c4": 1.45, "c5": 1.15, "c6": 16.0}
+    assert {k: CONFIGS[k].sigma for k in want} == want
+    # The spread acts where the generator says: wider rows, same means.
+    narrow = make_workload(scaled("c2", 3000, 5, L=8, ncomp=8, sigma=16.0))[0]
+    wide = make_workload(scaled("c2", 3000, 5, L=8, ncomp=8))[0]
+    assert wide.std() > narrow.std()
