@@ -344,6 +344,24 @@ FACTOR_LADDER = (1 / 16, 1 / 8, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0)
 RECALL_TARGET = 0.90
 
 
+def batched_scan_points(probes, lens, pool, first_lists):
+    """Points the batched scan kernel covers per step: every probed list after
+    the ones the first-list pass scans. That pass walks a query's lists in
+    order: at least `first_lists` of them (0 = the default, 4), and on while
+    it has seen fewer than `pool` points -- the rule ivf.h states for
+    opts.first_lists."""
+    first = first_lists if first_lists > 0 else 4
+    total = 0
+    for row in probes:
+        row = row[row >= 0]
+        seen, p = 0, 0
+        while p < len(row) and (seen < pool or p < first):
+            seen += int(lens[row[p]])
+            p += 1
+        total += int(lens[row[p:]].sum())
+    return total
+
+
 def probe_ladder(cfg, base):
     """Probe settings in ascending order: uniform nprobe values for workloads
     with one configured nprobe, else the per-query draws `base` scaled by a
@@ -515,10 +533,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c5", choices=sorted(CONFIGS))
     ap.add_argument("--forms", default="plain:exact,batched:bf16",
-                    help="comma list of form:coarse[:rN][:wN][:aN][:gN], e.g. "
+                    help="comma list of form:coarse[:rN][:wN][:aN][:gN][:fN], e.g. "
                          "plain:exact,batched:bf16:r3:w1:a32 (rN: threshold-tightening rounds of "
                          "the batched form; wN / aN: widening factor / additive margin of an MFMA "
-                         "coarse form; gN: persistent workgroups per CU)")
+                         "coarse form; gN: persistent workgroups per CU; fN: lists of the batched "
+                         "form's first-list pass)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuned schedule (paper_2511_03298_amd.tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -637,24 +656,13 @@ def main():
     probes = g.debug_probes(Qd, npd, max_nprobe=max_np).cpu().numpy()
     scanned = int(lens[probes[probes >= 0]].sum())
     code_bytes = (cfg.m + 1) // 2
-    # The batched scan kernel covers the lists after each query's first ones
-    # holding >= R * copies entries (those go through the first-list pass).
-    scanned_main = 0
-    for row in probes:
-        row = row[row >= 0]
-        seen, p = 0, 0
-        while p < len(row) and seen < cfg.R * copies:
-            seen += int(lens[row[p]])
-            p += 1
-        scanned_main += int(lens[row[p:]].sum())
-    log(f"points scanned per step {scanned} ({scanned / cfg.nq:.0f} per query); "
-        f"batched scan kernel {scanned_main}")
+    log(f"points scanned per step {scanned} ({scanned / cfg.nq:.0f} per query)")
 
     runs = []
     for spec in args.forms.split(","):
         parts = spec.split(":")
         form, coarse = (parts + ["exact"])[:2]
-        extra = {"r": "rounds", "w": "widen", "a": "widen_add", "g": "grid"}
+        extra = {"r": "rounds", "w": "widen", "a": "widen_add", "g": "grid", "f": "first_lists"}
         kw = {extra[p_[0]]: int(p_[1:]) for p_ in parts[2:] if p_ and p_[0] in extra}
         runs.append(("fixed", ivf.make_opts(coarse=coarse, form=form, **kw)))
     if not args.no_tune:
@@ -709,7 +717,8 @@ def main():
             d2h_ms = (time.perf_counter() - t0) * 1000.0 / max(2, args.steps // 2)
         per = {k_: v / max(count, 1) for k_, v in stage_ms.items()}
         scan_ms = per["scan"]
-        pts = scanned_main if form == "batched" else scanned
+        pts = (batched_scan_points(probes, lens, cfg.R * copies, od["first_lists"])
+               if form == "batched" else scanned)
         r = dict(form=form, coarse=coarse, schedule=label, opts=od, dtype=path_dtype(coarse),
                  qps=cfg.nq / (ms_step / 1000.0), ms_per_step=ms_step,
                  qps_with_d2h=cfg.nq / (d2h_ms / 1000.0),

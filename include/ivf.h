@@ -176,6 +176,13 @@ typedef struct {
                           + widen_add) lists for the canonical re-score (an
                           additive margin: the approximate scores only misorder
                           lists near the cut)                                  */
+  int32_t first_lists; /* BATCHED: the first-list pass, whose pool's largest
+                          key is the first threshold of the rounds, scans each
+                          query's nearest lists in coarse order: at least
+                          first_lists of them, and on until it has seen
+                          rerank*copies points. 1..64, 0 = auto (4). More
+                          lists: a tighter first threshold (fewer survivors to
+                          merge) for more per-query scanning.                 */
 } ivf_search_opts;
 
 /* Entry points without a passage of the paper behind them are marked

@@ -210,6 +210,8 @@ ivf_status check_opts(const ivf_search_opts& o) {
     return fail(IVF_ERR_INVALID_ARG, "opts.widen must be in [1, 16384]");
   if (o.widen_add < 0 || o.widen_add > MAX_LISTS)
     return fail(IVF_ERR_INVALID_ARG, "opts.widen_add must be in [0, 16384]");
+  if (o.first_lists < 0 || o.first_lists > 64)
+    return fail(IVF_ERR_INVALID_ARG, "opts.first_lists must be in [0, 64]");
   if (o.form != IVF_FORM_PLAIN && o.form != IVF_FORM_BATCHED)
     return fail(IVF_ERR_INVALID_ARG, "opts.form out of range");
   if (o.use_graph != 0 && o.use_graph != 1)
@@ -285,6 +287,7 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   }
   w.pool_cap = o.pool_cap;
   w.grid = o.grid;
+  w.first_lists = o.first_lists > 0 ? o.first_lists : 4;
   if (o.form == IVF_FORM_BATCHED) {
     w.spill_cap = o.spill_cap > 0 ? o.spill_cap : batched_spill_cap(pool, nq);
     w.p1 = (int32_t*)take(nqs * 4);
@@ -318,6 +321,7 @@ void ivf_default_opts(ivf_search_opts* o) {
   o->coarse = IVF_COARSE_EXACT;
   o->widen = 2;
   o->widen_add = 0;
+  o->first_lists = 0;
   o->form = IVF_FORM_PLAIN;
   o->use_graph = 0;
   o->pool_cap = 0;
@@ -668,7 +672,7 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
     if (!s) return fail(IVF_ERR_INVALID_ARG, "graph capture needs a non-default stream");
     std::vector<uint64_t> key = {(uint64_t)nq, (uint64_t)max_nprobe, (uint64_t)k,
                                  (uint64_t)rerank, (uint64_t)o.coarse, (uint64_t)o.widen,
-                                 (uint64_t)o.widen_add,
+                                 (uint64_t)o.widen_add, (uint64_t)o.first_lists,
                                  (uint64_t)o.form, (uint64_t)o.pool_cap, (uint64_t)o.grid,
                                  (uint64_t)o.rounds, (uint64_t)o.spill_cap,
                                  (uint64_t)o.adaptive, (uint64_t)o.nprobe_init,

@@ -96,6 +96,7 @@ struct Workspace {
   int32_t spill_cap;
   int32_t pool_cap;  // plain scan candidate buffer beyond R (0 = auto)
   int32_t grid;      // batched workgroups per CU (0 = auto)
+  int32_t first_lists;  // batched first-list pass: lists scanned at least (>= 1)
 };
 
 int32_t batched_spill_cap(int32_t rerank, int32_t nq);

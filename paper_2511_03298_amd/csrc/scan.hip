@@ -127,6 +127,7 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
                                                          int32_t* __restrict__ p1_out,
                                                          uint64_t* __restrict__ thr_out,
                                                          const int32_t* __restrict__ only,
+                                                         int32_t first_lists,
                                                          uint8_t* __restrict__ qlut_out,
                                                          float* __restrict__ qlo_out,
                                                          float* __restrict__ qdelta_out) {
@@ -138,9 +139,10 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
   uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);            // [R + cap]
   float* Tf = reinterpret_cast<float*>(keys + R + cap);          // [m_pad*16]
   float* qv = Tf + t.m_pad * KSUB;                               // [d]
-  // `only`: recompute just the flagged queries. `p1_out`: stop after the
-  // first lists holding at least R points, and publish where phase 2 starts
-  // and the R-th smallest key (the batched form's threshold).
+  // `only`: recompute just the flagged queries. `p1_out`: the batched form's
+  // first-list pass: stop after the first first_lists lists, or later, once
+  // the lists scanned hold at least R points, and publish where phase 2
+  // starts and the R-th smallest key (the rounds' first threshold).
   if (only && only[q] == 0) return;
   const int np = nprobe_eff[q];
 
@@ -184,7 +186,7 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
   const int lane = lane_id();
   int seen = 0, p_end = np;
   for (int p = 0; p < np; ++p) {
-    if (p1_out && seen >= R) {
+    if (p1_out && seen >= R && p >= first_lists) {
       p_end = p;
       break;
     }
@@ -316,6 +318,7 @@ static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t n
   const bool pub = p1_out && t.metric == IVF_METRIC_IP;
   hipLaunchKernelGGL(scan_plain_kernel<W>, dim3(nq), dim3(256), lds, s, t, Q, nq, max_nprobe, R,
                      cap, w.probes, w.nprobe_eff, w.bias, w.cand, p1_out, thr_out, only,
+                     w.first_lists > 0 ? w.first_lists : 1,
                      pub ? w.qlut : nullptr, pub ? w.qlo_sum : nullptr,
                      pub ? w.qdelta : nullptr);
   return hipGetLastError();

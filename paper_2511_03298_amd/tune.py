@@ -8,8 +8,9 @@ device and keeps the fastest admissible one:
     only when its probe sets agree with the exact ones on at least
     `min_agree` of the queries (results are otherwise bit-identical, the
     forms only change the schedule);
-  * plain candidate-buffer size (pool_cap), batched persistent grid size and
-    number of threshold-tightening rounds;
+  * plain candidate-buffer size (pool_cap), batched persistent grid size,
+    number of threshold-tightening rounds and lists of the first-list pass
+    (first_lists);
   * then the fastest schedule captured into a hipGraph and replayed on a
     side stream (use_graph), kept when faster.
 Results are cached in a JSON file keyed by the device architecture and the
@@ -45,9 +46,11 @@ def default_space():
         c = dict(coarse=coarse, widen=widen, widen_add=add)
         for pool in (0, 2048, 4096):
             space.append(dict(c, form="plain", pool_cap=pool))
-        for rounds in (1, 3):
-            for grid, pool in ((0, 0), (2, 0), (4, 0), (0, 4096)):
-                space.append(dict(c, form="batched", grid=grid, pool_cap=pool, rounds=rounds))
+        for rounds in (1, 2, 3):
+            for depth in (1, 2, 4, 8):
+                for grid, pool in ((0, 0), (4, 0)):
+                    space.append(dict(c, form="batched", grid=grid, pool_cap=pool, rounds=rounds,
+                                      first_lists=depth))
     return space
 
 
@@ -114,7 +117,7 @@ def autotune(g: GpuIndex, queries, nprobe, k: int, rerank: int,
             log(f"tune {cand}: {ms:.3f} ms")
     best = min(trials, key=lambda r: r["ms"])
     best_opts = {k_: best[k_] for k_ in ("form", "coarse", "widen", "widen_add", "pool_cap",
-                                         "grid", "rounds") if k_ in best}
+                                         "grid", "rounds", "first_lists") if k_ in best}
     # The same schedule captured into a hipGraph and replayed (a side stream:
     # capture needs one), kept when faster.
     side = torch.cuda.Stream()

@@ -92,3 +92,23 @@ def test_cpu_baseline_times_the_oracle_at_the_given_probe_counts():
     assert row["kind"] == "oracle" and row["unit"] == "queries/s" and row["value"] > 0
     assert row["cores"] >= 1 and "queries" in row["sample"]
     assert job.path is None   # staged files removed
+
+
+def test_batched_scan_points_follow_the_first_pass_rule():
+    import bench
+    lens = np.array([100, 50, 300, 10, 10, 10, 10, 10, 500])
+    probes = np.array([[0, 1, 2, 3, 4, 5, 6, 7, 8],
+                       [8, 0, -1, -1, -1, -1, -1, -1, -1],
+                       [3, 4, 5, 6, 7, -1, -1, -1, -1]])
+    # one list at least, 120 points: row 0 takes lists 0, 1 (100 < 120, then
+    # 150); row 1 list 8; row 2 never reaches 120 points and takes them all
+    assert bench.batched_scan_points(probes, lens, 120, 1) == (300 + 50 + 500) + 100 + 0
+    # four lists at least: row 0 lists 0..3, row 1 both lists, row 2 all
+    assert bench.batched_scan_points(probes, lens, 120, 4) == (40 + 500) + 0 + 0
+    # a pool of 1000 points outweighs four lists in row 0 (stops after list 8)
+    assert bench.batched_scan_points(probes, lens, 1000, 4) == 0
+    # pool 10, one list: every row stops after its first list
+    assert bench.batched_scan_points(probes, lens, 10, 1) == 900 + 100 + 40
+    # 0 means the default, four lists
+    assert bench.batched_scan_points(probes, lens, 40, 0) == bench.batched_scan_points(
+        probes, lens, 40, 4)

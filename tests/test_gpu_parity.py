@@ -473,15 +473,17 @@ def test_batched_search_identical_to_plain(name):
                 exact_ids=(cfg.dist == "int255"))
 
 
-@pytest.mark.parametrize("rounds", [2, 3, 4])
+@pytest.mark.parametrize("rounds,depth", [(2, 0), (3, 0), (4, 0), (1, 1), (3, 1), (1, 2),
+                                          (2, 8)])
 @pytest.mark.parametrize("name", ["c1", "c3s", "c4s", "c5s", "c6u", "c2w"])
-def test_batched_rounds_candidates_bit_exact(name, rounds):
+def test_batched_rounds_candidates_bit_exact(name, rounds, depth):
     # Rounds over probe ranks [0,4), [4,16), [16,64), ... tighten the
-    # threshold between them; the pool is still the exact R smallest keys.
+    # threshold between them, and the first-list pass (at least `depth`
+    # lists) sets the first one; the pool is still the exact R smallest keys.
     import paper_2511_03298_amd as ivf
     cfg, X, Q, nprobe, index, g, res = case(name)
     P = probes_tensor(res, nprobe)
-    opts = ivf.make_opts(form="batched", rounds=rounds)
+    opts = ivf.make_opts(form="batched", rounds=rounds, first_lists=depth)
     keys = g.debug_candidates(Q, P, nprobe, cfg.R, opts=opts).cpu().numpy()
     a, ids = ivf.decode_keys(keys)
     assert np.array_equal(ids, res["cand_id"])
@@ -494,10 +496,11 @@ def test_batched_rounds_candidates_bit_exact(name, rounds):
 
 @pytest.mark.parametrize("rounds,spill_cap", [(1, 1024), (3, 1024), (3, 2048), (1, 0), (3, 0)])
 def test_batched_survivor_overflow_recomputes(rounds, spill_cap):
-    # The first probed list is the farthest one, so the phase-1 threshold is
-    # loose and the near lists' survivors overflow a 1024-key buffer: those
-    # queries go through the plain recompute. With the automatic capacity
-    # nothing overflows and the merge takes its large-LDS launch.
+    # The first probed list is the farthest one and the first-list pass stops
+    # after it (one list), so the phase-1 threshold is loose and the near
+    # lists' survivors overflow a 1024-key buffer: those queries go through
+    # the plain recompute. With the automatic capacity nothing overflows and
+    # the merge takes its large-LDS launch.
     import paper_2511_03298_amd as ivf
     cfg, X, Q, nprobe, index, g, _ = case("c2s")
     nq = 6
@@ -513,7 +516,8 @@ def test_batched_survivor_overflow_recomputes(rounds, spill_cap):
     kp = g.debug_candidates(Q[:nq], P, npb, cfg.R).cpu().numpy()
     kb = g.debug_candidates(Q[:nq], P, npb, cfg.R,
                             opts=ivf.make_opts(form="batched", rounds=rounds,
-                                               spill_cap=spill_cap)).cpu().numpy()
+                                               spill_cap=spill_cap,
+                                               first_lists=1)).cpu().numpy()
     assert np.array_equal(kp, kb)
     res = oracle.search(index, X, Q[:nq], 1, cfg.k, cfg.R)  # shape only
     # Pool against the oracle on the same visiting order.
@@ -831,9 +835,10 @@ def test_spilled_search(name):
 
 
 def test_spilled_survivor_overflow_recomputes():
-    # Far list first: a loose first threshold, survivors overflow a 1024-key
-    # buffer and those queries are recomputed; pools equal the plain form's
-    # and the oracle's best-copy pool over the same lists.
+    # Far list first and a first-list pass of one list: a loose first
+    # threshold, survivors overflow a 1024-key buffer and those queries are
+    # recomputed; pools equal the plain form's and the oracle's best-copy
+    # pool over the same lists.
     import paper_2511_03298_amd as ivf
     cfg, X, Q, nprobe, sp, g, _ = _spilled_case("c2x")
     nq = 6
@@ -848,7 +853,8 @@ def test_spilled_survivor_overflow_recomputes():
     for rounds in (1, 3):
         kb = g.debug_candidates(Q[:nq], P, npb, cfg.R,
                                 opts=ivf.make_opts(form="batched", rounds=rounds,
-                                                   spill_cap=1024)).cpu().numpy()
+                                                   spill_cap=1024,
+                                                   first_lists=1)).cpu().numpy()
         assert np.array_equal(kp, kb), rounds
     off, lid = sp["list_offsets"], sp["list_ids"]
     for qi, r in enumerate(rows):
