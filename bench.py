@@ -41,20 +41,26 @@ HBM_PEAK_GBS = 8000.0
 LDS_BYTES_PER_CLK = 256
 LOOKUP_PEAK_T = 256 * 2.4e9 * LDS_BYTES_PER_CLK / 2 / 1e12
 
-# HBM traffic of the dominant scan kernel, from rocprofv3 --pmc FETCH_SIZE
-# and --pmc WRITE_SIZE runs (KiB per dispatch, the mean of the timed
-# launches, scaled by the factors a 1 GiB device copy gave: 2.0 and 1.0).
-# Valid only while the kernel source is the one measured (sha256 of the
-# listed files).
+# HBM-side traffic of the scan stage's kernel launches of one step, from
+# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per step: the mean
+# of the timed launches, summed over a step's launches), scaled by the factors
+# a 1 GiB device copy gave (2.0 and 1.0). Keyed by workload, operating point
+# and form, and for the batched form by its first-list count and rounds (they
+# decide which lists the kernel scans); valid only while the kernel sources
+# are the ones measured (sha256 of the listed files).
 TRAFFIC = {
-    ("c2", "batched"): dict(files=("batched.hip", "common.hpp"), sha="e4f7fb9f060a9dcf",
-                            fetch_kib=109117.7, write_kib=1726.8),
-    ("c2", "plain"): dict(files=("scan.hip", "common.hpp"), sha="245a781fa59d5e7d",
-                          fetch_kib=5191013.5, write_kib=15625.0),
-    ("c5", "plain"): dict(files=("scan.hip", "common.hpp"), sha="245a781fa59d5e7d",
-                          fetch_kib=48323178.0, write_kib=8192.0),
-    ("c5", "batched"): dict(files=("batched.hip", "common.hpp"), sha="e4f7fb9f060a9dcf",
-                            fetch_kib=3834007.3, write_kib=3189.3),
+    ("c5", "static x0.5", "plain"): dict(
+        files=("scan.hip", "common.hpp"), sha="d1f5028da08566ba",
+        fetch_kib=39110933.7, write_kib=8192.0),
+    ("c5", "static x0.5", "batched", 4, 1): dict(
+        files=("batched.hip", "scan.hip", "common.hpp"), sha="9cbd1ea2611153be",
+        fetch_kib=4233195.2, write_kib=60386.9),
+    ("c2", "static nprobe 24", "plain"): dict(
+        files=("scan.hip", "common.hpp"), sha="d1f5028da08566ba",
+        fetch_kib=3607212.1, write_kib=15625.0),
+    ("c2", "static nprobe 24", "batched", 2, 1): dict(
+        files=("batched.hip", "scan.hip", "common.hpp"), sha="9cbd1ea2611153be",
+        fetch_kib=149030.0, write_kib=40476.0),
 }
 
 
@@ -66,11 +72,21 @@ def source_sha(files):
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(config, form):
-    rec = TRAFFIC.get((config, form))
+def traffic_key(config, setting, form, opts):
+    """(workload, probe setting of the operating point, form[, first lists,
+    rounds]): the launches of one step that a record describes."""
+    if form == "plain":
+        return (config, setting, "plain")
+    return (config, setting, "batched", opts.get("first_lists") or 4,
+            max(1, opts.get("rounds") or 1))
+
+
+def recorded_traffic(config, setting, form, opts):
+    rec = TRAFFIC.get(traffic_key(config, setting, form, opts))
     if not rec or source_sha(rec["files"]) != rec["sha"]:
         return None
     return int(rec["fetch_kib"] * 1024 * 2.0 + rec["write_kib"] * 1024 * 1.0)
+
 
 WORKLOAD_TEXT = {
     "c1": "10k x 32 Gaussian mixture, L2, 64 lists, PQ 16x4-bit, nprobe 8, k 10, rerank 100",
@@ -307,7 +323,7 @@ def scan_kernel_name(form, cfg):
 CACHE_RESIDENT = {"c1", "c2", "c3", "c6"}
 
 
-def roofline(config, cfg, r, code_bytes):
+def roofline(config, setting, cfg, r, code_bytes):
     """Roofline of the dominant kernel (the scan stage's kernel) of form r.
 
     achieved = algorithmic work of the launches of one step / their summed
@@ -318,7 +334,7 @@ def roofline(config, cfg, r, code_bytes):
     point, from HBM when the code array exceeds the caches."""
     streaming = r["form"] == "plain" and config not in CACHE_RESIDENT
     alg_bytes = r["scan_points"] * code_bytes
-    traffic = recorded_traffic(config, r["form"])
+    traffic = recorded_traffic(config, setting, r["form"], r["opts"])
     out = {"kernel": scan_kernel_name(r["form"], cfg), "algorithmic_bytes_per_step": alg_bytes,
            "traffic": traffic,
            "traffic_source": (None if traffic is None else
@@ -764,10 +780,10 @@ def main():
         "forms": [{k_: (round(v, 4) if isinstance(v, float) and k_ != "max_rel_dist_err" else v)
                    for k_, v in r.items() if k_ not in ("stage_ms", "opts")} |
                   {"stage_ms": {s: round(x, 4) for s, x in r["stage_ms"].items()},
-                   "roofline": roofline(args.config, cfg, r, code_bytes),
+                   "roofline": roofline(args.config, op_label, cfg, r, code_bytes),
                    "coarse_mfma": coarse_mfma(cfg, r)}
                   for r in results],
-        "roofline": roofline(args.config, cfg, best, code_bytes),
+        "roofline": roofline(args.config, op_label, cfg, best, code_bytes),
         "coarse_mfma": coarse_mfma(cfg, best),
         "cpu_baseline": cpu,
     }

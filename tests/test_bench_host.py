@@ -49,12 +49,20 @@ def test_coarse_mfma_roofline_is_the_smaller_bound():
 
 def test_traffic_only_while_sources_match():
     import bench
-    for (config, form), rec in bench.TRAFFIC.items():
-        t = bench.recorded_traffic(config, form)
+    for key, rec in bench.TRAFFIC.items():
+        config, setting, form = key[:3]
+        opts = {} if form == "plain" else {"first_lists": key[3], "rounds": key[4]}
+        assert bench.traffic_key(config, setting, form, opts) == key
+        t = bench.recorded_traffic(config, setting, form, opts)
         if bench.source_sha(rec["files"]) == rec["sha"]:
             assert t == int(rec["fetch_kib"] * 1024 * 2.0 + rec["write_kib"] * 1024)
         else:
             assert t is None
+    # Defaults: four first lists, one round; another schedule has no record.
+    assert bench.traffic_key("c5", "static x0.5", "batched", {"first_lists": 0, "rounds": 0}) == \
+        ("c5", "static x0.5", "batched", 4, 1)
+    assert bench.recorded_traffic("c5", "static x0.5", "batched",
+                                  {"first_lists": 8, "rounds": 5}) is None
 
 
 def test_probe_ladder_settings():
