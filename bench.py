@@ -194,8 +194,9 @@ def _cpu_server(conn, X, Q, k, R, per_worker):
         t0 = time.perf_counter()
         oracle.search(index, X, Q[:2], nprobe[:2], k, R)
         per_query = (time.perf_counter() - t0) / 2
-    # At least 8 queries per worker; 32 unless that would take over ~30 s.
-    per_worker = max(8, min(per_worker, int(30.0 / max(per_query, 1e-6))))
+    # About 15 s of oracle work per process (at least 8 queries, at most
+    # per_worker), so the sample stays bounded whatever the per-query cost.
+    per_worker = max(8, min(per_worker, int(15.0 / max(per_query, 1e-6))))
     log(f"oracle: {per_query:.3f} s per query; {workers} processes x {per_worker} queries")
     _CPU.update(index=index, X=X, Q=Q, nprobe=nprobe, k=k, R=R)
     spans = [(w * per_worker, (w + 1) * per_worker) for w in range(workers)]
@@ -218,7 +219,7 @@ class CpuBaseline:
     writes the trained index for it, run(nprobe) hands over the per-query
     probe counts of the measured operating point and waits for the result."""
 
-    def __init__(self, X, Q, k, R, per_worker=32):
+    def __init__(self, X, Q, k, R, per_worker=2048):
         import multiprocessing as mp
         ctx = mp.get_context("fork")
         self.conn, child = ctx.Pipe()

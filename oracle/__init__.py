@@ -6,11 +6,13 @@ never calls it; it shares no code with the GPU path.
 
 Parity status: every function is pinned by a CPU test against the paper's
 definitions (brute-force k-NN, the reconstructed-vector identity of Eq. 1,
-lossless constructed cases, full sorts). The u8 LUT quantisation *scheme*
+lossless constructed cases, full sorts). The u8 LUT quantisation scheme
 (per-subspace offset, one shared scale per (query, list), round half to
-even) is a reading of a passage that only says the LUT entries are 8-bit
-unsigned integers; it is pinned by invariants and a lossless grid case, but
-no value printed by the paper pins it: parity unpinned for the scheme itself.
+even, a pairwise sum of the offsets) is a reading of a passage that only
+says the LUT entries are 8-bit unsigned integers, and the paper prints no
+quantised values; the function is pinned to that reading by its error
+bound, its invariants, lossless grid cases and two examples worked by hand
+(one where the pairwise and the left-to-right sums of the offsets differ).
 The adaptive nprobe/reorder stand-in (hardness, eq2) follows Eq. 2 with a
 closed-form p in place of the paper's trained model; Eq. 2 itself is pinned
 by hand-worked values and its limits, the choice of p is a reading.

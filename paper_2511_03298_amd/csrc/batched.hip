@@ -501,10 +501,12 @@ batched_scan_kernel(
     // Each wave's first code block is requested now; its latency overlaps
     // the table set-up below.
     uint32_t nx[W];
+    uint32_t nid = 0;
     if (wave < nblk) {
       const uint32_t* cw = t.codes + (size_t)(blk0 + wave) * W * BLOCK_PTS + ln;
 #pragma unroll
       for (int w = 0; w < W; ++w) nx[w] = cw[w * BLOCK_PTS];
+      nid = (uint32_t)t.slot_ids[(size_t)(blk0 + wave) * BLOCK_PTS + ln];
     }
     if constexpr (per_query) {
       // Copy the queries' tables into the interleaved layout. Lane (c, pp)
@@ -583,7 +585,8 @@ batched_scan_kernel(
     // Code words stay in registers: the current block in `cur`, the wave's
     // next block in flight into `nx` (when there is none the current block is
     // requested again and not used; a branch would make the compiler wait
-    // for the loads before the lookups).
+    // for the loads before the lookups). The block's slot ids travel with
+    // its words, so a block with candidates does not wait for them.
     const unsigned char* lutb = reinterpret_cast<const unsigned char*>(sh.lut16);
 #pragma unroll 1
     for (int bi = wave; bi < nblk; bi += IVF_NWAVES) {
@@ -591,11 +594,13 @@ batched_scan_kernel(
       uint32_t cur[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) cur[w] = nx[w];
+      const uint32_t cur_id = nid;
       {
         const int nb = bi + IVF_NWAVES < nblk ? blk + IVF_NWAVES : blk;
         const uint32_t* cw = t.codes + (size_t)nb * W * BLOCK_PTS + ln;
 #pragma unroll
         for (int w = 0; w < W; ++w) nx[w] = cw[w * BLOCK_PTS];
+        nid = (uint32_t)t.slot_ids[(size_t)nb * BLOCK_PTS + ln];
       }
       // acc[k] holds the sums of queries 2k (low half) and 2k+1 (high half).
       // Plain 32-bit adds are exact on the packed pairs: a half never exceeds
@@ -651,7 +656,7 @@ batched_scan_kernel(
       }
       if (!valid) cand = 0;
       // Rare path: exact keys for the candidate (point, query) pairs.
-      const uint32_t id = cand ? (uint32_t)t.slot_ids[(size_t)blk * BLOCK_PTS + ln] : 0u;
+      const uint32_t id = cand ? cur_id : 0u;
       // Which candidates pass on the full key; lane g collects query g's count.
       uint32_t passbits = 0, count = 0;
 #pragma unroll
