@@ -51,16 +51,16 @@ LOOKUP_PEAK_T = 256 * 2.4e9 * LDS_BYTES_PER_CLK / 2 / 1e12
 TRAFFIC = {
     ("c5", "static x0.5", "plain"): dict(
         files=("scan.hip", "common.hpp"), sha="d1f5028da08566ba",
-        fetch_kib=39110933.7, write_kib=8192.0),
+        fetch_kib=39111448.6, write_kib=8192.0),
     ("c5", "static x0.5", "batched", 4, 1): dict(
-        files=("batched.hip", "scan.hip", "common.hpp"), sha="9cbd1ea2611153be",
-        fetch_kib=4233195.2, write_kib=60386.9),
+        files=("batched.hip", "scan.hip", "common.hpp"), sha="23cc14ad80291eec",
+        fetch_kib=4369017.7, write_kib=60422.2),
     ("c2", "static nprobe 24", "plain"): dict(
         files=("scan.hip", "common.hpp"), sha="d1f5028da08566ba",
-        fetch_kib=3607212.1, write_kib=15625.0),
+        fetch_kib=3610304.8, write_kib=15625.0),
     ("c2", "static nprobe 24", "batched", 2, 1): dict(
-        files=("batched.hip", "scan.hip", "common.hpp"), sha="9cbd1ea2611153be",
-        fetch_kib=149030.0, write_kib=40476.0),
+        files=("batched.hip", "scan.hip", "common.hpp"), sha="23cc14ad80291eec",
+        fetch_kib=150523.7, write_kib=40461.5),
 }
 
 
