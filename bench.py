@@ -49,16 +49,16 @@ LOOKUP_PEAK_T = 256 * 2.4e9 * LDS_BYTES_PER_CLK / 2 / 1e12
 # decide which lists the kernel scans); valid only while the kernel sources
 # are the ones measured (sha256 of the listed files).
 TRAFFIC = {
-    ("c5", "static x0.5", "plain"): dict(
+    ("c5", "static x0.5", "plain", 0): dict(
         files=("scan.hip", "common.hpp"), sha="d1f5028da08566ba",
         fetch_kib=39111448.6, write_kib=8192.0),
-    ("c5", "static x0.5", "batched", 4, 1): dict(
+    ("c5", "static x0.5", "batched", 0, 4, 1, 0): dict(
         files=("batched.hip", "scan.hip", "common.hpp"), sha="23cc14ad80291eec",
         fetch_kib=4369017.7, write_kib=60422.2),
-    ("c2", "static nprobe 24", "plain"): dict(
+    ("c2", "static nprobe 24", "plain", 0): dict(
         files=("scan.hip", "common.hpp"), sha="d1f5028da08566ba",
         fetch_kib=3610304.8, write_kib=15625.0),
-    ("c2", "static nprobe 24", "batched", 2, 1): dict(
+    ("c2", "static nprobe 24", "batched", 0, 2, 1, 0): dict(
         files=("batched.hip", "scan.hip", "common.hpp"), sha="23cc14ad80291eec",
         fetch_kib=150523.7, write_kib=40461.5),
 }
@@ -73,12 +73,14 @@ def source_sha(files):
 
 
 def traffic_key(config, setting, form, opts):
-    """(workload, probe setting of the operating point, form[, first lists,
-    rounds]): the launches of one step that a record describes."""
+    """(workload, probe setting of the operating point, form, query order[,
+    first lists, rounds, list order]): the launches of one step that a record
+    describes."""
+    qo = opts.get("query_order") or 0
     if form == "plain":
-        return (config, setting, "plain")
-    return (config, setting, "batched", opts.get("first_lists") or 4,
-            max(1, opts.get("rounds") or 1))
+        return (config, setting, "plain", qo)
+    return (config, setting, "batched", qo, opts.get("first_lists") or 4,
+            max(1, opts.get("rounds") or 1), opts.get("list_order") or 0)
 
 
 def recorded_traffic(config, setting, form, opts):
@@ -679,7 +681,8 @@ def main():
     for spec in args.forms.split(","):
         parts = spec.split(":")
         form, coarse = (parts + ["exact"])[:2]
-        extra = {"r": "rounds", "w": "widen", "a": "widen_add", "g": "grid", "f": "first_lists"}
+        extra = {"r": "rounds", "w": "widen", "a": "widen_add", "g": "grid", "f": "first_lists",
+                 "q": "query_order", "l": "list_order"}
         kw = {extra[p_[0]]: int(p_[1:]) for p_ in parts[2:] if p_ and p_[0] in extra}
         runs.append(("fixed", ivf.make_opts(coarse=coarse, form=form, **kw)))
     if not args.no_tune:

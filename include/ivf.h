@@ -183,6 +183,15 @@ typedef struct {
                           rerank*copies points. 1..64, 0 = auto (4). More
                           lists: a tighter first threshold (fewer survivors to
                           merge) for more per-query scanning.                 */
+  int32_t query_order; /* launch order of the one-workgroup-per-query scans
+                          (plain form, first-list pass): 0 = longest scan
+                          first (queries bucketed by the points they will
+                          visit), 1 = query index order. Results are the same;
+                          longest-first ends the grid evenly when scan lengths
+                          vary across queries.                                 */
+  int32_t list_order;  /* BATCHED: order of the work items on the queue: 0 =
+                          longest list first, 1 = list index order. Results
+                          are the same.                                        */
 } ivf_search_opts;
 
 /* Entry points without a passage of the paper behind them are marked

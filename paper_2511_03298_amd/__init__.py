@@ -62,7 +62,8 @@ class SearchOpts(ctypes.Structure):
                 ("adaptive", ctypes.c_int32), ("nprobe_init", ctypes.c_int32),
                 ("nprobe_min", ctypes.c_int32), ("reorder_min", ctypes.c_int32),
                 ("p0", ctypes.c_float), ("p1", ctypes.c_float),
-                ("widen_add", ctypes.c_int32), ("first_lists", ctypes.c_int32)]
+                ("widen_add", ctypes.c_int32), ("first_lists", ctypes.c_int32),
+                ("query_order", ctypes.c_int32), ("list_order", ctypes.c_int32)]
 
 
 class TableLayout(ctypes.Structure):
@@ -138,7 +139,8 @@ def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
               use_graph: bool = False, pool_cap: int = 0, grid: int = 0,
               rounds: int = 0, spill_cap: int = 0,
               adaptive: Optional[dict] = None, widen_add: int = 0,
-              first_lists: int = 0) -> SearchOpts:
+              first_lists: int = 0, query_order: int = 0,
+              list_order: int = 0) -> SearchOpts:
     """adaptive: dict(nprobe_init, nprobe_min, reorder_min, p0, p1) turns on
     the per-query probe count and re-rank size of Eq. 2 (nprobe[q] and
     rerank are the maxima)."""
@@ -149,6 +151,7 @@ def make_opts(coarse: str = "exact", widen: int = 2, form: str = "plain",
     o.rounds, o.spill_cap = int(rounds), int(spill_cap)
     o.widen_add = int(widen_add)
     o.first_lists = int(first_lists)
+    o.query_order, o.list_order = int(query_order), int(list_order)
     if adaptive:
         o.adaptive = 1
         o.nprobe_init = int(adaptive["nprobe_init"])
@@ -164,7 +167,8 @@ def opts_dict(o: SearchOpts) -> dict:
     d = dict(coarse=inv_c[o.coarse], widen=o.widen, form=inv_f[o.form],
              use_graph=bool(o.use_graph), pool_cap=o.pool_cap, grid=o.grid,
              rounds=o.rounds, spill_cap=o.spill_cap, widen_add=o.widen_add,
-             first_lists=o.first_lists)
+             first_lists=o.first_lists, query_order=o.query_order,
+             list_order=o.list_order)
     if o.adaptive:
         d["adaptive"] = dict(nprobe_init=o.nprobe_init, nprobe_min=o.nprobe_min,
                              reorder_min=o.reorder_min, p0=o.p0, p1=o.p1)

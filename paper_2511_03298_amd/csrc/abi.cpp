@@ -2,6 +2,7 @@
 // workspace layout, and the order in which the kernels are enqueued.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -162,6 +163,9 @@ std::string plan_tables(const ivf_index_desc* d, ivf_table_layout* lay, int32_t*
   lay->probe_fp8 = take((size_t)lay->L_padded * lay->d_padded);
   lay->probe_fp8_scale = take((size_t)lay->L_padded * 4);
   lay->dims = take(d->dims ? (size_t)d->d * 4 : 0);
+  // List indices by length, longest first: the batched scan serves the work
+  // items of long lists first.
+  take((size_t)d->L * 4);
   // Build-time scratch: a spilled index's per-point numbering array and flag
   // (else just the flag word), then the copy of the CSR offsets (int64).
   take(copies > 1 ? (size_t)(d->n + 64) * 4 : 64);
@@ -180,6 +184,11 @@ size_t list_off_section(const ivf_index_desc* d, const ivf_table_layout& lay) {
 size_t copies_section(const ivf_index_desc* d, const ivf_table_layout& lay) {
   const bool spilled = d->copies > 1;
   return list_off_section(d, lay) - align_up(spilled ? (size_t)(d->n + 64) * 4 : 64);
+}
+
+// The longest-first list order: int32 [L], just before the numbering scratch.
+size_t list_order_section(const ivf_index_desc* d, const ivf_table_layout& lay) {
+  return copies_section(d, lay) - align_up((size_t)d->L * 4);
 }
 
 ivf_status check_device() {
@@ -212,6 +221,10 @@ ivf_status check_opts(const ivf_search_opts& o) {
     return fail(IVF_ERR_INVALID_ARG, "opts.widen_add must be in [0, 16384]");
   if (o.first_lists < 0 || o.first_lists > 64)
     return fail(IVF_ERR_INVALID_ARG, "opts.first_lists must be in [0, 64]");
+  if (o.query_order != 0 && o.query_order != 1)
+    return fail(IVF_ERR_INVALID_ARG, "opts.query_order must be 0 or 1");
+  if (o.list_order != 0 && o.list_order != 1)
+    return fail(IVF_ERR_INVALID_ARG, "opts.list_order must be 0 or 1");
   if (o.form != IVF_FORM_PLAIN && o.form != IVF_FORM_BATCHED)
     return fail(IVF_ERR_INVALID_ARG, "opts.form out of range");
   if (o.use_graph != 0 && o.use_graph != 1)
@@ -272,6 +285,9 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   };
   const size_t nqs = (size_t)(nq > 0 ? nq : 1);
   w.err = (int32_t*)take(16);
+  w.order = (int32_t*)take(nqs * 4);
+  w.order_bucket = (int32_t*)take(nqs * 4);
+  w.order_hist = (int32_t*)take((size_t)2 * ORDER_BUCKETS * 4);
   w.scores = (float*)take(nqs * t.L * 4);
   w.probes = (int32_t*)take(nqs * max_nprobe * 4);
   w.nprobe_eff = (int32_t*)take(nqs * 4);
@@ -288,6 +304,8 @@ Workspace plan_workspace(const Tables& t, int32_t nq, int32_t max_nprobe, int32_
   w.pool_cap = o.pool_cap;
   w.grid = o.grid;
   w.first_lists = o.first_lists > 0 ? o.first_lists : 4;
+  w.query_order = o.query_order;
+  w.list_order = o.list_order;
   if (o.form == IVF_FORM_BATCHED) {
     w.spill_cap = o.spill_cap > 0 ? o.spill_cap : batched_spill_cap(pool, nq);
     w.p1 = (int32_t*)take(nqs * 4);
@@ -322,6 +340,8 @@ void ivf_default_opts(ivf_search_opts* o) {
   o->widen = 2;
   o->widen_add = 0;
   o->first_lists = 0;
+  o->query_order = 0;
+  o->list_order = 0;
   o->form = IVF_FORM_PLAIN;
   o->use_graph = 0;
   o->pool_cap = 0;
@@ -403,6 +423,14 @@ ivf_status ivf_build_tables(const ivf_index_desc* desc, void* table_mem, size_t 
     llen[l] = (int32_t)len;
     boff[l + 1] = boff[l] + (int32_t)((len + BLOCK_PTS - 1) / BLOCK_PTS);
   }
+  // Lists by length, longest first (stable: ties keep index order).
+  std::vector<int32_t> lorder(desc->L);
+  for (int l = 0; l < desc->L; ++l) lorder[l] = l;
+  std::stable_sort(lorder.begin(), lorder.end(),
+                   [&](int32_t a, int32_t b) { return llen[a] > llen[b]; });
+  t.list_order = (const int32_t*)(base + list_order_section(desc, lay));
+  IVF_HIP(hipMemcpyAsync((void*)t.list_order, lorder.data(), lorder.size() * 4,
+                         hipMemcpyHostToDevice, s));
   int64_t* list_off_dev = (int64_t*)(base + list_off_section(desc, lay));
   const size_t cb_bytes = (size_t)desc->m * KSUB * t.dsub * 4;
   const size_t cb_pad_bytes = (size_t)t.m_pad * KSUB * t.dsub * 4;
@@ -673,6 +701,7 @@ ivf_status ivf_search(const ivf_index* idx, const float* queries, int32_t nq,
     std::vector<uint64_t> key = {(uint64_t)nq, (uint64_t)max_nprobe, (uint64_t)k,
                                  (uint64_t)rerank, (uint64_t)o.coarse, (uint64_t)o.widen,
                                  (uint64_t)o.widen_add, (uint64_t)o.first_lists,
+                                 (uint64_t)o.query_order, (uint64_t)o.list_order,
                                  (uint64_t)o.form, (uint64_t)o.pool_cap, (uint64_t)o.grid,
                                  (uint64_t)o.rounds, (uint64_t)o.spill_cap,
                                  (uint64_t)o.adaptive, (uint64_t)o.nprobe_init,

@@ -8,10 +8,10 @@
 //            (no key above thr can enter the final pool);
 //   rounds   the remaining (query, list) pairs, restricted to a range of
 //            probe ranks per round, are grouped by list into work items of
-//            up to 16 queries; persistent workgroups pull items from an
-//            atomic counter, build the 16 queries' tables, stream the list's
-//            code blocks once, and append every key <= thr of its query to a
-//            per-query survivor buffer;
+//            up to 16 queries (the longest lists' items first); persistent
+//            workgroups pull items from an atomic counter, build the
+//            queries' tables, stream the list's code blocks once, and append
+//            every key <= thr of its query to a per-query survivor buffer;
 //   merge    after each round, per query, the R smallest keys of the pool and
 //            its survivors become the new pool and its R-th key the new thr,
 //            so later rounds keep fewer survivors. A query whose buffer
@@ -86,9 +86,13 @@ __global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t ma
     if (hist[l]) atomicAdd(&cnt[l], hist[l]);
 }
 
-// Exclusive scans of per-list pair counts and item counts (one workgroup);
-// the items of one list are consecutive, lists in ascending order.
+// Exclusive scans of per-list pair counts and item counts (one workgroup)
+// over the lists in `order` (the index's lists longest first, so that the
+// persistent workgroups take the long items first and the grid ends on short
+// ones), or in index order when it is null; the items of one list are
+// consecutive.
 __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, int32_t BG,
+                                                         const int32_t* __restrict__ order,
                                                          const int32_t* __restrict__ cnt,
                                                          int32_t* __restrict__ list_start,
                                                          int32_t* __restrict__ item_start,
@@ -99,7 +103,8 @@ __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, int32_t BG,
   const int per = (L + 1023) / 1024;
   const int b = tid * per, e = min(L, b + per);
   int32_t ps = 0, is = 0;
-  for (int l = b; l < e; ++l) {
+  for (int i = b; i < e; ++i) {
+    const int l = order ? order[i] : i;
     ps += cnt[l];
     is += (cnt[l] + BG - 1) / BG;
   }
@@ -114,7 +119,8 @@ __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, int32_t BG,
     __syncthreads();
   }
   int32_t pacc = sp[tid] - ps, iacc = si[tid] - is;
-  for (int l = b; l < e; ++l) {
+  for (int i = b; i < e; ++i) {
+    const int l = order ? order[i] : i;
     list_start[l] = pacc;
     item_start[l] = iacc;
     cursor[l] = 0;
@@ -809,7 +815,9 @@ hipError_t launch_batched_pairs(const Tables& t, int32_t nq, int32_t max_nprobe,
   hipLaunchKernelGGL(pairs_count_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
                      w.probes, sel, w.list_cnt);
   hipLaunchKernelGGL(pairs_scan_kernel, dim3(1), dim3(1024), 0, s, t.L, item_queries_rt(t.words),
-                     w.list_cnt, w.list_start, w.item_start, w.list_cursor, w.item_list);
+                     w.list_order == 0 ? t.list_order : nullptr, w.list_cnt, w.list_start,
+                     w.item_start, w.list_cursor,
+                     w.item_list);
   hipLaunchKernelGGL(pairs_fill_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
                      w.probes, sel, w.list_start, w.list_cursor, w.pairs);
   return hipGetLastError();

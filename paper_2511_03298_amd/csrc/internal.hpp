@@ -18,6 +18,7 @@ constexpr int MAX_L = 1 << 20;
 constexpr int TILE_L = 64;        // low-precision centroid tables: L padded to this
 constexpr int TILE_D = 64;        // ... and d padded to this
 constexpr size_t ALIGN = 256;
+constexpr int ORDER_BUCKETS = 1024;  // scan-length buckets of the longest-first query order
 
 inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
 
@@ -38,6 +39,7 @@ struct Tables {
   const int32_t* slot_ids;      // [blocks][64]
   const int32_t* block_off;     // [L+1]
   const int32_t* list_len;      // [L]
+  const int32_t* list_order;    // [L] list indices by length, longest first (ties by index)
   const float* cm;              // [L][d]
   const float* cp;              // [L][d]
   const float* codebooks;       // [m_pad][16][dsub]
@@ -74,6 +76,9 @@ struct Workspace {
   uint64_t* cand;       // [nq][rerank * copies] scan pool (keys of list entries)
   uint64_t* cand_u;     // [nq][rerank] one key per point (spilled index only)
   int32_t* err;         // [4] device error word
+  int32_t* order;       // [nq] launch order of the per-query scans, longest first
+  int32_t* order_bucket;  // [nq] scan-length bucket of each query
+  int32_t* order_hist;  // [2 * ORDER_BUCKETS] bucket counts, then bucket cursors
   // batched form
   int32_t* p1;          // [nq] first probe slot of phase 2
   uint64_t* thr;        // [nq] phase-1 threshold keys
@@ -97,6 +102,8 @@ struct Workspace {
   int32_t pool_cap;  // plain scan candidate buffer beyond R (0 = auto)
   int32_t grid;      // batched workgroups per CU (0 = auto)
   int32_t first_lists;  // batched first-list pass: lists scanned at least (>= 1)
+  int32_t query_order;  // 0: per-query scans longest first; 1: query index order
+  int32_t list_order;   // 0: batched work items of the longest lists first; 1: list order
 };
 
 int32_t batched_spill_cap(int32_t rerank, int32_t nq);

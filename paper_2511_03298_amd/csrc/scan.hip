@@ -130,10 +130,13 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
                                                          int32_t first_lists,
                                                          uint8_t* __restrict__ qlut_out,
                                                          float* __restrict__ qlo_out,
-                                                         float* __restrict__ qdelta_out) {
+                                                         float* __restrict__ qdelta_out,
+                                                         const int32_t* __restrict__ order) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ ScanShared<W> sh;
-  const int q = blockIdx.x;
+  // `order`: the launch order of the queries (longest scan first), or the
+  // identity when null.
+  const int q = order ? order[blockIdx.x] : blockIdx.x;
   const int tid = threadIdx.x;
   const int wave = tid / IVF_WAVE;
   uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);            // [R + cap]
@@ -299,6 +302,97 @@ hipError_t launch_sort_rows(uint64_t* cand, int32_t nq, int32_t R, hipStream_t s
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Longest-first launch order of the per-query scans. A query's scan length
+// is the number of list entries it will visit (for the batched form's
+// first-list pass, up to its stop rule); queries are bucketed by it on a log
+// scale, 32 buckets per octave, and a counting sort over the buckets gives
+// the workgroup order. Long scans then start first and the grid ends with
+// short ones. Only the schedule changes: each query's pool is the same.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int order_bucket(uint64_t len) {
+  const uint32_t w = len > 0xffffffffull ? 0xffffffffu : (uint32_t)len;
+  if (w == 0) return ORDER_BUCKETS - 1;
+  const int e = 31 - __clz((int)w);
+  const uint32_t f = e >= 5 ? (w >> (e - 5)) & 31u : (w << (5 - e)) & 31u;
+  return ORDER_BUCKETS - 1 - (e * 32 + (int)f);  // e * 32 + f <= 1023
+}
+
+// One thread per query: the points of the lists its scan will visit (for
+// the first-list pass, up to its stop rule).
+__global__ void __launch_bounds__(256) order_count_kernel(Tables t, int32_t nq, int32_t max_nprobe,
+                                                          const int32_t* __restrict__ probes,
+                                                          const int32_t* __restrict__ nprobe_eff,
+                                                          int32_t first_lists, int32_t R,
+                                                          int32_t* __restrict__ bucket,
+                                                          int32_t* __restrict__ hist) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const int np = nprobe_eff[q];
+  const int32_t* qprobes = probes + (size_t)q * max_nprobe;
+  uint64_t seen = 0;
+  for (int p = 0; p < np; ++p) {
+    if (first_lists > 0 && seen >= (uint64_t)R && p >= first_lists) break;
+    seen += (uint32_t)t.list_len[qprobes[p]];
+  }
+  const int b = order_bucket(seen);
+  bucket[q] = b;
+  atomicAdd(&hist[b], 1);
+}
+
+// Each workgroup scans the bucket counts in LDS, then places its queries:
+// position = start of the bucket + a global per-bucket cursor.
+__global__ void __launch_bounds__(256) order_place_kernel(int32_t nq,
+                                                          const int32_t* __restrict__ bucket,
+                                                          const int32_t* __restrict__ hist,
+                                                          int32_t* __restrict__ cursor,
+                                                          int32_t* __restrict__ order) {
+  constexpr int PER = ORDER_BUCKETS / 256;
+  __shared__ int32_t part[256];
+  __shared__ int32_t start[ORDER_BUCKETS];
+  const int tid = threadIdx.x;
+  int32_t c[PER], sum = 0;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    c[i] = hist[tid * PER + i];
+    sum += c[i];
+  }
+  part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int32_t a = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += a;
+    __syncthreads();
+  }
+  int32_t acc = part[tid] - sum;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    start[tid * PER + i] = acc;
+    acc += c[i];
+  }
+  __syncthreads();
+  const int q = blockIdx.x * blockDim.x + tid;
+  if (q < nq) {
+    const int b = bucket[q];
+    order[start[b] + atomicAdd(&cursor[b], 1)] = q;
+  }
+}
+
+static hipError_t launch_scan_order(const Tables& t, int32_t nq, int32_t max_nprobe,
+                                    int32_t first_lists, int32_t R, const Workspace& w,
+                                    hipStream_t s) {
+  hipError_t e = launch_fill_u32((uint32_t*)w.order_hist, 0u, (size_t)2 * ORDER_BUCKETS, s);
+  if (e != hipSuccess) return e;
+  const unsigned g = (unsigned)((nq + 255) / 256);
+  hipLaunchKernelGGL(order_count_kernel, dim3(g), dim3(256), 0, s, t, nq, max_nprobe, w.probes,
+                     w.nprobe_eff, first_lists, R, w.order_bucket, w.order_hist);
+  hipLaunchKernelGGL(order_place_kernel, dim3(g), dim3(256), 0, s, nq, w.order_bucket,
+                     w.order_hist, w.order_hist + ORDER_BUCKETS, w.order);
+  return hipGetLastError();
+}
+
 // Candidate-buffer slack beyond R (keys): the requested size (default 1024),
 // at least one round of one block per wave.
 inline int32_t scan_cap(int32_t R, int32_t requested) {
@@ -316,11 +410,17 @@ static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t n
   const int32_t cap = scan_cap(R, w.pool_cap);
   size_t lds = (size_t)(R + cap) * 8 + (size_t)t.m_pad * KSUB * 4 + (size_t)t.d * 4;
   const bool pub = p1_out && t.metric == IVF_METRIC_IP;
+  const int32_t first_lists = w.first_lists > 0 ? w.first_lists : 1;
+  // A recompute of flagged queries (`only`) keeps the identity order.
+  const bool ordered = !only && w.order && w.query_order == 0;
+  if (ordered) {
+    const hipError_t e = launch_scan_order(t, nq, max_nprobe, p1_out ? first_lists : 0, R, w, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(scan_plain_kernel<W>, dim3(nq), dim3(256), lds, s, t, Q, nq, max_nprobe, R,
                      cap, w.probes, w.nprobe_eff, w.bias, w.cand, p1_out, thr_out, only,
-                     w.first_lists > 0 ? w.first_lists : 1,
-                     pub ? w.qlut : nullptr, pub ? w.qlo_sum : nullptr,
-                     pub ? w.qdelta : nullptr);
+                     first_lists, pub ? w.qlut : nullptr, pub ? w.qlo_sum : nullptr,
+                     pub ? w.qdelta : nullptr, ordered ? w.order : nullptr);
   return hipGetLastError();
 }
 

@@ -11,6 +11,9 @@ device and keeps the fastest admissible one:
   * plain candidate-buffer size (pool_cap), batched persistent grid size,
     number of threshold-tightening rounds and lists of the first-list pass
     (first_lists);
+  * for the fastest of those, the launch orders: longest-first or index
+    order of the per-query scans (query_order) and of the batched work items
+    (list_order);
   * then the fastest schedule captured into a hipGraph and replayed on a
     side stream (use_graph), kept when faster.
 Results are cached in a JSON file keyed by the device architecture and the
@@ -118,6 +121,23 @@ def autotune(g: GpuIndex, queries, nprobe, k: int, rerank: int,
     best = min(trials, key=lambda r: r["ms"])
     best_opts = {k_: best[k_] for k_ in ("form", "coarse", "widen", "widen_add", "pool_cap",
                                          "grid", "rounds", "first_lists") if k_ in best}
+    # Launch orders of the fastest schedule (the defaults, longest first,
+    # were measured above).
+    lists = (0, 1) if best_opts["form"] == "batched" else (0,)
+    for qo in (0, 1):
+        for lo in lists:
+            if qo == 0 and lo == 0:
+                continue
+            cand = dict(best_opts, query_order=qo, list_order=lo)
+            ms = _time(g, Qd, npd, k, rerank, max_nprobe, make_opts(**cand), ids, dist, reps)
+            trials.append(dict(cand, ms=ms, probe_agreement=best["probe_agreement"]))
+            if log:
+                log(f"tune {cand}: {ms:.3f} ms")
+            if ms < best["ms"]:
+                best = trials[-1]
+    best_opts = {k_: best[k_] for k_ in ("form", "coarse", "widen", "widen_add", "pool_cap",
+                                         "grid", "rounds", "first_lists", "query_order",
+                                         "list_order") if k_ in best}
     # The same schedule captured into a hipGraph and replayed (a side stream:
     # capture needs one), kept when faster.
     side = torch.cuda.Stream()

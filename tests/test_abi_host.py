@@ -177,7 +177,8 @@ def test_adaptive_opts_validated():
 @pytest.mark.parametrize("field,value", [("pool_cap", 100), ("pool_cap", 20000), ("grid", 9),
                                          ("coarse", 7), ("widen", 0), ("form", 3),
                                          ("rounds", 9), ("spill_cap", 100),
-                                         ("spill_cap", 20000)])
+                                         ("spill_cap", 20000), ("first_lists", 65),
+                                         ("query_order", 2), ("list_order", -1)])
 def test_invalid_opts_rejected(field, value):
     ivf, lib = _lib()
     o = ivf.make_opts()

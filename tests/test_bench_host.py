@@ -51,18 +51,21 @@ def test_traffic_only_while_sources_match():
     import bench
     for key, rec in bench.TRAFFIC.items():
         config, setting, form = key[:3]
-        opts = {} if form == "plain" else {"first_lists": key[3], "rounds": key[4]}
+        opts = {"query_order": key[3]} if form == "plain" else \
+            {"query_order": key[3], "first_lists": key[4], "rounds": key[5], "list_order": key[6]}
         assert bench.traffic_key(config, setting, form, opts) == key
         t = bench.recorded_traffic(config, setting, form, opts)
         if bench.source_sha(rec["files"]) == rec["sha"]:
             assert t == int(rec["fetch_kib"] * 1024 * 2.0 + rec["write_kib"] * 1024)
         else:
             assert t is None
-    # Defaults: four first lists, one round; another schedule has no record.
+    # Defaults: longest-first orders, four first lists, one round; another
+    # schedule has no record.
     assert bench.traffic_key("c5", "static x0.5", "batched", {"first_lists": 0, "rounds": 0}) == \
-        ("c5", "static x0.5", "batched", 4, 1)
+        ("c5", "static x0.5", "batched", 0, 4, 1, 0)
     assert bench.recorded_traffic("c5", "static x0.5", "batched",
                                   {"first_lists": 8, "rounds": 5}) is None
+    assert bench.recorded_traffic("c5", "static x0.5", "plain", {"query_order": 1}) is None
 
 
 def test_probe_ladder_settings():

@@ -494,6 +494,26 @@ def test_batched_rounds_candidates_bit_exact(name, rounds, depth):
     assert g.device_error() == 0
 
 
+@pytest.mark.parametrize("query_order,list_order", [(1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("name", ["c1", "c3s", "c5s", "c2w"])
+def test_launch_orders_change_no_result(name, query_order, list_order):
+    # Longest-first (the default) or index-order launches of the per-query
+    # scans and of the batched work items: the same pools and results.
+    import paper_2511_03298_amd as ivf
+    cfg, X, Q, nprobe, index, g, res = case(name)
+    P = probes_tensor(res, nprobe)
+    ip, dp = g.search(Q, nprobe, cfg.k, cfg.R)
+    for form in ("plain", "batched"):
+        opts = ivf.make_opts(form=form, query_order=query_order, list_order=list_order)
+        keys = g.debug_candidates(Q, P, nprobe, cfg.R, opts=opts).cpu().numpy()
+        a, ids = ivf.decode_keys(keys)
+        assert np.array_equal(ids, res["cand_id"])
+        assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+        io, do = g.search(Q, nprobe, cfg.k, cfg.R, opts=opts)
+        assert torch.equal(io, ip) and torch.equal(do.view(torch.int32), dp.view(torch.int32))
+    assert g.device_error() == 0
+
+
 @pytest.mark.parametrize("rounds,spill_cap", [(1, 1024), (3, 1024), (3, 2048), (1, 0), (3, 0)])
 def test_batched_survivor_overflow_recomputes(rounds, spill_cap):
     # The first probed list is the farthest one and the first-list pass stops
