@@ -93,7 +93,7 @@ ivf_status static_scratch(void** out) {
   return IVF_OK;
 }
 
-constexpr int32_t MAX_LISTS = 16384;
+constexpr int32_t MAX_LISTS = MAX_SCAN_LISTS;
 constexpr int32_t MAX_WIDEN = MAX_LISTS;
 
 // Validate the descriptor and compute the table layout. Returns an empty

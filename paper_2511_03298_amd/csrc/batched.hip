@@ -54,8 +54,6 @@ __device__ __forceinline__ uint32_t bfe8(uint32_t x, int shift) {
 // and the query has not overflowed.
 // ---------------------------------------------------------------------------
 
-constexpr int PAIR_CHUNK = 4096;  // (query, probe) entries per workgroup
-
 struct RoundSel {
   const int32_t* nprobe_eff;
   const int32_t* p1;
@@ -66,8 +64,11 @@ struct RoundSel {
   }
 };
 
+constexpr int PAIR_CHUNK = 4096;  // (query, probe) entries per workgroup
+
 // Per-list counts of phase-2 pairs: a workgroup histograms its chunk in LDS
-// and adds each non-zero bin to the global count once.
+// and adds each non-zero bin to the global count once (lists probed by many
+// queries would otherwise serialise on global atomics).
 __global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t max_nprobe, int32_t L,
                                                           const int32_t* __restrict__ probes,
                                                           RoundSel sel,
@@ -90,7 +91,10 @@ __global__ void __launch_bounds__(256) pairs_count_kernel(int32_t nq, int32_t ma
 // over the lists in `order` (the index's lists longest first, so that the
 // persistent workgroups take the long items first and the grid ends on short
 // ones), or in index order when it is null; the items of one list are
-// consecutive.
+// consecutive. Thread t owns the lists at positions [t*per, t*per + per),
+// per <= 16 (L <= 16384): their list indices and counts are loaded together
+// before the scan.
+constexpr int SCAN_PER = MAX_SCAN_LISTS / 1024;
 __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, int32_t BG,
                                                          const int32_t* __restrict__ order,
                                                          const int32_t* __restrict__ cnt,
@@ -102,31 +106,41 @@ __global__ void __launch_bounds__(1024) pairs_scan_kernel(int32_t L, int32_t BG,
   const int tid = threadIdx.x;
   const int per = (L + 1023) / 1024;
   const int b = tid * per, e = min(L, b + per);
+  int32_t lid[SCAN_PER], c[SCAN_PER];
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    const int i = b + k;
+    lid[k] = k < per && i < e ? (order ? order[i] : i) : -1;
+  }
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) c[k] = lid[k] >= 0 ? cnt[lid[k]] : 0;
   int32_t ps = 0, is = 0;
-  for (int i = b; i < e; ++i) {
-    const int l = order ? order[i] : i;
-    ps += cnt[l];
-    is += (cnt[l] + BG - 1) / BG;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    ps += c[k];
+    is += (c[k] + BG - 1) / BG;
   }
   sp[tid] = ps;
   si[tid] = is;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    int32_t a = tid >= off ? sp[tid - off] : 0, c = tid >= off ? si[tid - off] : 0;
+    int32_t a = tid >= off ? sp[tid - off] : 0, d = tid >= off ? si[tid - off] : 0;
     __syncthreads();
     sp[tid] += a;
-    si[tid] += c;
+    si[tid] += d;
     __syncthreads();
   }
   int32_t pacc = sp[tid] - ps, iacc = si[tid] - is;
-  for (int i = b; i < e; ++i) {
-    const int l = order ? order[i] : i;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    if (lid[k] < 0) continue;
+    const int l = lid[k];
     list_start[l] = pacc;
     item_start[l] = iacc;
     cursor[l] = 0;
-    const int ni = (cnt[l] + BG - 1) / BG;
+    const int ni = (c[k] + BG - 1) / BG;
     for (int i = 0; i < ni; ++i) item_list[iacc + i] = l;
-    pacc += cnt[l];
+    pacc += c[k];
     iacc += ni;
   }
   if (tid == 1023) {
@@ -816,8 +830,7 @@ hipError_t launch_batched_pairs(const Tables& t, int32_t nq, int32_t max_nprobe,
                      w.probes, sel, w.list_cnt);
   hipLaunchKernelGGL(pairs_scan_kernel, dim3(1), dim3(1024), 0, s, t.L, item_queries_rt(t.words),
                      w.list_order == 0 ? t.list_order : nullptr, w.list_cnt, w.list_start,
-                     w.item_start, w.list_cursor,
-                     w.item_list);
+                     w.item_start, w.list_cursor, w.item_list);
   hipLaunchKernelGGL(pairs_fill_kernel, dim3(g1), dim3(256), hist_lds, s, nq, max_nprobe, t.L,
                      w.probes, sel, w.list_start, w.list_cursor, w.pairs);
   return hipGetLastError();

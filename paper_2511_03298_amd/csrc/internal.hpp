@@ -19,6 +19,7 @@ constexpr int TILE_L = 64;        // low-precision centroid tables: L padded to 
 constexpr int TILE_D = 64;        // ... and d padded to this
 constexpr size_t ALIGN = 256;
 constexpr int ORDER_BUCKETS = 1024;  // scan-length buckets of the longest-first query order
+constexpr int MAX_SCAN_LISTS = 16384;  // lists of an index that can be searched
 
 inline size_t align_up(size_t x, size_t a = ALIGN) { return (x + a - 1) / a * a; }
 
