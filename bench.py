@@ -44,23 +44,24 @@ LOOKUP_PEAK_T = 256 * 2.4e9 * LDS_BYTES_PER_CLK / 2 / 1e12
 # HBM-side traffic of the scan stage's kernel launches of one step, from
 # rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB per step: the mean
 # of the timed launches, summed over a step's launches), scaled by the factors
-# a 1 GiB device copy gave (2.0 and 1.0). Keyed by workload, operating point
-# and form, and for the batched form by its first-list count and rounds (they
-# decide which lists the kernel scans); valid only while the kernel sources
-# are the ones measured (sha256 of the listed files).
+# a 1 GiB device copy gave (2.0 and 1.0). Keyed by workload, operating point,
+# form and launch order of the per-query scans, and for the batched form also
+# by its first-list count and rounds (they decide which lists the kernel
+# scans) and its work-item order; valid only while the kernel sources are the
+# ones measured (sha256 of the listed files).
 TRAFFIC = {
     ("c5", "static x0.5", "plain", 0): dict(
-        files=("scan.hip", "common.hpp"), sha="d1f5028da08566ba",
-        fetch_kib=39111448.6, write_kib=8192.0),
+        files=("scan.hip", "common.hpp"), sha="6382d9349c4a2cfb",
+        fetch_kib=39061619.8, write_kib=8192.0),
     ("c5", "static x0.5", "batched", 0, 4, 1, 0): dict(
-        files=("batched.hip", "scan.hip", "common.hpp"), sha="23cc14ad80291eec",
-        fetch_kib=4369017.7, write_kib=60422.2),
+        files=("batched.hip", "scan.hip", "common.hpp"), sha="1790ef537716c52e",
+        fetch_kib=3304429.6, write_kib=59973.0),
     ("c2", "static nprobe 24", "plain", 0): dict(
-        files=("scan.hip", "common.hpp"), sha="d1f5028da08566ba",
-        fetch_kib=3610304.8, write_kib=15625.0),
+        files=("scan.hip", "common.hpp"), sha="6382d9349c4a2cfb",
+        fetch_kib=3561935.4, write_kib=15625.4),
     ("c2", "static nprobe 24", "batched", 0, 2, 1, 0): dict(
-        files=("batched.hip", "scan.hip", "common.hpp"), sha="23cc14ad80291eec",
-        fetch_kib=150523.7, write_kib=40461.5),
+        files=("batched.hip", "scan.hip", "common.hpp"), sha="1790ef537716c52e",
+        fetch_kib=152519.7, write_kib=40486.4),
 }
 
 
@@ -210,7 +211,9 @@ def _cpu_server(conn, X, Q, k, R, per_worker):
     phys = physical_cores()
     conn.send({"value": round(total / wall, 1), "unit": "queries/s", "cores": workers,
                "kind": "oracle", "physical_cores": phys,
-               "sample": f"{total} queries (the first {min(total, len(Q))} of the batch, "
+               "sample": (f"{total} queries (the first {total} of the batch, " if total <= len(Q)
+                          else f"{total} searches (cycling through all {len(Q)} queries of the "
+                               f"batch, ") +
                          f"{per_worker} per worker process, one single-threaded process per "
                          f"core on {workers} of the host's {phys} physical cores), same index, "
                          f"nprobe, k and rerank as the GPU run; wall {wall:.1f} s; {cpu_model()}"})
