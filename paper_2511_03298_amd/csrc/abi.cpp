@@ -613,7 +613,7 @@ ivf_status run_scan_and_rerank(const ivf_index* idx, const float* Q, const float
   // reduced to `rerank` distinct points before the re-rank.
   const int32_t pool = rerank * t.copies;
   IVF_HIP(prof_mark(idx, s, IVF_STAGE_PREP));
-  IVF_HIP(launch_bias(t, Q, nq, max_nprobe, w, s));
+  if (!scan_owns_bias(t, max_nprobe)) IVF_HIP(launch_bias(t, Q, nq, max_nprobe, w, s));
   if (o.form == IVF_FORM_BATCHED) {
     // Rounds over probe ranks [b_r, b_{r+1}) with b = 0, 4, 16, 64, ...:
     // each round's merge publishes a tighter threshold for the next.

@@ -504,10 +504,11 @@ hipError_t launch_copy_probes(const int32_t* probes, const int32_t* nprobe, int3
   return hipGetLastError();
 }
 
-// Inner-product list constant b = -<q, cm_l> (sequential over t, FP32, every
-// product and sum rounded on its own). One workgroup per query with the query
-// in LDS; one thread per probe slot walks its centroid row with 16-byte loads
-// (scalar loads when rows are not 16-byte multiples), in the same order.
+// Inner-product list constant b = -<q, cm_l> (ip_list_bias: sequential over t,
+// FP32, every product and sum rounded on its own) for every probe slot. One
+// workgroup per query with the query in LDS; one thread per probe slot walks
+// its centroid row. Used where the scan kernel does not compute the
+// constants itself (very long probe rows, parity exports).
 __global__ void __launch_bounds__(256) bias_kernel(Tables t, const float* __restrict__ Q,
                                                    int32_t max_nprobe,
                                                    const int32_t* __restrict__ probes,
@@ -521,24 +522,9 @@ __global__ void __launch_bounds__(256) bias_kernel(Tables t, const float* __rest
   __syncthreads();
   // One float4 at a time: the re-score's 16-vector prefetch measured slower
   // here (10M x 768 rows, 4096 queries: 0.1 ms more per search).
-  const bool vec = (t.d & 3) == 0;
   for (int p = threadIdx.x; p < np; p += blockDim.x) {
     const int l = probes[(size_t)q * max_nprobe + p];
-    const float* c = t.cm + (size_t)l * t.d;
-    float acc = 0.0f;
-    if (vec) {
-      const float4* c4 = reinterpret_cast<const float4*>(c);
-      for (int k4 = 0; k4 < t.d / 4; ++k4) {
-        const float4 v = c4[k4];
-        acc = acc + qs[4 * k4 + 0] * v.x;
-        acc = acc + qs[4 * k4 + 1] * v.y;
-        acc = acc + qs[4 * k4 + 2] * v.z;
-        acc = acc + qs[4 * k4 + 3] * v.w;
-      }
-    } else {
-      for (int k = 0; k < t.d; ++k) acc = acc + qs[k] * c[k];
-    }
-    bias[(size_t)q * max_nprobe + p] = plus_zero(-acc);
+    bias[(size_t)q * max_nprobe + p] = ip_list_bias(t.cm + (size_t)l * t.d, qs, t.d);
   }
 }
 

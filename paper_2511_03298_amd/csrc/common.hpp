@@ -28,6 +28,27 @@ __device__ __forceinline__ float plus_zero(float x) {
   // -0.0 -> +0.0, every other value unchanged.
   return x == 0.0f ? 0.0f : x;
 }
+
+// Inner-product list constant b = -<q, c> over d components: sequential in
+// the component index, FP32, every product and sum rounded on its own
+// (16-byte loads of the row when d is a multiple of 4, in the same order).
+// qv may live in LDS.
+__device__ __forceinline__ float ip_list_bias(const float* __restrict__ c, const float* qv, int d) {
+  float acc = 0.0f;
+  if ((d & 3) == 0) {
+    const float4* c4 = reinterpret_cast<const float4*>(c);
+    for (int k4 = 0; k4 < d / 4; ++k4) {
+      const float4 v = c4[k4];
+      acc = acc + qv[4 * k4 + 0] * v.x;
+      acc = acc + qv[4 * k4 + 1] * v.y;
+      acc = acc + qv[4 * k4 + 2] * v.z;
+      acc = acc + qv[4 * k4 + 3] * v.w;
+    }
+  } else {
+    for (int k = 0; k < d; ++k) acc = acc + qv[k] * c[k];
+  }
+  return plus_zero(-acc);
+}
 __device__ __forceinline__ uint64_t make_key(float v, uint32_t idx) {
   return ((uint64_t)f2ord(v) << 32) | (uint64_t)idx;
 }

@@ -144,6 +144,12 @@ hipError_t launch_gather_queries(const Tables& t, const float* Q, int32_t nq, fl
                                  hipStream_t s);
 hipError_t launch_bias(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
                        const Workspace& w, hipStream_t s);
+// Inner product with probe rows of at most 1024 slots: the scan kernel (plain
+// form, first-list pass) computes the list constants itself, so the search
+// needs no launch_bias.
+inline bool scan_owns_bias(const Tables& t, int32_t max_nprobe) {
+  return t.metric == IVF_METRIC_IP && max_nprobe <= 1024;
+}
 hipError_t launch_scan_plain(const Tables& t, const float* Q, int32_t nq, int32_t max_nprobe,
                              int32_t rerank, const Workspace& w, hipStream_t s);
 // Batched form: first-list pass (pool + threshold per query), then per

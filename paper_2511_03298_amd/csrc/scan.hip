@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
                                                          int32_t R, int32_t cap,
                                                          const int32_t* __restrict__ probes,
                                                          const int32_t* __restrict__ nprobe_eff,
-                                                         const float* __restrict__ bias,
+                                                         float* __restrict__ bias,
                                                          uint64_t* __restrict__ cand,
                                                          int32_t* __restrict__ p1_out,
                                                          uint64_t* __restrict__ thr_out,
@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
                                                          uint8_t* __restrict__ qlut_out,
                                                          float* __restrict__ qlo_out,
                                                          float* __restrict__ qdelta_out,
-                                                         const int32_t* __restrict__ order) {
+                                                         const int32_t* __restrict__ order,
+                                                         int32_t own_bias) {
   extern __shared__ __align__(16) unsigned char dyn[];
   __shared__ ScanShared<W> sh;
   // `order`: the launch order of the queries (longest scan first), or the
@@ -142,6 +143,7 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
   uint64_t* keys = reinterpret_cast<uint64_t*>(dyn);            // [R + cap]
   float* Tf = reinterpret_cast<float*>(keys + R + cap);          // [m_pad*16]
   float* qv = Tf + t.m_pad * KSUB;                               // [d]
+  float* sbias = qv + t.d;                                       // [max_nprobe] (own_bias)
   // `only`: recompute just the flagged queries. `p1_out`: the batched form's
   // first-list pass: stop after the first first_lists lists, or later, once
   // the lists scanned hold at least R points, and publish where phase 2
@@ -166,6 +168,17 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
   for (int i = tid; i < t.d; i += blockDim.x) qv[i] = Q[(size_t)q * t.d + i];
   if (tid == 0) sh.total = 0;
   __syncthreads();
+  // `own_bias` (inner product): the list constants -<q, cm_l> of every probe
+  // slot are computed here, one thread per slot, kept in LDS for this scan
+  // and published for the batched scan's work items. The table build below
+  // ends with barriers before any list is scanned.
+  if (own_bias) {
+    for (int p = tid; p < np; p += blockDim.x) {
+      const float b = ip_list_bias(t.cm + (size_t)qprobes[p] * t.d, qv, t.d);
+      sbias[p] = b;
+      bias[(size_t)q * max_nprobe + p] = b;
+    }
+  }
 
   uint64_t thr = KEY_NONE;
   const uint32_t limit = (uint32_t)(R + cap - IVF_BLOCK);
@@ -203,7 +216,7 @@ __global__ void __launch_bounds__(256) scan_plain_kernel(Tables t, const float* 
       __syncthreads();
       lut_quantize(t, Tf, sh.lo, sh.lut8, &sh.st);
     } else {
-      b = bias[(size_t)q * max_nprobe + p];
+      b = own_bias ? sbias[p] : bias[(size_t)q * max_nprobe + p];
     }
     const float B = sh.st.lo_sum + b;
     const float delta = sh.st.delta;
@@ -408,7 +421,11 @@ static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t n
                                       int32_t* p1_out, uint64_t* thr_out, const int32_t* only,
                                       hipStream_t s) {
   const int32_t cap = scan_cap(R, w.pool_cap);
-  size_t lds = (size_t)(R + cap) * 8 + (size_t)t.m_pad * KSUB * 4 + (size_t)t.d * 4;
+  // Inner product: the kernel computes the list constants itself unless it
+  // only recomputes flagged queries (their constants are in place already).
+  const bool own_bias = scan_owns_bias(t, max_nprobe) && !only;
+  size_t lds = (size_t)(R + cap) * 8 + (size_t)t.m_pad * KSUB * 4 + (size_t)t.d * 4 +
+               (own_bias ? (size_t)max_nprobe * 4 : 0);
   const bool pub = p1_out && t.metric == IVF_METRIC_IP;
   const int32_t first_lists = w.first_lists > 0 ? w.first_lists : 1;
   // A recompute of flagged queries (`only`) keeps the identity order.
@@ -420,7 +437,7 @@ static hipError_t launch_scan_plain_w(const Tables& t, const float* Q, int32_t n
   hipLaunchKernelGGL(scan_plain_kernel<W>, dim3(nq), dim3(256), lds, s, t, Q, nq, max_nprobe, R,
                      cap, w.probes, w.nprobe_eff, w.bias, w.cand, p1_out, thr_out, only,
                      first_lists, pub ? w.qlut : nullptr, pub ? w.qlo_sum : nullptr,
-                     pub ? w.qdelta : nullptr, ordered ? w.order : nullptr);
+                     pub ? w.qdelta : nullptr, ordered ? w.order : nullptr, own_bias ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -1119,6 +1119,31 @@ def test_filtered_and_spilled_index_from_the_gpu_trainer():
     assert g.device_error() == 0
 
 
+@pytest.mark.parametrize("max_np", [1030, 600])
+def test_ip_list_constants_long_probe_rows(max_np):
+    # Inner product: with probe rows of at most 1024 slots the scan kernel
+    # computes the list constants -<q, cm_l> itself, with longer rows a
+    # separate kernel does; both give the oracle's pools bit-exactly.
+    import paper_2511_03298_amd as ivf
+    _gpu()
+    L, k, R = 1100, 5, 64
+    cfg, X, Q, nprobe, index = cached_workload("c3", 8000, 6, L=L, ncomp=300, d=20, m=10,
+                                               nprobe=(max_np, max_np), k=k, R=R)
+    print(f"[long probe rows] {cfg.metric} L={cfg.L} nprobe={nprobe.tolist()}", flush=True)
+    assert cfg.metric == "ip" and int(max(nprobe)) == max_np
+    g = ivf.GpuIndex.from_index(index, X)
+    res = oracle_stages(index, X, Q, nprobe, k, R)
+    P = probes_tensor(res, nprobe)
+    for opts in (ivf.make_opts(), ivf.make_opts(form="batched")):
+        keys = g.debug_candidates(Q, P, nprobe, R, opts=opts).cpu().numpy()
+        a, ids = ivf.decode_keys(keys)
+        assert np.array_equal(ids, res["cand_id"]), ivf.opts_dict(opts)
+        assert np.array_equal(a.view(np.uint32), res["cand_a"].view(np.uint32))
+        ids, dist = g.search(Q, nprobe, k, R, opts=opts)
+        check_final(ids.cpu().numpy(), dist.cpu().numpy(), res, X, Q, cfg.metric)
+    assert g.device_error() == 0
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_fuzz_shapes(seed):
     # Random shapes inside the supported range: d not a multiple of 16, any
