@@ -159,6 +159,10 @@ def test_default_opts():
     assert (o.coarse, o.widen, o.form, o.use_graph, o.pool_cap, o.grid, o.rounds) == \
         (0, 2, 0, 0, 0, 0, 0)
     assert (o.spill_cap, o.adaptive) == (0, 0)
+    # Auto first-list count; both launch orders longest first.
+    assert (o.widen_add, o.first_lists, o.query_order, o.list_order) == (0, 0, 0, 0)
+    d = ivf.opts_dict(ivf.make_opts(form="batched", query_order=1, list_order=1))
+    assert (d["query_order"], d["list_order"]) == (1, 1)
 
 
 def test_adaptive_opts_validated():
